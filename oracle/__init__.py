@@ -1,0 +1,17 @@
+"""Plain FP64 CPU oracle of the SMC-MPC hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls, links
+or runs this package: only the tests, the smoke check and the CPU-baseline leg
+of the benchmark do.  It shares no code with the HIP path; both are fed from
+the seeded input generators in ``synth``.
+
+Modules:
+  philox   -- Philox4x32-10 counter-based generator, uniform and normal draws
+  wind     -- grid, Kronecker Cholesky factor, field samples, trilinear lookup
+  rollout  -- dynamics, constraints, landing, cost terms, pairwise separation
+  smc      -- Alg. 1: initialisation, weights, resampling, moves, selection
+
+Each function cites the passage of the paper it follows.  Functions without an
+independent pin say "parity unpinned" in their docstring.
+"""
+from . import philox, wind, rollout, smc  # noqa: F401
