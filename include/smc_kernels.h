@@ -1,0 +1,133 @@
+/*
+ * smc_kernels.h -- kernel-level entry points of the SMC-MPC engine.
+ *
+ * Each function runs exactly one step of the hot path on device buffers, so
+ * that every step can be checked on its own against an independent
+ * implementation fed with identical inputs.  smc_mpc_step() chains the same
+ * kernels.
+ *
+ * Conventions (in addition to those of smc_mpc.h):
+ *  - All array pointers are DEVICE pointers, caller-owned; `stream` is a
+ *    hipStream_t passed as void* (NULL = the context's stream).  Calls return
+ *    after queueing the work; synchronise the stream before reading outputs.
+ *  - "real" arrays hold double for an SMC_FP64 context and float for an
+ *    SMC_FP32 context.  Costs, log-weights and scans are double always.
+ *  - Sizes are validated on the host before any launch (SMC_EINVAL).
+ *  - Layouts (row-major):
+ *      particles u      [P][N][S][3] real, normalised controls in [0, 1]
+ *      wind normals Z   [G][2M]      real, column 2m+c = sample m, component c
+ *      wind fields W    [M][G][2]    real
+ *      rollout cost     [M][P][N]    double;  rollout feasibility same, uint8
+ *      expected cost    [P][N]       double;  feasibility [P][N] uint8
+ *      log-weights      [P][N]       double (-inf = violating aircraft)
+ *      ancestors        [N][P]       int32
+ *    with G = nx ny nz grid points, grid point g = (ix ny + iy) nz + iz.
+ */
+#ifndef SMC_KERNELS_H
+#define SMC_KERNELS_H
+
+#include <stdint.h>
+#include "smc_mpc.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Philox4x32-10 (Salmon et al., SC'11) words of n consecutive counters
+ * (element e0 .. e0+n-1) of stream (seed, mpc_step, iter, purpose,
+ * scenario).  out[4 n] uint32: the 4 words of each counter.  This replaces
+ * the paper's stateful per-thread generator (Sec. "Kernel Design") by a
+ * counter-based one, so any draw is reproducible from its coordinates. */
+smc_status smc_k_philox(uint64_t seed, int64_t mpc_step, int32_t iter,
+                        int32_t purpose, int32_t scenario, int64_t e0, int64_t n,
+                        uint32_t* out, void* stream);
+
+/* Alg. 1 initialisation (Sec. "Particles"): u[P][N][S][3] ~ U(0, 1) from the
+ * INIT stream, element ((p N + i) S + s) 3 + c. */
+smc_status smc_k_init_particles(smc_ctx* ctx, int64_t mpc_step, int32_t P,
+                                void* u, void* stream);
+
+/* Standard normals Z[G][2M] of iteration `iter` (WIND stream, element
+ * m G + g, Box-Muller pair -> components x, y). */
+smc_status smc_k_wind_normals(smc_ctx* ctx, int64_t mpc_step, int32_t iter,
+                              void* Z, void* stream);
+
+/* Wind fields W[m][g][c] = wind_mean[c] + sum_h Lchol[g][h] Z[h][2m+c]
+ * (Sec. "Wind Model": Cholesky factor times Gaussian vector), with the
+ * context's dense lower-triangular factor; MFMA GEMM. wind_mean: host [2]. */
+smc_status smc_k_wind_gemm(smc_ctx* ctx, const void* Z, const double* wind_mean,
+                           void* W, void* stream);
+
+/* Copy of the context's dense factor Lchol[G][G] (real) into `out`. */
+smc_status smc_k_wind_factor(smc_ctx* ctx, void* out, void* stream);
+
+/* Rollout of P particles under the fields W (Sec. "Trajectory Planning",
+ * eq. hor; Sec. "Constraint Handling"; eq. TO_init; Sec. "Particle Costing";
+ * eq. avoidance): cost[M][P][N] (double), feas[M][P][N] (uint8).
+ * states[N][6] double and k_active[N] int32 are device arrays.
+ * steps (device uint64[64], may be NULL): simulated aircraft-steps are
+ * added, spread over the 64 slots. */
+smc_status smc_k_rollout(smc_ctx* ctx, const void* u, int32_t P, const void* W,
+                         const double* states, const int32_t* k_active,
+                         int32_t horizon, double* cost, uint8_t* feas,
+                         uint64_t* steps, void* stream);
+
+/* Expected cost over the M wind samples (Kahan-compensated FP64 sum in
+ * sample order), feasibility (all samples), log-weight -beta * c_hat or -inf
+ * (Sec. "Weight Scaling").  chat, logw [P][N] double; feas_pn [P][N] uint8. */
+smc_status smc_k_reduce(smc_ctx* ctx, int32_t P, const double* cost,
+                        const uint8_t* feas, double beta, double* chat,
+                        uint8_t* feas_pn, double* logw, void* stream);
+
+/* First Philox word of the RESAMPLE stream for each aircraft row:
+ * U[N] uint32. */
+smc_status smc_k_resample_offsets(smc_ctx* ctx, int64_t mpc_step, int32_t iter,
+                                  uint32_t* U, void* stream);
+
+/* Per-aircraft systematic resampling (Sec. "Particle Resampling and
+ * Perturbation"): for each row i, q_l = floor(exp(logw - max) 2^Kq) with
+ * Kq = 52 - ceil(log2 P), exact FP64 inclusive scan C, ancestors
+ * a_k = min{l : C_l P 2^32 > (k 2^32 + U_i) Q} in exact integer arithmetic;
+ * identity for an all -inf row.  logw [P][N], U [N], anc [N][P] int32.
+ * ess (device double[N], may be NULL): effective sample size per row. */
+smc_status smc_k_resample(smc_ctx* ctx, int32_t P, const double* logw,
+                          const uint32_t* U, int32_t* anc, double* ess,
+                          void* stream);
+
+/* Gather by ancestors, then (if jitter != 0) the paper's Gaussian white-noise
+ * perturbation u += sigma_move xi (MOVE stream of `iter`), clamped to [0, 1]
+ * (Alg. 1 resample / perturb).  u_in, u_out [P][N][S][3] real (distinct). */
+smc_status smc_k_gather_move(smc_ctx* ctx, int32_t P, const void* u_in,
+                             const int32_t* anc, void* u_out, int64_t mpc_step,
+                             int32_t iter, int32_t jitter, void* stream);
+
+/* Random-walk proposal u' = reflect(u + sigma_move xi) (MOVE stream),
+ * reflection into [0, 1] keeps the proposal symmetric. */
+smc_status smc_k_propose(smc_ctx* ctx, int32_t P, const void* u, void* u_prop,
+                         int64_t mpc_step, int32_t iter, void* stream);
+
+/* Metropolis acceptance on the joint particle (target prod_i W_i, final
+ * selection rule of Sec. "Final Sample Selection"): reject a violating
+ * proposal, accept a proposal if the current particle violates, otherwise
+ * accept iff log U < sum_i logw' - sum_i logw (ACCEPT stream, element p).
+ * Accepted rows of u, chat, feas_pn, logw are replaced by the proposal's.
+ * accepted (device int32[P], may be NULL) receives the decisions. */
+smc_status smc_k_accept(smc_ctx* ctx, int32_t P, void* u, const void* u_prop,
+                        double* chat, const double* chat_prop,
+                        uint8_t* feas_pn, const uint8_t* feas_prop,
+                        double* logw, const double* logw_prop,
+                        int64_t mpc_step, int32_t iter, int32_t* accepted,
+                        void* stream);
+
+/* Final selection (Sec. "Final Sample Selection"): the particle with the
+ * largest sum of log-weights, lowest index on ties; if every particle has a
+ * violating aircraft, the fewest violators first, then the largest sum of
+ * -beta c_hat.  best[0] = index, best[1] = 1 if infeasible else 0. */
+smc_status smc_k_select(smc_ctx* ctx, int32_t P, const double* logw,
+                        const double* chat, double beta, int32_t* best,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMC_KERNELS_H */

@@ -1,0 +1,85 @@
+// Internal interface between the host orchestrator and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace smc {
+
+constexpr int kMaxAircraft = 64;
+constexpr int kStepSlots = 64;   // striped counters of simulated aircraft-steps
+
+// Scalars of one rollout launch (uniform over the grid; kernel argument).
+struct RolloutParams {
+    int N, S, H, P, M, G;
+    int nx, ny, nz;
+    int use_noise, pop_nx, pop_ny;
+    double half_wx, half_wy, inv_hx, inv_hy, inv_hz;
+    double pop_inv_hx, pop_inv_hy;
+    double dt, sep_h2, sep_v;
+    double ctrl_lo[3], ctrl_span[3];
+    double zmin, zmax, vmin, vmax;
+    double p_run, p_beta, p_chi, p_vs, beta_f;
+    double w[9];
+    double time_norm, noise_alt, zdot_max;
+};
+
+// Device arrays of one rollout launch.
+struct RolloutArrays {
+    const void* u;            // [P][N][S][3] real
+    const void* W;            // [M][G][2] real
+    const double* states;     // [N][6]
+    const int32_t* k_active;  // [N]
+    const double* acpar;      // [N][9]
+    const double* targets;    // [N][4]
+    const int8_t* kind;       // [N]
+    const float* pop;         // [pop_ny][pop_nx] or null
+    double* cost;             // [M][P][N]
+    uint8_t* feas;            // [M][P][N]
+    unsigned long long* steps;  // [kStepSlots] or null
+};
+
+// precision: 0 = double, 1 = float
+hipError_t launch_philox_words(Stream s, uint32_t e0, int64_t n, uint32_t* out,
+                               hipStream_t st);
+hipError_t launch_init_particles(int prec, Stream s, int64_t count, void* u,
+                                 hipStream_t st);
+hipError_t launch_wind_normals(int prec, Stream s, int G, int M, void* Z,
+                               hipStream_t st);
+hipError_t launch_kron_expand(int prec, const double* Lx, const double* Ly,
+                              const double* Lz, int nx, int ny, int nz,
+                              double sigma, void* Lfac, hipStream_t st);
+hipError_t launch_wind_gemm(int prec, const void* Lfac, const void* Z,
+                            double wm0, double wm1, int G, int M, void* W,
+                            hipStream_t st);
+hipError_t launch_rollout(int prec, const RolloutParams& p,
+                          const RolloutArrays& a, hipStream_t st);
+hipError_t launch_reduce(int P, int M, int N, const double* cost,
+                         const uint8_t* feas, double beta, double* chat,
+                         uint8_t* feas_pn, double* logw, hipStream_t st);
+hipError_t launch_resample_offsets(Stream s, int N, uint32_t* U, hipStream_t st);
+hipError_t launch_resample(int P, int N, const double* logw, const uint32_t* U,
+                           double* scan, int32_t* anc, double* ess,
+                           hipStream_t st);
+hipError_t launch_gather_move(int prec, int P, int N, int D, const void* u_in,
+                              const int32_t* anc, void* u_out, Stream s,
+                              double sigma, int jitter, hipStream_t st);
+hipError_t launch_propose(int prec, int64_t count, const void* u, void* u_prop,
+                          Stream s, double sigma, hipStream_t st);
+hipError_t launch_accept(int prec, int P, int N, int D, void* u,
+                         const void* u_prop, double* chat,
+                         const double* chat_prop, uint8_t* feas_pn,
+                         const uint8_t* feas_prop, double* logw,
+                         const double* logw_prop, Stream s, int32_t* accepted,
+                         int32_t* flags, hipStream_t st);
+hipError_t launch_select(int P, int N, const double* logw, const double* chat,
+                         double beta, int32_t* best, hipStream_t st);
+hipError_t launch_write_result(int prec, int N, int S, const void* u,
+                               const int32_t* best, const double* chat,
+                               const double* ctrl_lo, const double* ctrl_span,
+                               double* controls_out, double* cost_out,
+                               int32_t* status_out, hipStream_t st);
+
+}  // namespace smc

@@ -1,0 +1,151 @@
+// Wind field generation (Sec. "Wind Model"): the dense lower-triangular
+// factor L = sigma Lx (x) Ly (x) Lz is expanded once per context; each SMC
+// iteration forms W = wbar + L Z for all 2M Gaussian columns with an MFMA
+// GEMM (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64 on gfx950).
+#include "engine.h"
+
+namespace smc {
+
+// L[g][h] = sigma * Lx[ix][jx] * Ly[iy][jy] * Lz[iz][jz] (computed in FP64).
+template <typename T>
+__global__ void k_kron_expand(const double* __restrict__ Lx, const double* __restrict__ Ly,
+                              const double* __restrict__ Lz, int nx, int ny, int nz,
+                              double sigma, T* __restrict__ Lf) {
+    const int64_t G = (int64_t)nx * ny * nz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= G * G) return;
+    const int64_t g = t / G, h = t % G;
+    const int iz = (int)(g % nz), iy = (int)((g / nz) % ny), ix = (int)(g / ((int64_t)ny * nz));
+    const int jz = (int)(h % nz), jy = (int)((h / nz) % ny), jx = (int)(h / ((int64_t)ny * nz));
+    const double v = sigma * ((Lx[ix * nx + jx] * Ly[iy * ny + jy]) * Lz[iz * nz + jz]);
+    Lf[t] = (T)v;
+}
+
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+// Block tile 32 (grid points) x 64 (columns), K stage 16; 4 waves as 2 x 2,
+// each wave 16 x 32 = two 16x16 MFMA tiles.  The factor is lower triangular,
+// so row block rb only needs k < (rb + 1) * 32.  Work is balanced by letting
+// each workgroup take row blocks rb and R - 1 - rb.
+constexpr int GB_M = 32, GB_N = 64, GB_K = 16;
+constexpr int GA_LD = GB_K + 1;      // LDS row pitch of the A tile (bank spread)
+constexpr int GBB_LD = GB_N + 16;    // LDS row pitch of the B tile
+
+template <typename T>
+__device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* __restrict__ Z,
+                                              int G, int NC, int rb, int cb, double wm0,
+                                              double wm1, T* __restrict__ W, T* As, T* Bs) {
+    typedef typename Mfma<T>::acc_t acc_t;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = (wave >> 1) * 16;         // wave row offset in tile
+    const int wc = (wave & 1) * 32;          // wave col offset in tile
+    const int row0 = rb * GB_M;
+    const int col0 = cb * GB_N;
+    const int kmax = min(G, row0 + GB_M);
+    acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+
+    for (int k0 = 0; k0 < kmax; k0 += GB_K) {
+        // A tile: 32 x 16 (2 per thread)
+        for (int e = tid; e < GB_M * GB_K; e += 256) {
+            const int r = e / GB_K, c = e % GB_K;
+            const int gr = row0 + r, gc = k0 + c;
+            As[r * GA_LD + c] = (gr < G && gc < G) ? A[(int64_t)gr * G + gc] : (T)0;
+        }
+        // B tile: 16 x 64 (4 per thread)
+        for (int e = tid; e < GB_K * GB_N; e += 256) {
+            const int r = e / GB_N, c = e % GB_N;
+            const int gr = k0 + r, gc = col0 + c;
+            Bs[r * GBB_LD + c] = (gr < G && gc < NC) ? Z[(int64_t)gr * NC + gc] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GB_K; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            const T a = As[(wr + (lane & 15)) * GA_LD + kr];
+            const T b0 = Bs[kr * GBB_LD + wc + (lane & 15)];
+            const T b1 = Bs[kr * GBB_LD + wc + 16 + (lane & 15)];
+            acc0 = Mfma<T>::op(a, b0, acc0);
+            acc1 = Mfma<T>::op(a, b1, acc1);
+        }
+        __syncthreads();
+    }
+    // epilogue: element (g, col) -> W[m][g][c] with col = 2 m + c
+    const int M = NC / 2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int g = row0 + wr + 4 * (lane >> 4) + r;
+        if (g >= G) continue;
+        const int c0 = col0 + wc + (lane & 15);
+        const int c1 = c0 + 16;
+        if (c0 < NC) {
+            const int m = c0 >> 1, c = c0 & 1;
+            W[((int64_t)m * G + g) * 2 + c] = (T)((c ? wm1 : wm0) + (double)acc0[r]);
+        }
+        if (c1 < NC) {
+            const int m = c1 >> 1, c = c1 & 1;
+            W[((int64_t)m * G + g) * 2 + c] = (T)((c ? wm1 : wm0) + (double)acc1[r]);
+        }
+    }
+    (void)M;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_wind_gemm(const T* __restrict__ A,
+                                                   const T* __restrict__ Z, int G, int NC,
+                                                   double wm0, double wm1, T* __restrict__ W) {
+    __shared__ T As[GB_M * GA_LD];
+    __shared__ T Bs[GB_K * GBB_LD];
+    const int R = (G + GB_M - 1) / GB_M;
+    const int rb = blockIdx.x;
+    const int rb2 = R - 1 - rb;
+    const int cb = blockIdx.y;
+    // heavy (bottom) block first
+    gemm_rowblock<T>(A, Z, G, NC, rb2, cb, wm0, wm1, W, As, Bs);
+    if (rb2 != rb) gemm_rowblock<T>(A, Z, G, NC, rb, cb, wm0, wm1, W, As, Bs);
+}
+
+hipError_t launch_kron_expand(int prec, const double* Lx, const double* Ly,
+                              const double* Lz, int nx, int ny, int nz,
+                              double sigma, void* Lfac, hipStream_t st) {
+    const int64_t G = (int64_t)nx * ny * nz;
+    const int64_t n = G * G;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_kron_expand<double>, dim3(blocks), dim3(256), 0, st, Lx, Ly,
+                           Lz, nx, ny, nz, sigma, (double*)Lfac);
+    else
+        hipLaunchKernelGGL(k_kron_expand<float>, dim3(blocks), dim3(256), 0, st, Lx, Ly,
+                           Lz, nx, ny, nz, sigma, (float*)Lfac);
+    return hipGetLastError();
+}
+
+hipError_t launch_wind_gemm(int prec, const void* Lfac, const void* Z, double wm0,
+                            double wm1, int G, int M, void* W, hipStream_t st) {
+    const int NC = 2 * M;
+    const int R = (G + GB_M - 1) / GB_M;
+    dim3 grid((unsigned)((R + 1) / 2), (unsigned)((NC + GB_N - 1) / GB_N));
+    if (prec == 0)
+        hipLaunchKernelGGL(k_wind_gemm<double>, grid, dim3(256), 0, st,
+                           (const double*)Lfac, (const double*)Z, G, NC, wm0, wm1,
+                           (double*)W);
+    else
+        hipLaunchKernelGGL(k_wind_gemm<float>, grid, dim3(256), 0, st, (const float*)Lfac,
+                           (const float*)Z, G, NC, wm0, wm1, (float*)W);
+    return hipGetLastError();
+}
+
+}  // namespace smc

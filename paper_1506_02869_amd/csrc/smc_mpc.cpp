@@ -1,0 +1,711 @@
+// Host orchestrator and C ABI of the SMC-MPC engine: scenario validation,
+// wind-covariance factorisation, device buffers, the SMC iteration loop of
+// one MPC update (Alg. 1) and the kernel-level entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "smc_kernels.h"
+#include "smc_mpc.h"
+
+using namespace smc;
+
+namespace {
+
+std::string g_init_error;
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct smc_ctx {
+    // scenario
+    int N, S, Hmax, L, M, K, G, prec, move, scen_id;
+    int nx, ny, nz;
+    double dt, box[3], sigma, ell, nugget, sep_h, sep_v;
+    double ctrl_lo[3], ctrl_hi[3], ctrl_span[3], env[4], landing[5], cost_w[9];
+    double time_norm, noise_alt, kappa, sigma_move, mala_step;
+    uint64_t seed;
+    int pop_nx, pop_ny, use_noise;
+    size_t rsz;  // sizeof(real)
+    RolloutParams rp;
+
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<DevBuf> bufs;
+    std::string err;
+
+    // device buffers
+    double *d_acpar = nullptr, *d_targets = nullptr;
+    int8_t* d_kind = nullptr;
+    float* d_pop = nullptr;
+    void* d_Lfac = nullptr;
+    void *d_Z = nullptr, *d_W = nullptr;
+    void *d_u = nullptr, *d_u2 = nullptr, *d_up = nullptr;
+    double* d_cost = nullptr;
+    uint8_t* d_feas = nullptr;
+    double *d_chat = nullptr, *d_logw = nullptr, *d_chat2 = nullptr, *d_logw2 = nullptr;
+    uint8_t *d_feaspn = nullptr, *d_feaspn2 = nullptr;
+    int32_t* d_anc = nullptr;
+    uint32_t* d_U = nullptr;
+    double* d_scan = nullptr;
+    double* d_ess = nullptr;
+    int32_t* d_flags = nullptr;
+    int32_t* d_best = nullptr;
+    int32_t* d_status = nullptr;
+    unsigned long long* d_steps = nullptr;
+    double *d_states = nullptr, *d_ctrl_out = nullptr, *d_cost_out = nullptr;
+    int32_t* d_kact = nullptr;
+    int64_t eval_cap = 0;  // particles the eval buffers hold
+    void* d_ueval = nullptr;
+    double* d_ecost = nullptr;
+    uint8_t* d_efeas = nullptr;
+    double *d_echat = nullptr, *d_elogw = nullptr;
+    uint8_t* d_efeaspn = nullptr;
+};
+
+namespace {
+
+smc_status fail(smc_ctx* c, smc_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf; else g_init_error = buf;
+    return code;
+}
+
+#define HIP_OK(ctx, expr)                                                               \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail((ctx), SMC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+smc_status dalloc(smc_ctx* c, void** p, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, SMC_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    c->bufs.push_back(DevBuf{*p, bytes});
+    return SMC_OK;
+}
+
+template <typename T>
+smc_status dalloc_t(smc_ctx* c, T** p, size_t count) {
+    void* v = nullptr;
+    smc_status s = dalloc(c, &v, count * sizeof(T));
+    *p = (T*)v;
+    return s;
+}
+
+hipStream_t pick(smc_ctx* c, void* stream) { return stream ? (hipStream_t)stream : c->stream; }
+
+double sample_schedule(int J) { return std::floor(3.0 + 5.0 * std::exp(0.05 * J)); }
+double beta_of(const smc_ctx* c, int J) { return c->kappa * sample_schedule(J); }
+
+// Lower Cholesky factor of the 1-D squared-exponential Gram matrix plus the
+// nugget (FP64); false if not positive definite.
+bool axis_factor(int n, double lo, double hi, double ell, double nugget, std::vector<double>& Lo) {
+    std::vector<double> nodes(n), K((size_t)n * n);
+    for (int a = 0; a < n; ++a) nodes[a] = (n == 1) ? lo : lo + (hi - lo) * a / (n - 1);
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            const double d = nodes[a] - nodes[b];
+            K[(size_t)a * n + b] = std::exp(-d * d / (2.0 * ell * ell)) + (a == b ? nugget : 0.0);
+        }
+    Lo.assign((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double s = K[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) s -= Lo[(size_t)j * n + k] * Lo[(size_t)j * n + k];
+        if (!(s > 0.0)) return false;
+        const double d = std::sqrt(s);
+        Lo[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double t = K[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= Lo[(size_t)i * n + k] * Lo[(size_t)j * n + k];
+            Lo[(size_t)i * n + j] = t / d;
+        }
+    }
+    return true;
+}
+
+smc_status validate(const smc_scenario* s) {
+    if (!s) return fail(nullptr, SMC_EINVAL, "scenario is NULL");
+    if (s->n_aircraft < 1 || s->n_aircraft > SMC_MAX_AIRCRAFT)
+        return fail(nullptr, SMC_EINVAL, "n_aircraft must be in [1, %d]", SMC_MAX_AIRCRAFT);
+    if (s->n_segments < 1) return fail(nullptr, SMC_EINVAL, "n_segments must be >= 1");
+    if (s->horizon_max < 1 || s->horizon_max > 100000)
+        return fail(nullptr, SMC_EINVAL, "horizon_max must be in [1, 100000]");
+    if (s->n_segments > s->horizon_max)
+        return fail(nullptr, SMC_EINVAL, "n_segments must not exceed horizon_max");
+    if (s->n_particles < 1 || s->n_particles > (1 << 24))
+        return fail(nullptr, SMC_EINVAL, "n_particles must be in [1, 2^24]");
+    if (s->n_wind < 1 || s->n_wind > 4096) return fail(nullptr, SMC_EINVAL, "n_wind must be in [1, 4096]");
+    if (s->n_iters < 1) return fail(nullptr, SMC_EINVAL, "n_iters must be >= 1");
+    if (!(s->dt > 0)) return fail(nullptr, SMC_EINVAL, "dt must be > 0");
+    for (int a = 0; a < 3; ++a) {
+        if (!(s->box[a] > 0)) return fail(nullptr, SMC_EINVAL, "box dimensions must be > 0");
+        if (s->grid_n[a] < 2 || s->grid_n[a] > 4096)
+            return fail(nullptr, SMC_EINVAL, "grid_n must be in [2, 4096] per axis");
+        if (!(s->ctrl_hi[a] >= s->ctrl_lo[a])) return fail(nullptr, SMC_EINVAL, "ctrl_hi < ctrl_lo");
+    }
+    const int64_t G = (int64_t)s->grid_n[0] * s->grid_n[1] * s->grid_n[2];
+    if (G > 65536) return fail(nullptr, SMC_EINVAL, "grid has more than 65536 points");
+    if (!(s->wind_sigma >= 0) || !(s->wind_ell > 0) || !(s->wind_nugget >= 0))
+        return fail(nullptr, SMC_EINVAL, "wind parameters out of range");
+    if (!(s->sep_h >= 0) || !(s->sep_v >= 0)) return fail(nullptr, SMC_EINVAL, "separations must be >= 0");
+    if (!s->kind || !s->aircraft || !s->targets)
+        return fail(nullptr, SMC_EINVAL, "kind, aircraft and targets are required");
+    for (int i = 0; i < s->n_aircraft; ++i) {
+        if (s->kind[i] != SMC_ARRIVAL && s->kind[i] != SMC_DEPARTURE)
+            return fail(nullptr, SMC_EINVAL, "kind[%d] must be 0 or 1", i);
+        const double* a = s->aircraft + (size_t)i * SMC_AC_NPAR;
+        if (!(a[0] > 0) || !(a[3] > 0) || !(a[4] > 0) || !(a[5] > 0))
+            return fail(nullptr, SMC_EINVAL, "aircraft[%d]: wing area, C_f1, C_f2, T_max must be > 0", i);
+        if (!(a[7] > 0) || !(a[7] < 1.5707963267948966) || !(a[8] > 0) || !(a[8] < 1.5707963267948966))
+            return fail(nullptr, SMC_EINVAL, "aircraft[%d]: angle limits must be in (0, pi/2)", i);
+        if (!(s->env[2] > 0)) return fail(nullptr, SMC_EINVAL, "v_min must be > 0");
+    }
+    if (!(s->ctrl_lo[1] > 0)) return fail(nullptr, SMC_EINVAL, "airspeed control must be > 0");
+    if (!(s->time_norm > 0) || !(s->noise_alt > 0))
+        return fail(nullptr, SMC_EINVAL, "time_norm and noise_alt must be > 0");
+    if (s->popdense && (s->pop_n[0] < 2 || s->pop_n[1] < 2))
+        return fail(nullptr, SMC_EINVAL, "population grid needs >= 2 nodes per axis");
+    if (s->precision != SMC_FP64 && s->precision != SMC_FP32)
+        return fail(nullptr, SMC_EINVAL, "precision must be SMC_FP64 or SMC_FP32");
+    if (s->move != SMC_MOVE_JITTER && s->move != SMC_MOVE_RWMH)
+        return fail(nullptr, SMC_EINVAL, "move must be SMC_MOVE_JITTER or SMC_MOVE_RWMH");
+    if (!(s->kappa >= 0) || !(s->sigma_move >= 0))
+        return fail(nullptr, SMC_EINVAL, "kappa and sigma_move must be >= 0");
+    const double D = (double)s->n_particles * s->n_aircraft * s->n_segments * 3;
+    if (D >= 4294967295.0)
+        return fail(nullptr, SMC_EINVAL, "particle array exceeds 2^32 elements (Philox element index)");
+    if ((double)G * s->n_wind >= 4294967295.0)
+        return fail(nullptr, SMC_EINVAL, "wind normals exceed 2^32 elements");
+    return SMC_OK;
+}
+
+smc_status ensure_eval(smc_ctx* c, int64_t P) {
+    if (P <= c->eval_cap) return SMC_OK;
+    for (void* p : {c->d_ueval, (void*)c->d_ecost, (void*)c->d_efeas, (void*)c->d_echat,
+                    (void*)c->d_elogw, (void*)c->d_efeaspn}) {
+        if (!p) continue;
+        for (auto it = c->bufs.begin(); it != c->bufs.end(); ++it)
+            if (it->p == p) { (void)hipFree(p); c->bufs.erase(it); break; }
+    }
+    const size_t D = (size_t)c->N * c->S * 3;
+    smc_status s;
+    if ((s = dalloc(c, &c->d_ueval, (size_t)P * D * c->rsz))) return s;
+    if ((s = dalloc_t(c, &c->d_ecost, (size_t)P * c->M * c->N))) return s;
+    if ((s = dalloc_t(c, &c->d_efeas, (size_t)P * c->M * c->N))) return s;
+    if ((s = dalloc_t(c, &c->d_echat, (size_t)P * c->N))) return s;
+    if ((s = dalloc_t(c, &c->d_elogw, (size_t)P * c->N))) return s;
+    if ((s = dalloc_t(c, &c->d_efeaspn, (size_t)P * c->N))) return s;
+    c->eval_cap = P;
+    return SMC_OK;
+}
+
+RolloutArrays rollout_arrays(smc_ctx* c, const void* u, const void* W, const double* states,
+                             const int32_t* kact, double* cost, uint8_t* feas,
+                             unsigned long long* steps) {
+    RolloutArrays a;
+    a.u = u;
+    a.W = W;
+    a.states = states;
+    a.k_active = kact;
+    a.acpar = c->d_acpar;
+    a.targets = c->d_targets;
+    a.kind = c->d_kind;
+    a.pop = c->d_pop;
+    a.cost = cost;
+    a.feas = feas;
+    a.steps = steps;
+    return a;
+}
+
+smc_status check_horizon(smc_ctx* c, int32_t horizon) {
+    if (horizon < 1 || horizon > c->Hmax)
+        return fail(c, SMC_EINVAL, "horizon %d outside [1, %d]", horizon, c->Hmax);
+    if (horizon < c->S)
+        return fail(c, SMC_EINVAL, "horizon %d shorter than n_segments %d", horizon, c->S);
+    return SMC_OK;
+}
+
+// The SMC loop of one MPC update on device buffers (Alg. 1).
+smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const int32_t* d_kact,
+                    const double* wind_mean, int32_t horizon, double* d_ctrl, double* d_cost_out,
+                    int32_t* d_status, smc_step_info* info, hipStream_t st) {
+    smc_status vs = check_horizon(c, horizon);
+    if (vs) return vs;
+    if (!wind_mean) return fail(c, SMC_EINVAL, "wind_mean is NULL");
+    const int N = c->N, L = c->L, D = c->S * 3;
+    const int64_t count = (int64_t)L * N * D;
+    RolloutParams rp = c->rp;
+    rp.H = horizon;
+    rp.P = L;
+    unsigned long long* steps = info ? c->d_steps : nullptr;
+    if (info) {
+        HIP_OK(c, hipMemsetAsync(c->d_steps, 0, sizeof(unsigned long long) * kStepSlots, st));
+        HIP_OK(c, hipEventRecord(c->ev0, st));
+    }
+    void* u = c->d_u;
+    void* u2 = c->d_u2;
+    HIP_OK(c, launch_init_particles(c->prec, make_stream(c->seed, mpc_step, 0, P_INIT, c->scen_id),
+                                    count, u, st));
+    double acc_sum = 0.0;
+    int acc_n = 0;
+    std::vector<int32_t> hflags;
+    for (int J = 0; J < c->K; ++J) {
+        const double beta = beta_of(c, J);
+        HIP_OK(c, launch_wind_normals(c->prec, make_stream(c->seed, mpc_step, J, P_WIND, c->scen_id),
+                                      c->G, c->M, c->d_Z, st));
+        HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G,
+                                   c->M, c->d_W, st));
+        HIP_OK(c, launch_rollout(c->prec, rp,
+                                 rollout_arrays(c, u, c->d_W, d_states, d_kact, c->d_cost,
+                                                c->d_feas, steps),
+                                 st));
+        HIP_OK(c, launch_reduce(L, c->M, N, c->d_cost, c->d_feas, beta, c->d_chat, c->d_feaspn,
+                                c->d_logw, st));
+        if (c->move == SMC_MOVE_RWMH) {
+            const Stream sm = make_stream(c->seed, mpc_step, J, P_MOVE, c->scen_id);
+            HIP_OK(c, launch_propose(c->prec, count, u, c->d_up, sm, c->sigma_move, st));
+            HIP_OK(c, launch_rollout(c->prec, rp,
+                                     rollout_arrays(c, c->d_up, c->d_W, d_states, d_kact,
+                                                    c->d_cost, c->d_feas, steps),
+                                     st));
+            HIP_OK(c, launch_reduce(L, c->M, N, c->d_cost, c->d_feas, beta, c->d_chat2,
+                                    c->d_feaspn2, c->d_logw2, st));
+            HIP_OK(c, launch_accept(c->prec, L, N, D, u, c->d_up, c->d_chat, c->d_chat2,
+                                    c->d_feaspn, c->d_feaspn2, c->d_logw, c->d_logw2,
+                                    make_stream(c->seed, mpc_step, J, P_ACCEPT, c->scen_id),
+                                    nullptr, c->d_flags, st));
+            if (info) {
+                hflags.resize(L);
+                HIP_OK(c, hipMemcpyAsync(hflags.data(), c->d_flags, sizeof(int32_t) * L,
+                                         hipMemcpyDeviceToHost, st));
+                HIP_OK(c, hipStreamSynchronize(st));
+                long a = 0;
+                for (int l = 0; l < L; ++l) a += hflags[l];
+                acc_sum += (double)a / L;
+                ++acc_n;
+            }
+        }
+        if (J == c->K - 1) break;
+        HIP_OK(c, launch_resample_offsets(make_stream(c->seed, mpc_step, J, P_RESAMPLE, c->scen_id),
+                                          N, c->d_U, st));
+        HIP_OK(c, launch_resample(L, N, c->d_logw, c->d_U, c->d_scan, c->d_anc, nullptr, st));
+        HIP_OK(c, launch_gather_move(c->prec, L, N, D, u, c->d_anc, u2,
+                                     make_stream(c->seed, mpc_step, J, P_MOVE, c->scen_id),
+                                     c->sigma_move, c->move == SMC_MOVE_JITTER ? 1 : 0, st));
+        std::swap(u, u2);
+    }
+    const double beta_last = beta_of(c, c->K - 1);
+    HIP_OK(c, launch_select(L, N, c->d_logw, c->d_chat, beta_last, c->d_best, st));
+    HIP_OK(c, launch_write_result(c->prec, N, c->S, u, c->d_best, c->d_chat, c->ctrl_lo,
+                                  c->ctrl_span, d_ctrl, d_cost_out,
+                                  d_status ? d_status : c->d_status, st));
+    if (!info) return SMC_OK;
+
+    HIP_OK(c, hipEventRecord(c->ev1, st));
+    HIP_OK(c, hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIP_OK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    int32_t best[2];
+    HIP_OK(c, hipMemcpy(best, c->d_best, sizeof best, hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> cnt(kStepSlots);
+    HIP_OK(c, hipMemcpy(cnt.data(), c->d_steps, sizeof(unsigned long long) * kStepSlots,
+                        hipMemcpyDeviceToHost));
+    std::vector<uint8_t> fe((size_t)L * N);
+    HIP_OK(c, hipMemcpy(fe.data(), c->d_feaspn, fe.size(), hipMemcpyDeviceToHost));
+    // ESS of the final weights (diagnostic)
+    HIP_OK(c, launch_resample_offsets(make_stream(c->seed, mpc_step, c->K - 1, P_RESAMPLE, c->scen_id),
+                                      N, c->d_U, st));
+    HIP_OK(c, launch_resample(L, N, c->d_logw, c->d_U, c->d_scan, c->d_anc, c->d_ess, st));
+    std::vector<double> ess(N);
+    HIP_OK(c, hipMemcpyAsync(ess.data(), c->d_ess, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipStreamSynchronize(st));
+    long nf = 0;
+    for (uint8_t f : fe) nf += f;
+    unsigned long long tot = 0;
+    for (auto v : cnt) tot += v;
+    info->iterations = c->K;
+    info->best_particle = best[0];
+    info->feasible_frac = (double)nf / (double)fe.size();
+    info->accept_rate = acc_n ? acc_sum / acc_n : 0.0;
+    info->ess_min = *std::min_element(ess.begin(), ess.end());
+    info->aircraft_steps = (int64_t)tot;
+    info->ms_total = ms;
+    return best[1] ? SMC_INFEASIBLE : SMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* smc_version(void) { return "smc-mpc-gfx950 0.1"; }
+
+const char* smc_last_error(const smc_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+void smc_destroy(smc_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& b : c->bufs) (void)hipFree(b.p);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
+    if (!out) return fail(nullptr, SMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    smc_status vs = validate(s);
+    if (vs) return vs;
+    smc_ctx* c = new (std::nothrow) smc_ctx();
+    if (!c) return fail(nullptr, SMC_ENOMEM, "host allocation failed");
+    c->N = s->n_aircraft; c->S = s->n_segments; c->Hmax = s->horizon_max;
+    c->L = s->n_particles; c->M = s->n_wind; c->K = s->n_iters;
+    c->nx = s->grid_n[0]; c->ny = s->grid_n[1]; c->nz = s->grid_n[2];
+    c->G = c->nx * c->ny * c->nz;
+    c->prec = s->precision; c->move = s->move; c->scen_id = s->scenario_id;
+    c->dt = s->dt;
+    for (int a = 0; a < 3; ++a) {
+        c->box[a] = s->box[a];
+        c->ctrl_lo[a] = s->ctrl_lo[a];
+        c->ctrl_hi[a] = s->ctrl_hi[a];
+        c->ctrl_span[a] = s->ctrl_hi[a] - s->ctrl_lo[a];
+    }
+    c->sigma = s->wind_sigma; c->ell = s->wind_ell; c->nugget = s->wind_nugget;
+    c->sep_h = s->sep_h; c->sep_v = s->sep_v;
+    std::memcpy(c->env, s->env, sizeof c->env);
+    std::memcpy(c->landing, s->landing, sizeof c->landing);
+    std::memcpy(c->cost_w, s->cost_w, sizeof c->cost_w);
+    c->time_norm = s->time_norm; c->noise_alt = s->noise_alt;
+    c->kappa = s->kappa; c->sigma_move = s->sigma_move; c->mala_step = s->mala_step;
+    c->seed = s->seed;
+    c->use_noise = (s->popdense != nullptr && s->cost_w[8] != 0.0) ? 1 : 0;
+    c->pop_nx = s->popdense ? s->pop_n[0] : 0;
+    c->pop_ny = s->popdense ? s->pop_n[1] : 0;
+    c->rsz = c->prec == SMC_FP64 ? sizeof(double) : sizeof(float);
+
+    // rollout scalars
+    RolloutParams& rp = c->rp;
+    std::memset(&rp, 0, sizeof rp);
+    rp.N = c->N; rp.S = c->S; rp.H = c->Hmax; rp.P = c->L; rp.M = c->M; rp.G = c->G;
+    rp.nx = c->nx; rp.ny = c->ny; rp.nz = c->nz;
+    rp.use_noise = c->use_noise; rp.pop_nx = c->pop_nx; rp.pop_ny = c->pop_ny;
+    rp.half_wx = 0.5 * c->box[0]; rp.half_wy = 0.5 * c->box[1];
+    rp.inv_hx = (c->nx - 1) / c->box[0]; rp.inv_hy = (c->ny - 1) / c->box[1];
+    rp.inv_hz = (c->nz - 1) / c->box[2];
+    rp.pop_inv_hx = c->pop_nx > 1 ? (c->pop_nx - 1) / c->box[0] : 0.0;
+    rp.pop_inv_hy = c->pop_ny > 1 ? (c->pop_ny - 1) / c->box[1] : 0.0;
+    rp.dt = c->dt; rp.sep_h2 = c->sep_h * c->sep_h; rp.sep_v = c->sep_v;
+    for (int a = 0; a < 3; ++a) { rp.ctrl_lo[a] = c->ctrl_lo[a]; rp.ctrl_span[a] = c->ctrl_span[a]; }
+    rp.zmin = c->env[0]; rp.zmax = c->env[1]; rp.vmin = c->env[2]; rp.vmax = c->env[3];
+    rp.p_run = c->landing[0]; rp.p_beta = c->landing[1]; rp.p_chi = c->landing[2];
+    rp.p_vs = c->landing[3]; rp.beta_f = c->landing[4];
+    for (int a = 0; a < 9; ++a) rp.w[a] = c->cost_w[a];
+    rp.time_norm = c->time_norm; rp.noise_alt = c->noise_alt;
+    rp.zdot_max = std::max(std::fabs(c->ctrl_lo[2]), std::fabs(c->ctrl_hi[2]));
+
+    // wind factor per axis (FP64, host)
+    std::vector<double> Lx, Ly, Lz;
+    if (!axis_factor(c->nx, -0.5 * c->box[0], 0.5 * c->box[0], c->ell, c->nugget, Lx) ||
+        !axis_factor(c->ny, -0.5 * c->box[1], 0.5 * c->box[1], c->ell, c->nugget, Ly) ||
+        !axis_factor(c->nz, 0.0, c->box[2], c->ell, c->nugget, Lz)) {
+        g_init_error = "wind covariance not positive definite (raise wind_nugget)";
+        delete c;
+        return SMC_ENOTSPD;
+    }
+
+    smc_status st;
+    auto bail = [&](smc_status code) {
+        g_init_error = c->err;
+        smc_destroy(c);
+        return code;
+    };
+    hipError_t he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (he != hipSuccess) {
+        fail(c, SMC_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(he));
+        return bail(SMC_EDEVICE);
+    }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        fail(c, SMC_EDEVICE, "hipEventCreate failed");
+        return bail(SMC_EDEVICE);
+    }
+    const size_t N = c->N, L = c->L, M = c->M, G = c->G, D = (size_t)c->S * 3;
+    double *d_Lx = nullptr, *d_Ly = nullptr, *d_Lz = nullptr;
+    if ((st = dalloc_t(c, &c->d_acpar, N * SMC_AC_NPAR)) || (st = dalloc_t(c, &c->d_targets, N * 4)) ||
+        (st = dalloc_t(c, &c->d_kind, N)) ||
+        (st = dalloc(c, &c->d_Lfac, G * G * c->rsz)) || (st = dalloc(c, &c->d_Z, G * 2 * M * c->rsz)) ||
+        (st = dalloc(c, &c->d_W, M * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_u, L * N * D * c->rsz)) ||
+        (st = dalloc(c, &c->d_u2, L * N * D * c->rsz)) ||
+        (st = dalloc(c, &c->d_up, (c->move == SMC_MOVE_RWMH ? L : 1) * N * D * c->rsz)) ||
+        (st = dalloc_t(c, &c->d_cost, M * L * N)) || (st = dalloc_t(c, &c->d_feas, M * L * N)) ||
+        (st = dalloc_t(c, &c->d_chat, L * N)) || (st = dalloc_t(c, &c->d_logw, L * N)) ||
+        (st = dalloc_t(c, &c->d_chat2, L * N)) || (st = dalloc_t(c, &c->d_logw2, L * N)) ||
+        (st = dalloc_t(c, &c->d_feaspn, L * N)) || (st = dalloc_t(c, &c->d_feaspn2, L * N)) ||
+        (st = dalloc_t(c, &c->d_anc, N * L)) || (st = dalloc_t(c, &c->d_U, N)) ||
+        (st = dalloc_t(c, &c->d_scan, N * L)) || (st = dalloc_t(c, &c->d_ess, N)) ||
+        (st = dalloc_t(c, &c->d_flags, L)) || (st = dalloc_t(c, &c->d_best, 2)) ||
+        (st = dalloc_t(c, &c->d_status, 1)) || (st = dalloc_t(c, &c->d_steps, kStepSlots)) ||
+        (st = dalloc_t(c, &c->d_states, N * 6)) || (st = dalloc_t(c, &c->d_kact, N)) ||
+        (st = dalloc_t(c, &c->d_ctrl_out, N * D)) || (st = dalloc_t(c, &c->d_cost_out, 1 + N)) ||
+        (st = dalloc_t(c, &d_Lx, (size_t)c->nx * c->nx)) || (st = dalloc_t(c, &d_Ly, (size_t)c->ny * c->ny)) ||
+        (st = dalloc_t(c, &d_Lz, (size_t)c->nz * c->nz)))
+        return bail(st);
+    if (c->use_noise || s->popdense) {
+        if ((st = dalloc_t(c, &c->d_pop, (size_t)c->pop_nx * c->pop_ny))) return bail(st);
+    }
+#define INIT_HIP(expr)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            fail(c, SMC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+            return bail(SMC_EDEVICE);                                                    \
+        }                                                                                \
+    } while (0)
+    INIT_HIP(hipMemcpy(c->d_acpar, s->aircraft, N * SMC_AC_NPAR * sizeof(double), hipMemcpyHostToDevice));
+    INIT_HIP(hipMemcpy(c->d_targets, s->targets, N * 4 * sizeof(double), hipMemcpyHostToDevice));
+    INIT_HIP(hipMemcpy(c->d_kind, s->kind, N, hipMemcpyHostToDevice));
+    if (c->d_pop)
+        INIT_HIP(hipMemcpy(c->d_pop, s->popdense, (size_t)c->pop_nx * c->pop_ny * sizeof(float),
+                           hipMemcpyHostToDevice));
+    INIT_HIP(hipMemcpy(d_Lx, Lx.data(), Lx.size() * sizeof(double), hipMemcpyHostToDevice));
+    INIT_HIP(hipMemcpy(d_Ly, Ly.data(), Ly.size() * sizeof(double), hipMemcpyHostToDevice));
+    INIT_HIP(hipMemcpy(d_Lz, Lz.data(), Lz.size() * sizeof(double), hipMemcpyHostToDevice));
+    INIT_HIP(launch_kron_expand(c->prec, d_Lx, d_Ly, d_Lz, c->nx, c->ny, c->nz, c->sigma, c->d_Lfac,
+                                c->stream));
+    INIT_HIP(hipStreamSynchronize(c->stream));
+#undef INIT_HIP
+    *out = c;
+    return SMC_OK;
+}
+
+smc_status smc_mpc_step_dev(smc_ctx* c, int64_t mpc_step, const double* d_states,
+                            const int32_t* d_kact, const double* wind_mean, int32_t horizon,
+                            double* d_ctrl, double* d_cost_out, int32_t* d_status,
+                            smc_step_info* info, void* stream) {
+    if (!c) return fail(nullptr, SMC_EINVAL, "ctx is NULL");
+    if (!d_states || !d_kact || !d_ctrl || !d_cost_out)
+        return fail(c, SMC_EINVAL, "NULL device pointer");
+    return run_step(c, mpc_step, d_states, d_kact, wind_mean, horizon, d_ctrl, d_cost_out,
+                    d_status, info, pick(c, stream));
+}
+
+smc_status smc_mpc_step(smc_ctx* c, int64_t mpc_step, const double* states,
+                        const int32_t* k_active, const double* wind_mean, int32_t horizon,
+                        double* controls_out, double* exp_cost_out, smc_step_info* info) {
+    if (!c) return fail(nullptr, SMC_EINVAL, "ctx is NULL");
+    if (!states || !k_active || !wind_mean || !controls_out || !exp_cost_out)
+        return fail(c, SMC_EINVAL, "NULL argument");
+    smc_status vs = check_horizon(c, horizon);
+    if (vs) return vs;
+    hipStream_t st = c->stream;
+    HIP_OK(c, hipMemcpyAsync(c->d_states, states, sizeof(double) * c->N * 6, hipMemcpyHostToDevice, st));
+    HIP_OK(c, hipMemcpyAsync(c->d_kact, k_active, sizeof(int32_t) * c->N, hipMemcpyHostToDevice, st));
+    smc_step_info local;
+    smc_status r = run_step(c, mpc_step, c->d_states, c->d_kact, wind_mean, horizon, c->d_ctrl_out,
+                            c->d_cost_out, c->d_status, info ? info : &local, st);
+    if (r < 0) return r;
+    HIP_OK(c, hipMemcpyAsync(controls_out, c->d_ctrl_out, sizeof(double) * c->N * c->S * 3,
+                             hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipMemcpyAsync(exp_cost_out, c->d_cost_out, sizeof(double) * (1 + c->N),
+                             hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipStreamSynchronize(st));
+    return r;
+}
+
+smc_status smc_eval_cost(smc_ctx* c, int64_t mpc_step, int32_t iter, const double* states,
+                         const int32_t* k_active, const double* wind_mean, int32_t horizon,
+                         const double* particles, int32_t P, double* cost_out,
+                         uint8_t* feasible_out) {
+    if (!c) return fail(nullptr, SMC_EINVAL, "ctx is NULL");
+    if (!states || !k_active || !wind_mean || !particles || !cost_out || !feasible_out)
+        return fail(c, SMC_EINVAL, "NULL argument");
+    if (P < 1) return fail(c, SMC_EINVAL, "P must be >= 1");
+    if (iter < 0) return fail(c, SMC_EINVAL, "iter must be >= 0");
+    smc_status vs = check_horizon(c, horizon);
+    if (vs) return vs;
+    if ((double)P * c->N * c->S * 3 >= 4294967295.0) return fail(c, SMC_EINVAL, "too many particles");
+    if ((vs = ensure_eval(c, P))) return vs;
+    hipStream_t st = c->stream;
+    const size_t D = (size_t)c->N * c->S * 3;
+    const size_t n = (size_t)P * D;
+    if (c->prec == SMC_FP64) {
+        HIP_OK(c, hipMemcpyAsync(c->d_ueval, particles, n * sizeof(double), hipMemcpyHostToDevice, st));
+    } else {
+        std::vector<float> tmp(n);
+        for (size_t e = 0; e < n; ++e) tmp[e] = (float)particles[e];
+        HIP_OK(c, hipMemcpyAsync(c->d_ueval, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+        HIP_OK(c, hipStreamSynchronize(st));
+    }
+    HIP_OK(c, hipMemcpyAsync(c->d_states, states, sizeof(double) * c->N * 6, hipMemcpyHostToDevice, st));
+    HIP_OK(c, hipMemcpyAsync(c->d_kact, k_active, sizeof(int32_t) * c->N, hipMemcpyHostToDevice, st));
+    HIP_OK(c, launch_wind_normals(c->prec, make_stream(c->seed, mpc_step, iter, P_WIND, c->scen_id),
+                                  c->G, c->M, c->d_Z, st));
+    HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G, c->M,
+                               c->d_W, st));
+    RolloutParams rp = c->rp;
+    rp.H = horizon;
+    rp.P = P;
+    HIP_OK(c, launch_rollout(c->prec, rp,
+                             rollout_arrays(c, c->d_ueval, c->d_W, c->d_states, c->d_kact, c->d_ecost,
+                                            c->d_efeas, nullptr),
+                             st));
+    HIP_OK(c, launch_reduce(P, c->M, c->N, c->d_ecost, c->d_efeas, 1.0, c->d_echat, c->d_efeaspn,
+                            c->d_elogw, st));
+    HIP_OK(c, hipMemcpyAsync(cost_out, c->d_echat, sizeof(double) * P * c->N, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipMemcpyAsync(feasible_out, c->d_efeaspn, (size_t)P * c->N, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipStreamSynchronize(st));
+    return SMC_OK;
+}
+
+// ---- kernel-level entry points -------------------------------------------------------
+
+smc_status smc_k_philox(uint64_t seed, int64_t mpc_step, int32_t iter, int32_t purpose,
+                        int32_t scenario, int64_t e0, int64_t n, uint32_t* out, void* stream) {
+    if (!out || n < 0 || e0 < 0 || e0 + n > 4294967296LL)
+        return fail(nullptr, SMC_EINVAL, "smc_k_philox: bad arguments");
+    hipError_t e = launch_philox_words(make_stream(seed, mpc_step, iter, (uint32_t)purpose, scenario),
+                                       (uint32_t)e0, n, out, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, SMC_EDEVICE, "philox launch: %s", hipGetErrorString(e));
+    return SMC_OK;
+}
+
+smc_status smc_k_init_particles(smc_ctx* c, int64_t mpc_step, int32_t P, void* u, void* stream) {
+    if (!c || !u || P < 1) return fail(c, SMC_EINVAL, "smc_k_init_particles: bad arguments");
+    const int64_t count = (int64_t)P * c->N * c->S * 3;
+    if (count >= 4294967296LL) return fail(c, SMC_EINVAL, "too many particles");
+    HIP_OK(c, launch_init_particles(c->prec, make_stream(c->seed, mpc_step, 0, P_INIT, c->scen_id),
+                                    count, u, pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_wind_normals(smc_ctx* c, int64_t mpc_step, int32_t iter, void* Z, void* stream) {
+    if (!c || !Z || iter < 0) return fail(c, SMC_EINVAL, "smc_k_wind_normals: bad arguments");
+    HIP_OK(c, launch_wind_normals(c->prec, make_stream(c->seed, mpc_step, iter, P_WIND, c->scen_id),
+                                  c->G, c->M, Z, pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_wind_gemm(smc_ctx* c, const void* Z, const double* wind_mean, void* W, void* stream) {
+    if (!c || !Z || !W || !wind_mean) return fail(c, SMC_EINVAL, "smc_k_wind_gemm: bad arguments");
+    HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, Z, wind_mean[0], wind_mean[1], c->G, c->M, W,
+                               pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_wind_factor(smc_ctx* c, void* out, void* stream) {
+    if (!c || !out) return fail(c, SMC_EINVAL, "smc_k_wind_factor: bad arguments");
+    HIP_OK(c, hipMemcpyAsync(out, c->d_Lfac, (size_t)c->G * c->G * c->rsz, hipMemcpyDeviceToDevice,
+                             pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_rollout(smc_ctx* c, const void* u, int32_t P, const void* W, const double* states,
+                         const int32_t* k_active, int32_t horizon, double* cost, uint8_t* feas,
+                         uint64_t* steps, void* stream) {
+    if (!c || !u || !W || !states || !k_active || !cost || !feas || P < 1)
+        return fail(c, SMC_EINVAL, "smc_k_rollout: bad arguments");
+    smc_status vs = check_horizon(c, horizon);
+    if (vs) return vs;
+    RolloutParams rp = c->rp;
+    rp.H = horizon;
+    rp.P = P;
+    HIP_OK(c, launch_rollout(c->prec, rp,
+                             rollout_arrays(c, u, W, states, k_active, cost, feas,
+                                            (unsigned long long*)steps),
+                             pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_reduce(smc_ctx* c, int32_t P, const double* cost, const uint8_t* feas, double beta,
+                        double* chat, uint8_t* feas_pn, double* logw, void* stream) {
+    if (!c || !cost || !feas || !chat || !feas_pn || !logw || P < 1)
+        return fail(c, SMC_EINVAL, "smc_k_reduce: bad arguments");
+    HIP_OK(c, launch_reduce(P, c->M, c->N, cost, feas, beta, chat, feas_pn, logw, pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_resample_offsets(smc_ctx* c, int64_t mpc_step, int32_t iter, uint32_t* U,
+                                  void* stream) {
+    if (!c || !U) return fail(c, SMC_EINVAL, "smc_k_resample_offsets: bad arguments");
+    HIP_OK(c, launch_resample_offsets(make_stream(c->seed, mpc_step, iter, P_RESAMPLE, c->scen_id),
+                                      c->N, U, pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_resample(smc_ctx* c, int32_t P, const double* logw, const uint32_t* U,
+                          int32_t* anc, double* ess, void* stream) {
+    if (!c || !logw || !U || !anc || P < 1) return fail(c, SMC_EINVAL, "smc_k_resample: bad arguments");
+    if (P > c->L) {
+        // the scan scratch holds N x L doubles
+        return fail(c, SMC_EINVAL, "smc_k_resample: P exceeds the context's n_particles");
+    }
+    HIP_OK(c, launch_resample(P, c->N, logw, U, c->d_scan, anc, ess, pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_gather_move(smc_ctx* c, int32_t P, const void* u_in, const int32_t* anc,
+                             void* u_out, int64_t mpc_step, int32_t iter, int32_t jitter,
+                             void* stream) {
+    if (!c || !u_in || !anc || !u_out || P < 1 || u_in == u_out)
+        return fail(c, SMC_EINVAL, "smc_k_gather_move: bad arguments");
+    HIP_OK(c, launch_gather_move(c->prec, P, c->N, c->S * 3, u_in, anc, u_out,
+                                 make_stream(c->seed, mpc_step, iter, P_MOVE, c->scen_id),
+                                 c->sigma_move, jitter, pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_propose(smc_ctx* c, int32_t P, const void* u, void* u_prop, int64_t mpc_step,
+                         int32_t iter, void* stream) {
+    if (!c || !u || !u_prop || P < 1) return fail(c, SMC_EINVAL, "smc_k_propose: bad arguments");
+    HIP_OK(c, launch_propose(c->prec, (int64_t)P * c->N * c->S * 3, u, u_prop,
+                             make_stream(c->seed, mpc_step, iter, P_MOVE, c->scen_id), c->sigma_move,
+                             pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_accept(smc_ctx* c, int32_t P, void* u, const void* u_prop, double* chat,
+                        const double* chat_prop, uint8_t* feas_pn, const uint8_t* feas_prop,
+                        double* logw, const double* logw_prop, int64_t mpc_step, int32_t iter,
+                        int32_t* accepted, void* stream) {
+    if (!c || !u || !u_prop || !chat || !chat_prop || !feas_pn || !feas_prop || !logw || !logw_prop ||
+        P < 1)
+        return fail(c, SMC_EINVAL, "smc_k_accept: bad arguments");
+    if (!accepted && P > c->L) return fail(c, SMC_EINVAL, "smc_k_accept: P exceeds n_particles");
+    HIP_OK(c, launch_accept(c->prec, P, c->N, c->S * 3, u, u_prop, chat, chat_prop, feas_pn, feas_prop,
+                            logw, logw_prop,
+                            make_stream(c->seed, mpc_step, iter, P_ACCEPT, c->scen_id), accepted,
+                            c->d_flags, pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_select(smc_ctx* c, int32_t P, const double* logw, const double* chat, double beta,
+                        int32_t* best, void* stream) {
+    if (!c || !logw || !chat || !best || P < 1) return fail(c, SMC_EINVAL, "smc_k_select: bad arguments");
+    HIP_OK(c, launch_select(P, c->N, logw, chat, beta, best, pick(c, stream)));
+    return SMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,329 @@
+"""GPU parity of each hot-path kernel against the FP64 oracle, on identical
+inputs, through the C ABI.
+
+Tolerances:
+  * integer work (Philox words, ancestors, selection index): bit-exact;
+  * FP64 kernels: a few ulps of the operation count involved (Box-Muller and
+    trilinear/dynamics transcendentals differ by libm/ocml ulps);
+  * FP32 kernels: 1e-5 relative on per-particle expected cost, as the
+    target states, with near-threshold decisions (relative margin < 1e-4)
+    excluded and counted.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import philox as oph
+from oracle import rollout as oro
+from oracle import smc as osmc
+from oracle import wind as owind
+from tests.gpu_helpers import dev, empty, host, rel_err, separable_field, small_scenario, zeros
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(lib, scen):
+    return lib.smc_mpc_init(scen)
+
+
+# ---- RNG -------------------------------------------------------------------------
+
+@pytest.mark.parametrize("stream", [(0, 0, 0, 1, 0), (123456789012345, 7, 3, 2, 5),
+                                    (2**64 - 1, -1, 2**31 - 1, 6, 255)])
+def test_philox_words_bit_exact(lib, stream):
+    import torch
+    seed, step, J, purpose, scen = stream
+    for e0, n in ((0, 1), (0, 1000), (2**32 - 5, 5), (77777, 4097)):
+        out = zeros((n, 4), torch.int32)
+        lib.smc_k_philox(seed, step, J, purpose, scen, e0, n, out)
+        got = host(out).view(np.uint32)
+        ref = oph.words(seed, step, J, purpose, np.arange(e0, e0 + n, dtype=np.int64), scen)
+        assert np.array_equal(got, np.stack(ref, axis=1))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_init_particles(lib, prec):
+    s = small_scenario("c1", prec)
+    ctx = _ctx(lib, s)
+    P = 300
+    u = empty((P, s["N"], s["S"], 3), ctx.real_dtype)
+    lib.smc_k_init_particles(ctx, 5, P, u)
+    ref = osmc.init_particles(s, mpc_step=5, L=P)
+    got = host(u)
+    if prec == "fp64":
+        assert np.array_equal(got, ref)
+    else:
+        assert np.array_equal(got, ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wind_normals(lib, prec):
+    s = small_scenario("c1", prec)
+    ctx = _ctx(lib, s)
+    G, M = ctx.G, ctx.M
+    Z = empty((G, 2 * M), ctx.real_dtype)
+    lib.smc_k_wind_normals(ctx, 2, 9, Z)
+    ref = owind.wind_normals(s["seed"], 2, 9, G, M).reshape(G, 2 * M)
+    got = host(Z).astype(np.float64)
+    if prec == "fp64":
+        assert np.abs(got - ref).max() < 1e-13
+    else:
+        assert np.abs(got - ref).max() < 6e-7 * max(1.0, np.abs(ref).max())
+
+
+def test_wind_factor_matches_kronecker(lib):
+    s = small_scenario("c1", "fp64")
+    ctx = _ctx(lib, s)
+    out = empty((ctx.G, ctx.G), ctx.real_dtype)
+    lib.smc_k_wind_factor(ctx, out)
+    ref = owind.kron_factor(s["box"], s["grid"], s["wind_sigma"], s["wind_ell"], s["wind_nugget"])
+    assert np.abs(host(out) - ref).max() < 1e-13 * s["wind_sigma"]
+
+
+@pytest.mark.parametrize("prec,grid,M", [("fp64", (16, 16, 4), 16), ("fp64", (5, 7, 3), 3),
+                                         ("fp32", (16, 16, 4), 16), ("fp32", (32, 32, 8), 64),
+                                         ("fp32", (9, 6, 5), 40)])
+def test_wind_gemm(lib, prec, grid, M):
+    s = synth.shrink(small_scenario("c1", prec), grid=grid, M=M)
+    ctx = _ctx(lib, s)
+    G = ctx.G
+    rng = np.random.default_rng(G + M)
+    Zr = rng.standard_normal((G, 2 * M))
+    if prec == "fp32":
+        Zr = Zr.astype(np.float32).astype(np.float64)
+    Lf = owind.kron_factor(s["box"], s["grid"], s["wind_sigma"], s["wind_ell"], s["wind_nugget"])
+    wm = np.array([1.5, -2.0])
+    ref = owind.wind_field(Lf, Zr.reshape(G, M, 2), wm)
+    W = empty((M, G, 2), ctx.real_dtype)
+    lib.smc_k_wind_gemm(ctx, dev(Zr, ctx.real_dtype), wm, W)
+    got = host(W).astype(np.float64)
+    # error bound: sum over G terms of |L||Z| times the unit roundoff
+    scale = (np.abs(Lf) @ np.abs(Zr)).max()
+    eps = 2.3e-16 if prec == "fp64" else 1.2e-7
+    assert np.abs(got - ref).max() <= 4 * eps * scale + (0 if prec == "fp64" else 1e-6)
+
+
+# ---- rollout ---------------------------------------------------------------------
+
+def _rollout_case(lib, s, P, seed=0, horizon=None, states=None, k_active=None, u=None, W=None):
+    import torch
+    ctx = _ctx(lib, s)
+    rng = np.random.default_rng(seed)
+    N, S, M = s["N"], s["S"], s["M"]
+    H = s["H"] if horizon is None else horizon
+    states = s["states"] if states is None else states
+    k_active = s["k_active"] if k_active is None else k_active
+    if u is None:
+        u = rng.uniform(0, 1, (P, N, S, 3))
+    if W is None:
+        W = separable_field(s, seed + 100)
+    rnp = np.float64 if s["precision"] == 0 else np.float32
+    u = u.astype(rnp).astype(np.float64)
+    W = W.astype(rnp).astype(np.float64)
+    cost = empty((M, P, N), torch.float64)
+    feas = empty((M, P, N), torch.uint8)
+    steps = zeros((64,), torch.int64)
+    lib.smc_k_rollout(ctx, dev(u, ctx.real_dtype), P, dev(W, ctx.real_dtype), dev(states),
+                      dev(np.asarray(k_active, np.int32)), H, cost, feas, steps)
+    ref = oro.rollout(s, u, W, states, k_active, H, with_margins=True)
+    got_c = host(cost).transpose(1, 0, 2)
+    got_f = host(feas).transpose(1, 0, 2).astype(bool)
+    return ctx, got_c, got_f, int(host(steps).sum()), ref
+
+
+def _compare_rollout(got_c, got_f, ref, prec, near=1e-4):
+    margin = ref["margin"]
+    # a world with any near-threshold decision may legitimately differ
+    world_near = (margin < near).any(axis=2, keepdims=True) | (margin < near)
+    world_near = np.broadcast_to(world_near.any(axis=2, keepdims=True), margin.shape)
+    ok = ~world_near
+    tol = 1e-10 if prec == 0 else 2e-5
+    err = rel_err(got_c, ref["cost"])
+    assert np.all(got_f[ok] == ref["feas"][ok])
+    assert err[ok].max() < tol, err[ok].max()
+    return int(world_near[..., 0].sum())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rollout_c1_shape(lib, prec):
+    s = small_scenario("c1", prec)
+    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=200)
+    n_near = _compare_rollout(gc, gf, ref, s["precision"])
+    assert steps == ref["steps"]
+    assert n_near < 0.05 * 200 * s["M"]
+    # per-particle expected cost (mean over samples)
+    chat_ref, _ = osmc.expected_cost(ref["cost"], ref["feas"])
+    world_near = (ref["margin"] < 1e-4).any(axis=(1, 2))
+    err = rel_err(gc.mean(axis=1), chat_ref)[~world_near]
+    assert err.max() < (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rollout_c2_shape_ragged(lib, prec):
+    """10 aircraft (worlds of 10 lanes, 6 per wave, 4 idle lanes), staggered
+    departures, P not a multiple of the worlds per wave, grid 32x32x8."""
+    s = synth.shrink(synth.c2(precision=prec), M=5)
+    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=37, seed=4)
+    n_near = _compare_rollout(gc, gf, ref, s["precision"])
+    assert steps == ref["steps"]
+    assert n_near < 0.25 * 37 * 5
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 7, 16, 33, 64])
+def test_rollout_aircraft_counts(lib, N):
+    """Worlds from 1 lane to a full wave; mixed kinds and activation steps."""
+    rng = np.random.default_rng(N)
+    s = synth.make_scenario("T", n_arr=max(1, N // 2), n_dep=N - max(1, N // 2),
+                            box=(100e3, 100e3, 8e3), grid=(6, 5, 4), H=30, dt=5.0, S=3,
+                            M=3, L=8, K=2, precision="fp64", seed=N)
+    k_act = s["k_active"].copy()
+    k_act[rng.uniform(size=N) < 0.2] = -1
+    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=11, seed=N, horizon=27, k_active=k_act)
+    _compare_rollout(gc, gf, ref, 0)
+    assert steps == ref["steps"]
+
+
+def test_rollout_close_traffic_separation(lib):
+    """Aircraft packed inside one separation cell so that many pair tests
+    fire, exercising both the pair split and the mask reduction."""
+    N = 12
+    rng = np.random.default_rng(5)
+    s = synth.make_scenario("T", n_arr=0, n_dep=N, box=(60e3, 60e3, 6e3), grid=(4, 4, 3),
+                            H=8, dt=5.0, S=2, M=2, L=4, K=2, precision="fp64", seed=1)
+    st = np.zeros((N, 6))
+    st[:, 0] = rng.uniform(-8e3, 8e3, N)
+    st[:, 1] = rng.uniform(-8e3, 8e3, N)
+    st[:, 2] = rng.uniform(2000, 2800, N)
+    st[:, 3] = 150.0
+    st[:, 4] = rng.uniform(-3, 3, N)
+    st[:, 5] = 60e3
+    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=50, states=st, k_active=np.zeros(N, np.int32))
+    _compare_rollout(gc, gf, ref, 0)
+    assert (~ref["feas"]).mean() > 0.2
+
+
+def test_rollout_noise_term(lib):
+    s = synth.shrink(synth.c5(precision="fp64"), M=2, H=30, S=3, grid=(8, 8, 4))
+    s = dict(s)
+    keep = [0, 1, 2, 24, 25]
+    for k in ("kind", "aircraft", "targets", "states", "k_active"):
+        s[k] = s[k][keep]
+    s["N"] = len(keep)
+    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=20)
+    _compare_rollout(gc, gf, ref, 0)
+
+
+# ---- weights, resampling, moves, selection -------------------------------------
+
+def test_reduce_matches_oracle(lib):
+    import torch
+    s = small_scenario("c1", "fp64")
+    ctx = _ctx(lib, s)
+    P, M, N = 97, s["M"], s["N"]
+    rng = np.random.default_rng(0)
+    cost = rng.uniform(0, 1, (M, P, N))
+    feas = rng.uniform(size=(M, P, N)) > 0.02
+    chat = empty((P, N), torch.float64)
+    fpn = empty((P, N), torch.uint8)
+    logw = empty((P, N), torch.float64)
+    lib.smc_k_reduce(ctx, P, dev(cost), dev(feas.astype(np.uint8)), 8.0, chat, fpn, logw)
+    rc, rf = osmc.expected_cost(cost.transpose(1, 0, 2), feas.transpose(1, 0, 2))
+    assert np.abs(host(chat) - rc).max() < 4e-16
+    assert np.array_equal(host(fpn).astype(bool), rf)
+    rl = osmc.log_weights(rc, rf, 8.0)
+    gl = host(logw)
+    assert np.array_equal(np.isfinite(gl), np.isfinite(rl))
+    assert np.abs(gl[np.isfinite(rl)] - rl[np.isfinite(rl)]).max() < 1e-14
+
+
+@pytest.mark.parametrize("P", [1, 2, 7, 256, 1000, 1025, 8192, 65536])
+def test_resample_bit_exact(lib, P):
+    import torch
+    N = 3
+    s = synth.shrink(small_scenario("c1", "fp64"), L=max(P, 2))
+    s = dict(s)
+    for k in ("kind", "aircraft", "targets", "states", "k_active"):
+        s[k] = np.concatenate([s[k], s[k][:1]])
+    s["N"] = N
+    ctx = _ctx(lib, s)
+    rng = np.random.default_rng(P)
+    logw = rng.normal(0, 4, (P, N)) - 30.0
+    logw[rng.uniform(size=(P, N)) < 0.3] = -np.inf
+    logw[:, 2] = -np.inf                   # an all-violating row
+    if P > 1:
+        logw[0, 0] = -30.0                 # keep row 0 non-empty
+    U = rng.integers(0, 2**32, N, dtype=np.uint64).astype(np.uint32)
+    anc = empty((N, P), torch.int32)
+    lib.smc_k_resample(ctx, P, dev(logw), dev(U.view(np.int32)), anc)
+    got = host(anc)
+    for i in range(N):
+        ref = osmc.resample_row(logw[:, i], int(U[i]))
+        assert np.array_equal(got[i], ref), i
+
+
+def test_resample_offsets_and_gather_jitter(lib):
+    import torch
+    s = small_scenario("c1", "fp64")
+    ctx = _ctx(lib, s)
+    N, S, P = s["N"], s["S"], 333
+    U = empty((N,), torch.int32)
+    lib.smc_k_resample_offsets(ctx, 4, 6, U)
+    assert [int(x) for x in host(U).view(np.uint32)] == osmc.resample_offsets(s, 6, N, 4)
+    rng = np.random.default_rng(1)
+    u = rng.uniform(0, 1, (P, N, S, 3))
+    anc = np.sort(rng.integers(0, P, (N, P)), axis=1).astype(np.int32)
+    out = empty((P, N, S, 3), torch.float64)
+    for jit in (0, 1):
+        lib.smc_k_gather_move(ctx, P, dev(u), dev(anc), out, 4, 6, jit)
+        ref = osmc.gather(u, anc)
+        if jit:
+            ref = osmc.jitter(s, ref, 6, mpc_step=4)
+        assert np.abs(host(out) - ref).max() < 1e-15
+
+
+def test_propose_accept_select(lib):
+    import torch
+    s = small_scenario("c1", "fp64")
+    s = dict(s, move=1)
+    ctx = _ctx(lib, s)
+    N, S, P = s["N"], s["S"], 257
+    rng = np.random.default_rng(2)
+    u = rng.uniform(0, 1, (P, N, S, 3))
+    up = empty((P, N, S, 3), torch.float64)
+    lib.smc_k_propose(ctx, P, dev(u), up, 3, 5)
+    ref_up = osmc.rw_propose(s, u, 5, mpc_step=3)
+    assert np.abs(host(up) - ref_up).max() < 1e-15
+    chat = rng.uniform(0, 1, (P, N))
+    chat2 = rng.uniform(0, 1, (P, N))
+    f1 = rng.uniform(size=(P, N)) > 0.1
+    f2 = rng.uniform(size=(P, N)) > 0.1
+    l1 = osmc.log_weights(chat, f1, 9.0)
+    l2 = osmc.log_weights(chat2, f2, 9.0)
+    acc_ref = osmc.mh_accept(s, 5, l1, l2, mpc_step=3)
+    d_u, d_chat, d_f, d_l = dev(u), dev(chat), dev(f1.astype(np.uint8)), dev(l1)
+    acc = empty((P,), torch.int32)
+    lib.smc_k_accept(ctx, P, d_u, dev(ref_up), d_chat, dev(chat2), d_f,
+                     dev(f2.astype(np.uint8)), d_l, dev(l2), 3, 5, acc)
+    assert np.array_equal(host(acc).astype(bool), acc_ref)
+    assert np.array_equal(host(d_u), np.where(acc_ref[:, None, None, None], ref_up, u))
+    assert np.array_equal(host(d_chat), np.where(acc_ref[:, None], chat2, chat))
+    # selection
+    lw = np.where(acc_ref[:, None], l2, l1)
+    ch = np.where(acc_ref[:, None], chat2, chat)
+    best = empty((2,), torch.int32)
+    lib.smc_k_select(ctx, P, dev(lw), dev(ch), 9.0, best)
+    l_ref, bad = osmc.select_best(lw, ch, 9.0)
+    assert list(host(best)) == [l_ref, int(bad)]
+    # all infeasible -> fewest violators, then cost
+    lw2 = lw.copy()
+    lw2[:, 0] = -np.inf
+    lib.smc_k_select(ctx, P, dev(lw2), dev(ch), 9.0, best)
+    l_ref, bad = osmc.select_best(lw2, ch, 9.0)
+    assert list(host(best)) == [l_ref, 1]
+    # exact ties -> lowest index
+    lw3 = np.full((P, N), -1.0)
+    ch3 = np.full((P, N), 1.0 / 9.0)
+    lib.smc_k_select(ctx, P, dev(lw3), dev(ch3), 9.0, best)
+    assert list(host(best)) == [0, 0]
