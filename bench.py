@@ -1,0 +1,229 @@
+"""Throughput of one SMC-MPC update on one MI355X, with the rollout kernel's
+roofline fraction and the CPU oracle timed beside it.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+                [--no-cpu-baseline] [--cpu-particles P]
+
+A step is one MPC update: the whole hot path (particle init, K_smc wind
+fields, rollouts with separation, weighting, resampling, moves, final
+selection) over one synthetic scenario, inputs resident in device memory.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "aircraft-step rollouts/sec + ms per MPC step to cost within 1e-3 of oracle"
+
+# MI355X published peaks
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+
+# Algorithmic work of one aircraft-step of the rollout (elementary operations
+# of the oracle's per-step list, each transcendental counted once) and of
+# one pair test; see the design notes for the table.
+FLOPS_PER_AIRCRAFT_STEP = 174
+FLOPS_PER_PAIR_TEST = 9
+
+
+def rollout_flops_per_aircraft_step(N: int) -> float:
+    # each present aircraft-step carries (N - 1) / 2 pair tests
+    return FLOPS_PER_AIRCRAFT_STEP + FLOPS_PER_PAIR_TEST * (N - 1) / 2.0
+
+
+WORKLOADS = {
+    "c1": ("2 aircraft (1 arrival, 1 departure), 60x60x6 km, H=60 dt=5 s, S=6, wind 16x16x4 "
+           "M=16, L=256, K=20, FP64", "c1"),
+    "c2": ("10 aircraft (6 arrivals, 4 departures released at steps 0/12/24/36), "
+           "100x100x8 km, H=120 dt=5 s, S=8, wind 32x32x8 (G=8192) M=64, L=8192, K=40, "
+           "FP32 rollout with FP64 weights and scan, jitter moves", "c2"),
+}
+
+
+def _src_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1506_02869_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel_src: str, key: str, launches_bytes_alg: float):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or
+    None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "rollout_c2_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != _src_hash(kernel_src):
+        return None
+    return t.get(key)
+
+
+def cpu_baseline(scen, particles: int):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    `particles` particles, 2 SMC iterations, all wind samples, aircraft and
+    steps; one host thread (BLAS pinned to 1 thread)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import rollout as oro
+    from oracle import smc as osmc
+    from oracle import wind as owind
+
+    s = synth.shrink(scen, L=particles, K=2)
+    steps = 0
+
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        Lfac = owind.kron_factor(s["box"], s["grid"], s["wind_sigma"], s["wind_ell"],
+                                 s["wind_nugget"])
+
+        def evaluate(u, J):
+            nonlocal steps
+            W = owind.sample_field(s, J, s["mpc_step"], Lfac)
+            r = oro.rollout(s, u, W)
+            steps += r["steps"]
+            return osmc.expected_cost(r["cost"], r["feas"])
+
+        osmc.run_smc(s, evaluate, s["L"], s["K"], s["N"], s["S"])
+        dt = time.perf_counter() - t0
+    return {"value": steps / dt, "unit": "aircraft-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle smc loop on {particles} particles x {s['M']} wind samples x "
+                       f"{s['N']} aircraft x {s['H']} steps, 2 SMC iterations "
+                       f"({steps} aircraft-steps in {dt:.1f} s, wind factor included)"),
+            "seconds": round(dt, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-particles", type=int, default=64)
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding of the path is described in the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1506_02869_amd as smc
+    import synth
+
+    desc, key = WORKLOADS[args.workload]
+    scen = getattr(synth, key)()
+    torch.cuda.set_device(0)
+    ctx = smc.smc_mpc_init(scen)
+    dev = torch.device("cuda")
+    states = torch.as_tensor(scen["states"], dtype=torch.float64, device=dev)
+    kact = torch.as_tensor(scen["k_active"], dtype=torch.int32, device=dev)
+    ctrl = torch.empty((scen["N"], scen["S"], 3), dtype=torch.float64, device=dev)
+    cost = torch.empty(1 + scen["N"], dtype=torch.float64, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    wm = scen["wind_mean"]
+    step_id = int(scen["mpc_step"])
+
+    def one(info=False):
+        return smc.smc_mpc_step_dev(ctx, step_id, states, kact, wm, scen["H"], ctrl, cost,
+                                    status, want_info=info)
+
+    # one instrumented update: work count and per-kernel event timings
+    _, info0 = one(info=True)
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
+    # per-kernel timings over instrumented updates (event pairs on the stream
+    # the kernels run on)
+    infos = [one(info=True)[1] for _ in range(max(1, min(args.steps, 3)))]
+    torch.cuda.synchronize()
+    aircraft_steps = info0["aircraft_steps"]
+    value = aircraft_steps / (ms_step * 1e-3)
+
+    n_roll = sum(i["rollout_launches"] for i in infos)
+    ms_roll = sum(i["ms_rollout"] for i in infos) / n_roll
+    n_wind = sum(i["wind_launches"] for i in infos)
+    ms_wind = sum(i["ms_wind"] for i in infos) / n_wind
+    as_per_launch = aircraft_steps / info0["rollout_launches"]
+    N = scen["N"]
+    flops_launch = as_per_launch * rollout_flops_per_aircraft_step(N)
+    achieved = flops_launch / (ms_roll * 1e-3) / 1e12
+    fp64 = scen["precision"] == 0
+    peak = PEAK_FP64_VECTOR_TFLOPS if fp64 else PEAK_FP32_VECTOR_TFLOPS
+    roof = {"kernel": "k_rollout", "bound": "alu", "achieved": round(achieved, 3),
+            "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": traffic_for("kernels_rollout.hip", "bytes_per_launch", flops_launch),
+            "ms_per_launch": round(ms_roll, 4),
+            "aircraft_steps_per_launch": int(as_per_launch),
+            "flops_per_aircraft_step": rollout_flops_per_aircraft_step(N)}
+    G = int(np.prod(scen["grid"]))
+    gemm_flops = float(G) * (G + 1) * 2 * scen["M"]      # triangular factor x 2M columns
+    gemm_ach = gemm_flops / (ms_wind * 1e-3) / 1e12
+    gpeak = PEAK_FP64_MFMA_TFLOPS if fp64 else PEAK_FP32_MFMA_TFLOPS
+    wind_roof = {"kernel": "k_wind_gemm", "bound": "mfma", "achieved": round(gemm_ach, 3),
+                 "peak": gpeak, "unit": "TFLOP/s", "frac": round(gemm_ach / gpeak, 4),
+                 "ms_per_launch": round(ms_wind, 4)}
+
+    check = None
+    if not args.no_check:
+        # re-score the returned controls with the FP64 oracle on the last
+        # iteration's wind fields
+        from oracle import smc as osmc
+        one()
+        torch.cuda.synchronize()
+        c_ctrl = ctrl.cpu().numpy()
+        c_cost = cost.cpu().numpy()
+        u = (c_ctrl - scen["ctrl_lo"]) / (scen["ctrl_hi"] - scen["ctrl_lo"])
+        rc, rf = osmc.eval_cost(scen, u[None], scen["K"] - 1)
+        rel = abs(float(rc.sum()) - float(c_cost[0])) / max(abs(float(rc.sum())), 1e-3)
+        check = {"gpu_cost": float(c_cost[0]), "oracle_rescored_cost": float(rc.sum()),
+                 "rel_err": rel, "within_1e-3": bool(rel <= 1e-3),
+                 "oracle_feasible": bool(rf.all()), "status": int(status.cpu()[0])}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scen, args.cpu_particles)
+
+    out = {"metric": METRIC, "value": value, "unit": "aircraft-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if fp64 else "f32", "data": "synthetic",
+           "config": {"workload": f"{args.workload.upper()}: {desc}", "aircraft": N,
+                      "particles": scen["L"], "wind_samples": scen["M"],
+                      "smc_iterations": scen["K"], "horizon": scen["H"],
+                      "segments": scen["S"], "grid": [int(g) for g in scen["grid"]],
+                      "aircraft_steps_per_mpc_step": aircraft_steps},
+           "roofline": roof, "cpu_baseline": cpu, "wind_gemm_roofline": wind_roof,
+           "cost_check": check,
+           "step_info": {k: info0[k] for k in ("feasible_frac", "ess_min", "best_particle",
+                                              "ms_total")}}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

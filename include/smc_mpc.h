@@ -114,7 +114,8 @@ typedef struct {
     int32_t scenario_id;
 } smc_scenario;
 
-/* Diagnostics of one MPC update (optional output). */
+/* Diagnostics of one MPC update (optional output).  When requested, device
+ * events bracket the rollout and wind GEMM launches on the update's stream. */
 typedef struct {
     int32_t iterations;       /* weighting passes run (= n_iters)               */
     int32_t best_particle;    /* index of the returned particle                 */
@@ -123,6 +124,10 @@ typedef struct {
     double ess_min;           /* smallest per-aircraft ESS at the last pass     */
     int64_t aircraft_steps;   /* simulated aircraft-steps over all passes       */
     double ms_total;          /* wall time of the update, device events         */
+    double ms_rollout;        /* summed duration of the rollout launches        */
+    double ms_wind;           /* summed duration of the wind GEMM launches      */
+    int32_t rollout_launches; /* rollout launches in the update                 */
+    int32_t wind_launches;    /* wind GEMM launches in the update               */
 } smc_step_info;
 
 /* Create a context: validates the scenario, factors the wind covariance

@@ -211,8 +211,8 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
         viol = ((T > tmax) | (np.abs(phi) >= phi_max) | (np.abs(gamma) > gamma_max)
                 | (zn < zmin) | (zn > zmax) | (vn < vmin) | (vn > vmax)
                 | (mn < m_empty))
-        feas &= ~(present & viol)
-        if with_margins:
+        if with_margins:   # only decisions that can still change feasibility
+            relevant = present & feas
             mg = np.minimum.reduce([
                 np.abs(T - tmax) / tmax,
                 np.abs(np.abs(phi) - phi_max) / phi_max,
@@ -220,7 +220,8 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
                 np.abs(zn - zmin) / zmax, np.abs(zn - zmax) / zmax,
                 np.abs(vn - vmin) / vmax, np.abs(vn - vmax) / vmax,
                 np.abs(mn - m_empty) / m_empty])
-            margin = np.where(present, np.minimum(margin, mg), margin)
+            margin = np.where(relevant, np.minimum(margin, mg), margin)
+        feas &= ~(present & viol)
 
         x = np.where(present, xn, x)
         y = np.where(present, yn, y)
@@ -256,14 +257,14 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
                 A = dh2 < p_sep_h2
                 B = dz < p_sep_v
                 bad = both & A & B
-                feas[..., i] &= ~bad
-                feas[..., jj] &= ~bad
                 if with_margins:
                     mg = np.minimum(np.where(B, np.abs(dh2 / p_sep_h2 - 1.0), np.inf),
                                     np.where(A, np.abs(dz / p_sep_v - 1.0), np.inf))
-                    mg = np.where(both, mg, np.inf)
+                    mg = np.where(both & (feas[..., i] | feas[..., jj]), mg, np.inf)
                     margin[..., i] = np.minimum(margin[..., i], mg)
                     margin[..., jj] = np.minimum(margin[..., jj], mg)
+                feas[..., i] &= ~bad
+                feas[..., jj] &= ~bad
 
     w = scen["cost_w"]
     mix = 1.0 - w[7] - w[8]

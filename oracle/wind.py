@@ -21,29 +21,67 @@ Readings used here (listed with the others in the design notes):
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from . import philox
+
+
+def _nodes(lo, hi, n):
+    """n evenly spaced nodes lo + (hi - lo) a / (n - 1)."""
+    return np.array([lo + (hi - lo) * a / (n - 1) for a in range(n)])
 
 
 def grid_axes(box, grid_n):
     """Node coordinates: x, y in [-W/2, W/2], z in [0, Z_top], evenly spaced."""
     wx, wy, zt = (float(b) for b in box)
     nx, ny, nz = (int(n) for n in grid_n)
-    return (np.linspace(-wx / 2, wx / 2, nx), np.linspace(-wy / 2, wy / 2, ny),
-            np.linspace(0.0, zt, nz))
+    return (_nodes(-0.5 * wx, 0.5 * wx, nx), _nodes(-0.5 * wy, 0.5 * wy, ny),
+            _nodes(0.0, zt, nz))
 
 
 def se_gram(nodes, ell):
     """K[a, b] = exp(-(p_a - p_b)^2 / (2 ell^2))."""
-    d = nodes[:, None] - nodes[None, :]
-    return np.exp(-d * d / (2.0 * ell * ell))
+    n = len(nodes)
+    K = np.empty((n, n))
+    for a in range(n):
+        for b in range(n):
+            d = nodes[a] - nodes[b]
+            K[a, b] = math.exp(-d * d / (2.0 * ell * ell))
+    return K
+
+
+def cholesky_lower(K):
+    """Textbook (row by row) Cholesky factorisation K = L L^T, FP64.
+
+    The 1-D squared-exponential Gram matrices are nearly singular, so their
+    factors are sensitive to rounding; a fixed, explicit operation order
+    keeps this factor reproducible."""
+    n = K.shape[0]
+    L = np.zeros((n, n))
+    for j in range(n):
+        s = K[j, j]
+        for k in range(j):
+            s -= L[j, k] * L[j, k]
+        if not s > 0.0:
+            raise np.linalg.LinAlgError("matrix not positive definite")
+        d = math.sqrt(s)
+        L[j, j] = d
+        for i in range(j + 1, n):
+            t = K[i, j]
+            for k in range(j):
+                t -= L[i, k] * L[j, k]
+            L[i, j] = t / d
+    return L
 
 
 def axis_factor(nodes, ell, nugget):
     """Lower Cholesky factor of the 1-D Gram matrix plus the nugget."""
-    K = se_gram(nodes, ell) + nugget * np.eye(len(nodes))
-    return np.linalg.cholesky(K)
+    K = se_gram(nodes, ell)
+    for a in range(len(nodes)):
+        K[a, a] += nugget
+    return cholesky_lower(K)
 
 
 def kron_factor(box, grid_n, sigma, ell, nugget):

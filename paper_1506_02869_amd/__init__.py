@@ -60,7 +60,9 @@ class StepInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("best_particle", C.c_int32),
                 ("feasible_frac", C.c_double), ("accept_rate", C.c_double),
                 ("ess_min", C.c_double), ("aircraft_steps", C.c_int64),
-                ("ms_total", C.c_double)]
+                ("ms_total", C.c_double), ("ms_rollout", C.c_double),
+                ("ms_wind", C.c_double), ("rollout_launches", C.c_int32),
+                ("wind_launches", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

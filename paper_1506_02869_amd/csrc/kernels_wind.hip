@@ -22,17 +22,23 @@ __global__ void k_kron_expand(const double* __restrict__ Lx, const double* __res
 }
 
 template <typename T> struct Mfma;
+// Operands of both instructions: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16].  Result register r of lane l holds D[row][l % 16] with
+// row = 4 (l / 16) + r for f32 (groups of 4 consecutive rows) and
+// row = 4 r + l / 16 for f64 (4 groups of one row).
 template <> struct Mfma<float> {
     typedef float acc_t __attribute__((ext_vector_type(4)));
     static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 template <> struct Mfma<double> {
     typedef double acc_t __attribute__((ext_vector_type(4)));
     static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
 };
 
 // Block tile 32 (grid points) x 64 (columns), K stage 16; 4 waves as 2 x 2,
@@ -87,7 +93,7 @@ __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* 
     const int M = NC / 2;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int g = row0 + wr + 4 * (lane >> 4) + r;
+        const int g = row0 + wr + Mfma<T>::row(lane, r);
         if (g >= G) continue;
         const int c0 = col0 + wc + (lane & 15);
         const int c1 = c0 + 16;

@@ -43,6 +43,7 @@ struct smc_ctx {
 
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> ev_roll, ev_wind;  // pairs bracketing launches
     std::vector<DevBuf> bufs;
     std::string err;
 
@@ -269,27 +270,35 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     HIP_OK(c, launch_init_particles(c->prec, make_stream(c->seed, mpc_step, 0, P_INIT, c->scen_id),
                                     count, u, st));
     double acc_sum = 0.0;
-    int acc_n = 0;
+    int acc_n = 0, n_roll = 0, n_roll2 = 0;
     std::vector<int32_t> hflags;
     for (int J = 0; J < c->K; ++J) {
         const double beta = beta_of(c, J);
         HIP_OK(c, launch_wind_normals(c->prec, make_stream(c->seed, mpc_step, J, P_WIND, c->scen_id),
                                       c->G, c->M, c->d_Z, st));
+        if (info) HIP_OK(c, hipEventRecord(c->ev_wind[2 * J], st));
         HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G,
                                    c->M, c->d_W, st));
+        if (info) HIP_OK(c, hipEventRecord(c->ev_wind[2 * J + 1], st));
+        if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J], st));
         HIP_OK(c, launch_rollout(c->prec, rp,
                                  rollout_arrays(c, u, c->d_W, d_states, d_kact, c->d_cost,
                                                 c->d_feas, steps),
                                  st));
+        if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J + 1], st));
+        ++n_roll;
         HIP_OK(c, launch_reduce(L, c->M, N, c->d_cost, c->d_feas, beta, c->d_chat, c->d_feaspn,
                                 c->d_logw, st));
         if (c->move == SMC_MOVE_RWMH) {
             const Stream sm = make_stream(c->seed, mpc_step, J, P_MOVE, c->scen_id);
             HIP_OK(c, launch_propose(c->prec, count, u, c->d_up, sm, c->sigma_move, st));
+            if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J + 2], st));
             HIP_OK(c, launch_rollout(c->prec, rp,
                                      rollout_arrays(c, c->d_up, c->d_W, d_states, d_kact,
                                                     c->d_cost, c->d_feas, steps),
                                      st));
+            if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J + 3], st));
+            ++n_roll2;
             HIP_OK(c, launch_reduce(L, c->M, N, c->d_cost, c->d_feas, beta, c->d_chat2,
                                     c->d_feaspn2, c->d_logw2, st));
             HIP_OK(c, launch_accept(c->prec, L, N, D, u, c->d_up, c->d_chat, c->d_chat2,
@@ -352,6 +361,22 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     info->ess_min = *std::min_element(ess.begin(), ess.end());
     info->aircraft_steps = (int64_t)tot;
     info->ms_total = ms;
+    double ms_r = 0.0, ms_w = 0.0;
+    for (int J = 0; J < c->K; ++J) {
+        float t = 0.f;
+        HIP_OK(c, hipEventElapsedTime(&t, c->ev_wind[2 * J], c->ev_wind[2 * J + 1]));
+        ms_w += t;
+        HIP_OK(c, hipEventElapsedTime(&t, c->ev_roll[4 * J], c->ev_roll[4 * J + 1]));
+        ms_r += t;
+        if (J < n_roll2) {
+            HIP_OK(c, hipEventElapsedTime(&t, c->ev_roll[4 * J + 2], c->ev_roll[4 * J + 3]));
+            ms_r += t;
+        }
+    }
+    info->ms_rollout = ms_r;
+    info->ms_wind = ms_w;
+    info->rollout_launches = n_roll + n_roll2;
+    info->wind_launches = c->K;
     return best[1] ? SMC_INFEASIBLE : SMC_OK;
 }
 
@@ -369,6 +394,8 @@ void smc_destroy(smc_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto& b : c->bufs) (void)hipFree(b.p);
+    for (hipEvent_t e : c->ev_roll) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_wind) (void)hipEventDestroy(e);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -452,6 +479,14 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         fail(c, SMC_EDEVICE, "hipEventCreate failed");
         return bail(SMC_EDEVICE);
     }
+    c->ev_roll.assign((size_t)4 * c->K, nullptr);
+    c->ev_wind.assign((size_t)2 * c->K, nullptr);
+    for (auto* v : {&c->ev_roll, &c->ev_wind})
+        for (auto& e : *v)
+            if (hipEventCreate(&e) != hipSuccess) {
+                fail(c, SMC_EDEVICE, "hipEventCreate failed");
+                return bail(SMC_EDEVICE);
+            }
     const size_t N = c->N, L = c->L, M = c->M, G = c->G, D = (size_t)c->S * 3;
     double *d_Lx = nullptr, *d_Ly = nullptr, *d_Lz = nullptr;
     if ((st = dalloc_t(c, &c->d_acpar, N * SMC_AC_NPAR)) || (st = dalloc_t(c, &c->d_targets, N * 4)) ||

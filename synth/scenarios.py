@@ -90,7 +90,8 @@ def _arrival_states(rng, n, box, r_entry, min_sep, z_lo=3048.0, z_hi=4572.0,
         chi = math.atan2(-y, -x) + rng.uniform(-30.0, 30.0) * DEG
         m0 = rng.uniform(55_000.0, 70_000.0)
         placed.append((x, y, z, v0, chi, m0))
-    out[:] = np.array(placed)
+    if n:
+        out[:] = np.array(placed)
     return out
 
 

@@ -79,7 +79,8 @@ def test_wind_factor_matches_kronecker(lib):
     out = empty((ctx.G, ctx.G), ctx.real_dtype)
     lib.smc_k_wind_factor(ctx, out)
     ref = owind.kron_factor(s["box"], s["grid"], s["wind_sigma"], s["wind_ell"], s["wind_nugget"])
-    assert np.abs(host(out) - ref).max() < 1e-13 * s["wind_sigma"]
+    # same per-axis Cholesky operation order on both sides, products only
+    assert np.array_equal(host(out), ref)
 
 
 @pytest.mark.parametrize("prec,grid,M", [("fp64", (16, 16, 4), 16), ("fp64", (5, 7, 3), 3),
@@ -99,10 +100,12 @@ def test_wind_gemm(lib, prec, grid, M):
     W = empty((M, G, 2), ctx.real_dtype)
     lib.smc_k_wind_gemm(ctx, dev(Zr, ctx.real_dtype), wm, W)
     got = host(W).astype(np.float64)
-    # error bound: sum over G terms of |L||Z| times the unit roundoff
+    # rounding of a G-term dot product: |error| <~ u sqrt(G) sum|L||Z| for
+    # random-signed partial sums (u = unit roundoff), plus the rounding of
+    # the factor to FP32 (u sum|L||Z|) and of the output
     scale = (np.abs(Lf) @ np.abs(Zr)).max()
-    eps = 2.3e-16 if prec == "fp64" else 1.2e-7
-    assert np.abs(got - ref).max() <= 4 * eps * scale + (0 if prec == "fp64" else 1e-6)
+    u = 2.0 ** -53 if prec == "fp64" else 2.0 ** -24
+    assert np.abs(got - ref).max() <= 2 * u * scale * (2 + np.sqrt(G))
 
 
 # ---- rollout ---------------------------------------------------------------------
@@ -133,7 +136,8 @@ def _rollout_case(lib, s, P, seed=0, horizon=None, states=None, k_active=None, u
     return ctx, got_c, got_f, int(host(steps).sum()), ref
 
 
-def _compare_rollout(got_c, got_f, ref, prec, near=1e-4):
+def _compare_rollout(got_c, got_f, ref, prec, near=None):
+    near = (1e-9 if prec == 0 else 1e-4) if near is None else near
     margin = ref["margin"]
     # a world with any near-threshold decision may legitimately differ
     world_near = (margin < near).any(axis=2, keepdims=True) | (margin < near)
@@ -155,7 +159,7 @@ def test_rollout_c1_shape(lib, prec):
     assert n_near < 0.05 * 200 * s["M"]
     # per-particle expected cost (mean over samples)
     chat_ref, _ = osmc.expected_cost(ref["cost"], ref["feas"])
-    world_near = (ref["margin"] < 1e-4).any(axis=(1, 2))
+    world_near = (ref["margin"] < (1e-9 if prec == "fp64" else 1e-4)).any(axis=(1, 2))
     err = rel_err(gc.mean(axis=1), chat_ref)[~world_near]
     assert err.max() < (1e-12 if prec == "fp64" else 1e-5)
 
@@ -175,7 +179,8 @@ def test_rollout_c2_shape_ragged(lib, prec):
 def test_rollout_aircraft_counts(lib, N):
     """Worlds from 1 lane to a full wave; mixed kinds and activation steps."""
     rng = np.random.default_rng(N)
-    s = synth.make_scenario("T", n_arr=max(1, N // 2), n_dep=N - max(1, N // 2),
+    n_arr = min(max(1, N // 2), 12)
+    s = synth.make_scenario("T", n_arr=n_arr, n_dep=N - n_arr,
                             box=(100e3, 100e3, 8e3), grid=(6, 5, 4), H=30, dt=5.0, S=3,
                             M=3, L=8, K=2, precision="fp64", seed=N)
     k_act = s["k_active"].copy()
