@@ -30,16 +30,12 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
-# Algorithmic work of one aircraft-step of the rollout (elementary operations
-# of the oracle's per-step list, each transcendental counted once) and of
-# one pair test; see the design notes for the table.
-FLOPS_PER_AIRCRAFT_STEP = 174
-FLOPS_PER_PAIR_TEST = 9
-
-
-def rollout_flops_per_aircraft_step(N: int) -> float:
-    # each present aircraft-step carries (N - 1) / 2 pair tests
-    return FLOPS_PER_AIRCRAFT_STEP + FLOPS_PER_PAIR_TEST * (N - 1) / 2.0
+# Algorithmic work of the rollout: elementary operations of the oracle's
+# per-step list (each transcendental, square root or division counted once)
+# per simulated aircraft-step, and per separation test between two present
+# aircraft; the table is in the design notes.
+FLOPS_PER_AIRCRAFT_STEP = 170
+FLOPS_PER_PAIR_TEST = 10
 
 
 WORKLOADS = {
@@ -170,17 +166,23 @@ def main():
     n_wind = sum(i["wind_launches"] for i in infos)
     ms_wind = sum(i["ms_wind"] for i in infos) / n_wind
     as_per_launch = aircraft_steps / info0["rollout_launches"]
+    pt_per_launch = info0["pair_tests"] / info0["rollout_launches"]
     N = scen["N"]
-    flops_launch = as_per_launch * rollout_flops_per_aircraft_step(N)
+    flops_launch = (as_per_launch * FLOPS_PER_AIRCRAFT_STEP
+                    + pt_per_launch * FLOPS_PER_PAIR_TEST)
     achieved = flops_launch / (ms_roll * 1e-3) / 1e12
     fp64 = scen["precision"] == 0
     peak = PEAK_FP64_VECTOR_TFLOPS if fp64 else PEAK_FP32_VECTOR_TFLOPS
-    roof = {"kernel": "k_rollout", "bound": "alu", "achieved": round(achieved, 3),
+    wm = N <= 16     # the library picks the world-per-lane rollout up to 16 aircraft
+    kname, ksrc = (("k_rollout_wm", "kernels_rollout_wm.hip") if wm
+                   else ("k_rollout", "kernels_rollout.hip"))
+    roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 3),
             "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": traffic_for("kernels_rollout.hip", "bytes_per_launch", flops_launch),
+            "traffic": traffic_for(ksrc, "bytes_per_launch", flops_launch),
             "ms_per_launch": round(ms_roll, 4),
             "aircraft_steps_per_launch": int(as_per_launch),
-            "flops_per_aircraft_step": rollout_flops_per_aircraft_step(N)}
+            "pair_tests_per_launch": int(pt_per_launch),
+            "flops_per_launch": flops_launch}
     G = int(np.prod(scen["grid"]))
     gemm_flops = float(G) * (G + 1) * 2 * scen["M"]      # triangular factor x 2M columns
     gemm_ach = gemm_flops / (ms_wind * 1e-3) / 1e12

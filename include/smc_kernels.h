@@ -65,8 +65,9 @@ smc_status smc_k_wind_factor(smc_ctx* ctx, void* out, void* stream);
  * eq. hor; Sec. "Constraint Handling"; eq. TO_init; Sec. "Particle Costing";
  * eq. avoidance): cost[M][P][N] (double), feas[M][P][N] (uint8).
  * states[N][6] double and k_active[N] int32 are device arrays.
- * steps (device uint64[64], may be NULL): simulated aircraft-steps are
- * added, spread over the 64 slots. */
+ * steps (device uint64[128], may be NULL): simulated aircraft-steps are
+ * added to slots 0..63 and separation tests with both aircraft present to
+ * slots 64..127 (spread over the slots; sum each half). */
 smc_status smc_k_rollout(smc_ctx* ctx, const void* u, int32_t P, const void* W,
                          const double* states, const int32_t* k_active,
                          int32_t horizon, double* cost, uint8_t* feas,
@@ -126,6 +127,15 @@ smc_status smc_k_accept(smc_ctx* ctx, int32_t P, void* u, const void* u_prop,
 smc_status smc_k_select(smc_ctx* ctx, int32_t P, const double* logw,
                         const double* chat, double beta, int32_t* best,
                         void* stream);
+
+/* Rollout kernel layout used by every pass of this context:
+ *  0 automatic (world-per-lane for N <= 16, aircraft-per-lane above),
+ *  1 aircraft-per-lane: one lane per (particle, sample, aircraft), the world's
+ *    aircraft in consecutive lanes of a wavefront, positions exchanged in LDS;
+ *  2 world-per-lane: one lane per (particle, sample) holding all N aircraft
+ *    in registers (N <= 16).
+ * Both compute the same rollout; SMC_EINVAL for an unsupported choice. */
+smc_status smc_set_rollout_layout(smc_ctx* ctx, int32_t layout);
 
 #ifdef __cplusplus
 }

@@ -123,6 +123,7 @@ typedef struct {
     double accept_rate;       /* mean MH acceptance (0 for jitter)              */
     double ess_min;           /* smallest per-aircraft ESS at the last pass     */
     int64_t aircraft_steps;   /* simulated aircraft-steps over all passes       */
+    int64_t pair_tests;       /* separation tests with both aircraft present    */
     double ms_total;          /* wall time of the update, device events         */
     double ms_rollout;        /* summed duration of the rollout launches        */
     double ms_wind;           /* summed duration of the wind GEMM launches      */

@@ -145,7 +145,8 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
     [0, 1]) under wind fields ``W`` [M, G, 2].
 
     Returns dict with cost [L, M, N], feas [L, M, N] (bool), steps (number of
-    simulated aircraft-steps), and, if asked, margin [L, M, N]: the smallest
+    simulated aircraft-steps), pair_tests (separation tests with both aircraft
+    present), and, if asked, margin [L, M, N]: the smallest
     relative distance of any discrete decision (unary check, landing test,
     separation test) to its threshold; if ``record``, track [H+1, L, M, N, 6]
     (state after each step, frozen once an aircraft is absent) and present
@@ -176,6 +177,7 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
     margin = np.full(shape, np.inf)
     m_idx = np.arange(M)[None, :, None]
     steps = 0
+    pair_tests = 0
     p_sep_h2, p_sep_v = scen["sep_h"] ** 2, scen["sep_v"]
     track = [np.stack([x, y, z, v, chi, mass], axis=-1)] if record else None
     pres_log = [] if record else None
@@ -252,6 +254,7 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
         for i in range(N):
             for jj in range(i + 1, N):
                 both = present[..., i] & present[..., jj]
+                pair_tests += int(both.sum())
                 dh2 = (x[..., i] - x[..., jj]) ** 2 + (y[..., i] - y[..., jj]) ** 2
                 dz = np.abs(z[..., i] - z[..., jj])
                 A = dh2 < p_sep_h2
@@ -273,7 +276,7 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
     fuel_term = (m_act - mass) / denom
     cost = np.where(active, mix * a_fuel * fuel_term + acc / np.maximum(n_steps, 1),
                     0.0)
-    out = dict(cost=cost, feas=feas, steps=steps,
+    out = dict(cost=cost, feas=feas, steps=steps, pair_tests=pair_tests,
                final=np.stack([x, y, z, v, chi, mass], axis=-1))
     if with_margins:
         out["margin"] = margin

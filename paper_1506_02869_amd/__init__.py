@@ -60,6 +60,7 @@ class StepInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("best_particle", C.c_int32),
                 ("feasible_frac", C.c_double), ("accept_rate", C.c_double),
                 ("ess_min", C.c_double), ("aircraft_steps", C.c_int64),
+                ("pair_tests", C.c_int64),
                 ("ms_total", C.c_double), ("ms_rollout", C.c_double),
                 ("ms_wind", C.c_double), ("rollout_launches", C.c_int32),
                 ("wind_launches", C.c_int32)]
@@ -97,6 +98,7 @@ _SIGS = {
     "smc_k_accept": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                C.c_int64, C.c_int32, _VP, _VP]),
     "smc_k_select": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, _VP, _VP]),
+    "smc_set_rollout_layout": (C.c_int, [_VP, C.c_int32]),
 }
 
 _lib = None
@@ -364,3 +366,8 @@ def smc_k_accept(ctx, P, u, u_prop, chat, chat_prop, feas_pn, feas_prop, logw, l
 def smc_k_select(ctx, P, logw, chat, beta, best, stream=None):
     _check(lib().smc_k_select(ctx.handle, int(P), _ptr(logw), _ptr(chat), float(beta),
                               _ptr(best), _stream(stream)), ctx)
+
+
+def smc_set_rollout_layout(ctx, layout):
+    """0 automatic, 1 aircraft-per-lane, 2 world-per-lane."""
+    _check(lib().smc_set_rollout_layout(ctx.handle, int(layout)), ctx)

@@ -10,6 +10,8 @@ namespace smc {
 
 constexpr int kMaxAircraft = 64;
 constexpr int kStepSlots = 64;   // striped counters of simulated aircraft-steps
+constexpr int kWorldLaneMaxN = 16;  // largest N of the world-per-lane rollout
+constexpr int kAcR = 16;            // per-aircraft parameters in the rollout's precision
 
 // Scalars of one rollout launch (uniform over the grid; kernel argument).
 struct RolloutParams {
@@ -38,7 +40,7 @@ struct RolloutArrays {
     const float* pop;         // [pop_ny][pop_nx] or null
     double* cost;             // [M][P][N]
     uint8_t* feas;            // [M][P][N]
-    unsigned long long* steps;  // [kStepSlots] or null
+    unsigned long long* steps;  // [2 kStepSlots] or null: aircraft-steps, pair tests
 };
 
 // precision: 0 = double, 1 = float
@@ -56,6 +58,12 @@ hipError_t launch_wind_gemm(int prec, const void* Lfac, const void* Z,
                             hipStream_t st);
 hipError_t launch_rollout(int prec, const RolloutParams& p,
                           const RolloutArrays& a, hipStream_t st);
+bool rollout_wm_supported(int N);
+// acR: [N][kAcR] real: wing area, C_D0, C_D2, C_f1, 1/C_f2, T_max, empty
+// mass, tan(phi_max), sin(gamma_max), theta_F, Z, v_D, D_TMA, 1/speed span,
+// kind (0 arrival, 1 departure), 0
+hipError_t launch_rollout_wm(int prec, const RolloutParams& p, const RolloutArrays& a,
+                             const void* acR, hipStream_t st);
 hipError_t launch_reduce(int P, int M, int N, const double* cost,
                          const uint8_t* feas, double beta, double* chat,
                          uint8_t* feas_pn, double* logw, hipStream_t st);

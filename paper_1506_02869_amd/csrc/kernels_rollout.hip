@@ -16,39 +16,13 @@
 // i+1 .. i+(N-1)/2 modulo N, plus i+N/2 for i < N/2 when N is even); a hit
 // sets the bits of both aircraft in a per-lane violation mask that is
 // OR-reduced over the world once, after the last step.
-#include "engine.h"
+#include "rollout_math.h"
 
 namespace smc {
 
-template <typename R> struct V2;
-template <> struct V2<float> { typedef float2 t; };
-template <> struct V2<double> { typedef double2 t; };
-template <typename R> struct V4;
-template <> struct V4<float> { typedef float4 t; };
-template <> struct V4<double> { typedef double4 t; };
-
-constexpr double kG0 = 9.80665;
-constexpr double kRho0 = 1.225, kT0 = 288.15, kLapse = 0.0065, kRair = 287.05287;
-
 template <typename R>
-__device__ __forceinline__ R wrap_angle(R a) {
-    return a - Consts<R>::two_pi * m_floor((a + Consts<R>::pi) * Consts<R>::inv_two_pi);
-}
-
-template <typename R>
-__device__ __forceinline__ R clampr(R v, R lo, R hi) { return m_min(m_max(v, lo), hi); }
-
-// Kahan-compensated accumulation.
-template <typename R>
-__device__ __forceinline__ void kahan_add(R& sum, R& comp, R x) {
-    const R y = x - comp;
-    const R t = sum + y;
-    comp = (t - sum) - y;
-    sum = t;
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_rollout(const RolloutParams p, const RolloutArrays a) {
+__global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1)
+k_rollout(const RolloutParams p, const RolloutArrays a) {
     typedef typename V2<R>::t R2;
     typedef typename V4<R>::t R4;
     __shared__ R4 pos[4][2][64];
@@ -69,14 +43,15 @@ __global__ void __launch_bounds__(256) k_rollout(const RolloutParams p, const Ro
 
     // per-aircraft constants
     const double* ac = a.acpar + i * 9;
-    const R Sw = (R)ac[0], cd0 = (R)ac[1], cd2 = (R)ac[2], cf1 = (R)ac[3], cf2 = (R)ac[4];
+    const R Sw = (R)ac[0], cd0 = (R)ac[1], cd2 = (R)ac[2], cf1 = (R)ac[3];
     const R tmax = (R)ac[5], m_empty = (R)ac[6];
     const R tan_phimax = (R)tan(ac[7]);
     const R sin_gmax = (R)sin(ac[8]);
     const bool is_arr = a.kind[i] == 0;
     const double* tg = a.targets + i * 4;
     const R thF = (R)tg[0], Zt = (R)tg[1], vD = (R)tg[2], dtma = (R)tg[3];
-    const R spd_den = (R)fmax(p.vmax - tg[2], tg[2] - p.vmin);
+    const R inv_spd_den = (R)(1.0 / fmax(p.vmax - tg[2], tg[2] - p.vmin));
+    const R inv_cf2 = (R)(1.0 / ac[4]);
     const int k0 = a.k_active[i];
     const bool active = valid && k0 >= 0 && k0 < H;
     const double* st = a.states + i * 6;
@@ -85,7 +60,7 @@ __global__ void __launch_bounds__(256) k_rollout(const RolloutParams p, const Ro
     const R d0 = m_abs(Zt - (R)st[2]);
 
     // uniform scalars
-    const R dt = (R)p.dt, g0 = (R)kG0, inv_g = (R)(1.0 / kG0);
+    const R dt = (R)p.dt, inv_dt = (R)(1.0 / p.dt), g0 = (R)kG0, inv_g = (R)(1.0 / kG0);
     const R half_wx = (R)p.half_wx, half_wy = (R)p.half_wy;
     const R inv_hx = (R)p.inv_hx, inv_hy = (R)p.inv_hy, inv_hz = (R)p.inv_hz;
     const R fnx1 = (R)(p.nx - 1), fny1 = (R)(p.ny - 1), fnz1 = (R)(p.nz - 1);
@@ -110,9 +85,10 @@ __global__ void __launch_bounds__(256) k_rollout(const RolloutParams p, const Ro
     R burn = 0, burn_c = 0, acc = 0, acc_c = 0;
     bool feas_unary = true, done = false;
     unsigned long long vmask = 0ull;
-    int nsim = 0;
+    int nsim = 0, npair = 0;
     R chidot = 0, vc = 0, zdot = 0;
     int s_cur = -1, k_end = 0;
+    R inv_rem = 0;
 
     for (int k = 0; k < H; ++k) {
         const int s = (k * S) / H;
@@ -123,6 +99,8 @@ __global__ void __launch_bounds__(256) k_rollout(const RolloutParams p, const Ro
             zdot = (R)p.ctrl_lo[2] + ubase[s * 3 + 2] * (R)p.ctrl_span[2];
             k_end = ((s + 1) * H + S - 1) / S;
         }
+        // airspeed ramps to vc by the segment's end: 1 / (steps remaining)
+        inv_rem = Ops<R>::rcp((R)(k_end - k));
         const bool present = active && k >= k0 && !done;
 
         // trilinear wind at the current position (coordinates clamped)
@@ -149,22 +127,24 @@ __global__ void __launch_bounds__(256) k_rollout(const RolloutParams p, const Ro
         }
 
         // climb angle, bank, aerodynamics, thrust, fuel
-        const R sg = zdot / v;
-        const R cg = m_sqrt((R)1 - sg * sg);
+        typedef Ops<R> O;
+        const R inv_v = O::rcp(v);
+        const R sg = zdot * inv_v;
+        const R cg = O::sqrt((R)1 - sg * sg);
         const R tphi = v * chidot * inv_g;
-        const R inv_cphi = m_sqrt((R)1 + tphi * tphi);
+        const R inv_cphi = O::sqrt((R)1 + tphi * tphi);
         const R zc = clampr(z, (R)0, (R)11000);
-        const R rho = rho0 * m_exp(isa_e * m_log((R)1 - isa_c * zc));
+        const R rho = rho0 * O::pow_pos((R)1 - isa_c * zc, isa_e);
         const R qd = (R)0.5 * rho * v * v;
         const R mass = m0 - burn;
-        const R CL = mass * g0 * inv_cphi / (qd * Sw);
+        const R CL = O::div(mass * g0 * inv_cphi, qd * Sw);
         const R D = qd * Sw * (cd0 + cd2 * CL * CL);
-        const R vn = v + (vc - v) / (R)(k_end - k);
-        const R T = mass * (vn - v) / dt + D + mass * g0 * sg;
-        const R eta = cf1 * ((R)1 + v / cf2);
+        const R vn = v + (vc - v) * inv_rem;
+        const R T = mass * (vn - v) * inv_dt + D + mass * g0 * sg;
+        const R eta = cf1 * ((R)1 + v * inv_cf2);
         const R fuel = dt * eta * m_max(T, (R)0);
         R sc, cc;
-        m_sincos(chi, &sc, &cc);
+        O::sincos(chi, &sc, &cc);
         const R xn = x + dt * (v * cc * cg + w.x);
         const R yn = y + dt * (v * sc * cg + w.y);
         const R zn = z + dt * (v * sg);
@@ -182,34 +162,36 @@ __global__ void __launch_bounds__(256) k_rollout(const RolloutParams p, const Ro
             ++nsim;
         }
 
-        // geometry at the new state (shared by landing test and cost)
-        const R r = m_sqrt(x * x + y * y);
-        const R theta = m_atan2(y, x);
+        // geometry at the new state, shared by the landing test and the cost
+        // elements of both kinds (one wrap, one time-to-go)
+        const R r = O::sqrt(x * x + y * y);
+        const R theta = O::atan2(y, x);
         const R tha = m_abs(theta);
-        const R ratio = tha > (R)1e-4 ? tha / m_max(m_sin(tha), (R)1e-6)
+        const R ratio = tha > (R)1e-4 ? tha * O::rcp(m_max(O::sin(tha), (R)1e-6))
                                       : (R)1 + tha * tha * (R)(1.0 / 6.0);
         const R s_arc = r * ratio;
-        const R vv = m_max(v, vmin);
+        const R inv_vv = O::rcp(m_max(v, vmin));
+        // arrivals: heading off the flow field chi_hat = pi + 2 theta;
+        // departures: bearing off the target bearing
+        const R ang = is_arr ? chi - (Consts<R>::pi + (R)2 * theta) : theta - thF;
+        const R e_ang = m_abs(wrap_angle<R>(ang)) * (R)(1.0 / Consts<double>::pi);
+        const R tnum = is_arr ? s_arc : m_max(dtma - r, (R)0);
+        const R tt = m_min(tnum * inv_vv * inv_tnorm, (R)1);
         R c;
         bool landed = false;
         if (is_arr) {
-            const R beta = m_atan2(z, s_arc);
+            const R beta = O::atan2(z, s_arc);
             landed = present && r <= p_run && beta <= p_beta && tha <= p_chi &&
                      m_abs(wrap_angle<R>(chi - Consts<R>::pi)) <= p_chi && v <= p_vs;
-            const R hdg = m_abs(wrap_angle<R>(chi - (Consts<R>::pi + (R)2 * theta))) *
-                          (R)(1.0 / Consts<double>::pi);
             const R glide = m_abs(beta - beta_f) * (R)(1.0 / Consts<double>::half_pi);
-            const R tt = m_min(s_arc / vv * inv_tnorm, (R)1);
-            c = mix * (w_hdg * hdg + w_gl * glide) + a_time * tt;
+            c = mix * (w_hdg * e_ang + w_gl * glide) + a_time * tt;
         } else {
-            const R brg = m_abs(wrap_angle<R>(theta - thF)) * (R)(1.0 / Consts<double>::pi);
             const R span = zdm_dt * (R)max(k + 1 - k0, 1);
             const R sup = d0 + span;
             const R inf = m_max(d0 - span, (R)0);
-            const R alt = clampr((m_abs(Zt - z) - inf) / (sup - inf), (R)0, (R)1);
-            const R spd = m_abs(v - vD) / spd_den;
-            const R tt = m_min(m_max(dtma - r, (R)0) / vv * inv_tnorm, (R)1);
-            c = mix * (w_brg * brg + w_alt * alt + w_spd * spd) + a_time * tt;
+            const R alt = clampr(O::div(m_abs(Zt - z) - inf, sup - inf), (R)0, (R)1);
+            const R spd = m_abs(v - vD) * inv_spd_den;
+            c = mix * (w_brg * e_ang + w_alt * alt + w_spd * spd) + a_time * tt;
         }
         if (p.use_noise) {
             R fpx = clampr((x + half_wx) * (R)p.pop_inv_hx, (R)0, (R)(p.pop_nx - 1));
@@ -232,7 +214,7 @@ __global__ void __launch_bounds__(256) k_rollout(const RolloutParams p, const Ro
         const R py_ = present ? y : (R)0;
         const R pz_ = present ? z : (R)0;
         R4 me;
-        me.x = px_; me.y = py_; me.z = pz_; me.w = (R)0;
+        me.x = px_; me.y = py_; me.z = pz_; me.w = present ? (R)1 : (R)0;
         pos[wv][buf][lane] = me;
         wave_sync();
         if (valid) {
@@ -241,6 +223,7 @@ __global__ void __launch_bounds__(256) k_rollout(const RolloutParams p, const Ro
                 int j = i + d;
                 if (j >= N) j -= N;
                 const R4 q = pos[wv][buf][base + j];
+                npair += (present && q.w != (R)0) ? 1 : 0;
                 const R dx = px_ - q.x, dy = py_ - q.y, dz = pz_ - q.z;
                 if (dx * dx + dy * dy < sep_h2 && m_abs(dz) < sep_v)
                     vmask |= (1ull << i) | (1ull << j);
@@ -248,6 +231,7 @@ __global__ void __launch_bounds__(256) k_rollout(const RolloutParams p, const Ro
             if (((N & 1) == 0) && i < (N >> 1)) {
                 const int j = i + (N >> 1);
                 const R4 q = pos[wv][buf][base + j];
+                npair += (present && q.w != (R)0) ? 1 : 0;
                 const R dx = px_ - q.x, dy = py_ - q.y, dz = pz_ - q.z;
                 if (dx * dx + dy * dy < sep_h2 && m_abs(dz) < sep_v)
                     vmask |= (1ull << i) | (1ull << j);
@@ -282,9 +266,17 @@ __global__ void __launch_bounds__(256) k_rollout(const RolloutParams p, const Ro
 
     if (a.steps) {
         int cnt = valid ? nsim : 0;
-        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
-        if (lane == 0 && cnt)
-            atomicAdd(&a.steps[blockIdx.x & (kStepSlots - 1)], (unsigned long long)cnt);
+        int cp = valid ? npair : 0;
+        for (int off = 32; off > 0; off >>= 1) {
+            cnt += __shfl_xor(cnt, off);
+            cp += __shfl_xor(cp, off);
+        }
+        if (lane == 0) {
+            if (cnt) atomicAdd(&a.steps[blockIdx.x & (kStepSlots - 1)], (unsigned long long)cnt);
+            if (cp)
+                atomicAdd(&a.steps[kStepSlots + (blockIdx.x & (kStepSlots - 1))],
+                          (unsigned long long)cp);
+        }
     }
 }
 

@@ -41,13 +41,83 @@ template <> struct Mfma<double> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
 };
 
-// Block tile 32 (grid points) x 64 (columns), K stage 16; 4 waves as 2 x 2,
+// Block tile 32 (grid points) x 64 (columns), K stage 32; 4 waves as 2 x 2,
 // each wave 16 x 32 = two 16x16 MFMA tiles.  The factor is lower triangular,
-// so row block rb only needs k < (rb + 1) * 32.  Work is balanced by letting
-// each workgroup take row blocks rb and R - 1 - rb.
-constexpr int GB_M = 32, GB_N = 64, GB_K = 16;
-constexpr int GA_LD = GB_K + 1;      // LDS row pitch of the A tile (bank spread)
-constexpr int GBB_LD = GB_N + 16;    // LDS row pitch of the B tile
+// so row block rb only needs k < (rb + 1) * 32; each workgroup takes row
+// blocks R - 1 - rb and rb so that all workgroups do the same work.
+// Stages are double-buffered in LDS with the next stage's global loads in
+// flight in registers while the current one feeds the MFMAs (one barrier per
+// stage).  LDS tiles are k-major: As[k][row], Bs[k][col], so the fragment
+// reads A[l % 16][l / 16] and B[l / 16][l % 16] of the 64 lanes hit
+// consecutive addresses.
+constexpr int GB_M = 32, GB_N = 64, GB_K = 32;
+constexpr int GA_LD = GB_M + 4;
+constexpr int GBB_LD = GB_N + 4;
+
+template <typename T>
+struct GemmStage {
+    T a[4];      // A[row][k4 .. k4+3] of this thread
+    T b[2][4];   // B[k][c4 .. c4+3], two chunks
+};
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef float4 t; };
+template <> struct Vec4<double> { typedef double4 t; };
+
+// Four consecutive elements; one vector load when they are in bounds and the
+// offset is a multiple of 4 elements (row pitch divisible by 4).
+template <typename T>
+__device__ __forceinline__ void load4(const T* __restrict__ src, int64_t off, bool full,
+                                      int nvalid, T (&out)[4]) {
+    if (full && (off & 3) == 0) {
+        const typename Vec4<T>::t v = *reinterpret_cast<const typename Vec4<T>::t*>(src + off);
+        out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    } else if (full) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[e] = src[off + e];
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[e] = e < nvalid ? src[off + e] : (T)0;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void gemm_fetch(const T* __restrict__ A, const T* __restrict__ Z,
+                                           int G, int NC, int row0, int col0, int k0,
+                                           GemmStage<T>& st) {
+    const int tid = threadIdx.x;
+    {   // A: 32 rows x 32 k, one 4-vector per thread
+        const int r = tid >> 3, kq = (tid & 7) * 4;
+        const int gr = row0 + r, gk = k0 + kq;
+        const bool ok = gr < G && gk < G;
+        load4(A, (int64_t)gr * G + gk, ok && gk + 4 <= G, ok ? G - gk : 0, st.a);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {   // B: 32 k x 64 cols, two 4-vectors per thread
+        const int e = tid + h * 256;
+        const int r = e >> 4, cq = (e & 15) * 4;
+        const int gk = k0 + r, gc = col0 + cq;
+        const bool ok = gk < G && gc < NC;
+        load4(Z, (int64_t)gk * NC + gc, ok && gc + 4 <= NC, ok ? NC - gc : 0, st.b[h]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void gemm_store(const GemmStage<T>& st, T* As, T* Bs) {
+    const int tid = threadIdx.x;
+    {
+        const int r = tid >> 3, kq = (tid & 7) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) As[(kq + e) * GA_LD + r] = st.a[e];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e0 = tid + h * 256;
+        const int r = e0 >> 4, cq = (e0 & 15) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Bs[r * GBB_LD + cq + e] = st.b[h][e];
+    }
+}
 
 template <typename T>
 __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* __restrict__ Z,
@@ -62,35 +132,32 @@ __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* 
     const int row0 = rb * GB_M;
     const int col0 = cb * GB_N;
     const int kmax = min(G, row0 + GB_M);
+    const int nst = (kmax + GB_K - 1) / GB_K;
     acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 
-    for (int k0 = 0; k0 < kmax; k0 += GB_K) {
-        // A tile: 32 x 16 (2 per thread)
-        for (int e = tid; e < GB_M * GB_K; e += 256) {
-            const int r = e / GB_K, c = e % GB_K;
-            const int gr = row0 + r, gc = k0 + c;
-            As[r * GA_LD + c] = (gr < G && gc < G) ? A[(int64_t)gr * G + gc] : (T)0;
-        }
-        // B tile: 16 x 64 (4 per thread)
-        for (int e = tid; e < GB_K * GB_N; e += 256) {
-            const int r = e / GB_N, c = e % GB_N;
-            const int gr = k0 + r, gc = col0 + c;
-            Bs[r * GBB_LD + c] = (gr < G && gc < NC) ? Z[(int64_t)gr * NC + gc] : (T)0;
-        }
-        __syncthreads();
+    GemmStage<T> st;
+    gemm_fetch<T>(A, Z, G, NC, row0, col0, 0, st);
+    gemm_store<T>(st, As, Bs);
+    __syncthreads();
+    for (int s = 0; s < nst; ++s) {
+        const int cur = s & 1;
+        const T* Ac = As + cur * (GB_K * GA_LD);
+        const T* Bc = Bs + cur * (GB_K * GBB_LD);
+        if (s + 1 < nst) gemm_fetch<T>(A, Z, G, NC, row0, col0, (s + 1) * GB_K, st);
 #pragma unroll
         for (int kk = 0; kk < GB_K; kk += 4) {
             const int kr = kk + (lane >> 4);
-            const T a = As[(wr + (lane & 15)) * GA_LD + kr];
-            const T b0 = Bs[kr * GBB_LD + wc + (lane & 15)];
-            const T b1 = Bs[kr * GBB_LD + wc + 16 + (lane & 15)];
+            const T a = Ac[kr * GA_LD + wr + (lane & 15)];
+            const T b0 = Bc[kr * GBB_LD + wc + (lane & 15)];
+            const T b1 = Bc[kr * GBB_LD + wc + 16 + (lane & 15)];
             acc0 = Mfma<T>::op(a, b0, acc0);
             acc1 = Mfma<T>::op(a, b1, acc1);
         }
+        if (s + 1 < nst) gemm_store<T>(st, As + (cur ^ 1) * (GB_K * GA_LD),
+                                       Bs + (cur ^ 1) * (GB_K * GBB_LD));
         __syncthreads();
     }
     // epilogue: element (g, col) -> W[m][g][c] with col = 2 m + c
-    const int M = NC / 2;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int g = row0 + wr + Mfma<T>::row(lane, r);
@@ -106,22 +173,23 @@ __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* 
             W[((int64_t)m * G + g) * 2 + c] = (T)((c ? wm1 : wm0) + (double)acc1[r]);
         }
     }
-    (void)M;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_wind_gemm(const T* __restrict__ A,
                                                    const T* __restrict__ Z, int G, int NC,
                                                    double wm0, double wm1, T* __restrict__ W) {
-    __shared__ T As[GB_M * GA_LD];
-    __shared__ T Bs[GB_K * GBB_LD];
+    __shared__ T As[2 * GB_K * GA_LD];
+    __shared__ T Bs[2 * GB_K * GBB_LD];
     const int R = (G + GB_M - 1) / GB_M;
     const int rb = blockIdx.x;
     const int rb2 = R - 1 - rb;
     const int cb = blockIdx.y;
-    // heavy (bottom) block first
-    gemm_rowblock<T>(A, Z, G, NC, rb2, cb, wm0, wm1, W, As, Bs);
-    if (rb2 != rb) gemm_rowblock<T>(A, Z, G, NC, rb, cb, wm0, wm1, W, As, Bs);
+    gemm_rowblock<T>(A, Z, G, NC, rb2, cb, wm0, wm1, W, As, Bs);   // heavy block first
+    if (rb2 != rb) {
+        __syncthreads();
+        gemm_rowblock<T>(A, Z, G, NC, rb, cb, wm0, wm1, W, As, Bs);
+    }
 }
 
 hipError_t launch_kron_expand(int prec, const double* Lx, const double* Ly,

@@ -49,6 +49,8 @@ struct smc_ctx {
 
     // device buffers
     double *d_acpar = nullptr, *d_targets = nullptr;
+    void* d_acR = nullptr;       // [N][kAcR] per-aircraft parameters, real
+    int layout = 0;              // rollout layout: 0 auto, 1 aircraft/lane, 2 world/lane
     int8_t* d_kind = nullptr;
     float* d_pop = nullptr;
     void* d_Lfac = nullptr;
@@ -240,6 +242,15 @@ RolloutArrays rollout_arrays(smc_ctx* c, const void* u, const void* W, const dou
     return a;
 }
 
+// The rollout launch behind every pass: world-per-lane when N allows it
+// (or when asked), aircraft-per-lane otherwise.
+hipError_t do_rollout(smc_ctx* c, const RolloutParams& rp, const RolloutArrays& a,
+                      hipStream_t st) {
+    const bool wm = c->layout == 2 || (c->layout == 0 && rollout_wm_supported(c->N));
+    if (wm) return launch_rollout_wm(c->prec, rp, a, c->d_acR, st);
+    return launch_rollout(c->prec, rp, a, st);
+}
+
 smc_status check_horizon(smc_ctx* c, int32_t horizon) {
     if (horizon < 1 || horizon > c->Hmax)
         return fail(c, SMC_EINVAL, "horizon %d outside [1, %d]", horizon, c->Hmax);
@@ -262,7 +273,7 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     rp.P = L;
     unsigned long long* steps = info ? c->d_steps : nullptr;
     if (info) {
-        HIP_OK(c, hipMemsetAsync(c->d_steps, 0, sizeof(unsigned long long) * kStepSlots, st));
+        HIP_OK(c, hipMemsetAsync(c->d_steps, 0, sizeof(unsigned long long) * 2 * kStepSlots, st));
         HIP_OK(c, hipEventRecord(c->ev0, st));
     }
     void* u = c->d_u;
@@ -281,7 +292,7 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
                                    c->M, c->d_W, st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_wind[2 * J + 1], st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J], st));
-        HIP_OK(c, launch_rollout(c->prec, rp,
+        HIP_OK(c, do_rollout(c, rp,
                                  rollout_arrays(c, u, c->d_W, d_states, d_kact, c->d_cost,
                                                 c->d_feas, steps),
                                  st));
@@ -293,7 +304,7 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
             const Stream sm = make_stream(c->seed, mpc_step, J, P_MOVE, c->scen_id);
             HIP_OK(c, launch_propose(c->prec, count, u, c->d_up, sm, c->sigma_move, st));
             if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J + 2], st));
-            HIP_OK(c, launch_rollout(c->prec, rp,
+            HIP_OK(c, do_rollout(c, rp,
                                      rollout_arrays(c, c->d_up, c->d_W, d_states, d_kact,
                                                     c->d_cost, c->d_feas, steps),
                                      st));
@@ -338,8 +349,8 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     HIP_OK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     int32_t best[2];
     HIP_OK(c, hipMemcpy(best, c->d_best, sizeof best, hipMemcpyDeviceToHost));
-    std::vector<unsigned long long> cnt(kStepSlots);
-    HIP_OK(c, hipMemcpy(cnt.data(), c->d_steps, sizeof(unsigned long long) * kStepSlots,
+    std::vector<unsigned long long> cnt(2 * kStepSlots);
+    HIP_OK(c, hipMemcpy(cnt.data(), c->d_steps, sizeof(unsigned long long) * 2 * kStepSlots,
                         hipMemcpyDeviceToHost));
     std::vector<uint8_t> fe((size_t)L * N);
     HIP_OK(c, hipMemcpy(fe.data(), c->d_feaspn, fe.size(), hipMemcpyDeviceToHost));
@@ -352,14 +363,15 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     HIP_OK(c, hipStreamSynchronize(st));
     long nf = 0;
     for (uint8_t f : fe) nf += f;
-    unsigned long long tot = 0;
-    for (auto v : cnt) tot += v;
+    unsigned long long tot = 0, totp = 0;
+    for (int q = 0; q < kStepSlots; ++q) { tot += cnt[q]; totp += cnt[kStepSlots + q]; }
     info->iterations = c->K;
     info->best_particle = best[0];
     info->feasible_frac = (double)nf / (double)fe.size();
     info->accept_rate = acc_n ? acc_sum / acc_n : 0.0;
     info->ess_min = *std::min_element(ess.begin(), ess.end());
     info->aircraft_steps = (int64_t)tot;
+    info->pair_tests = (int64_t)totp;
     info->ms_total = ms;
     double ms_r = 0.0, ms_w = 0.0;
     for (int J = 0; J < c->K; ++J) {
@@ -502,12 +514,13 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         (st = dalloc_t(c, &c->d_anc, N * L)) || (st = dalloc_t(c, &c->d_U, N)) ||
         (st = dalloc_t(c, &c->d_scan, N * L)) || (st = dalloc_t(c, &c->d_ess, N)) ||
         (st = dalloc_t(c, &c->d_flags, L)) || (st = dalloc_t(c, &c->d_best, 2)) ||
-        (st = dalloc_t(c, &c->d_status, 1)) || (st = dalloc_t(c, &c->d_steps, kStepSlots)) ||
+        (st = dalloc_t(c, &c->d_status, 1)) || (st = dalloc_t(c, &c->d_steps, 2 * kStepSlots)) ||
         (st = dalloc_t(c, &c->d_states, N * 6)) || (st = dalloc_t(c, &c->d_kact, N)) ||
         (st = dalloc_t(c, &c->d_ctrl_out, N * D)) || (st = dalloc_t(c, &c->d_cost_out, 1 + N)) ||
         (st = dalloc_t(c, &d_Lx, (size_t)c->nx * c->nx)) || (st = dalloc_t(c, &d_Ly, (size_t)c->ny * c->ny)) ||
         (st = dalloc_t(c, &d_Lz, (size_t)c->nz * c->nz)))
         return bail(st);
+    if ((st = dalloc(c, &c->d_acR, N * kAcR * c->rsz))) return bail(st);
     if (c->use_noise || s->popdense) {
         if ((st = dalloc_t(c, &c->d_pop, (size_t)c->pop_nx * c->pop_ny))) return bail(st);
     }
@@ -522,6 +535,25 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     INIT_HIP(hipMemcpy(c->d_acpar, s->aircraft, N * SMC_AC_NPAR * sizeof(double), hipMemcpyHostToDevice));
     INIT_HIP(hipMemcpy(c->d_targets, s->targets, N * 4 * sizeof(double), hipMemcpyHostToDevice));
     INIT_HIP(hipMemcpy(c->d_kind, s->kind, N, hipMemcpyHostToDevice));
+    {
+        std::vector<double> t(N * kAcR, 0.0);
+        for (size_t i = 0; i < N; ++i) {
+            const double* a = s->aircraft + i * SMC_AC_NPAR;
+            const double* g = s->targets + i * 4;
+            double* o = t.data() + i * kAcR;
+            o[0] = a[0]; o[1] = a[1]; o[2] = a[2]; o[3] = a[3]; o[4] = 1.0 / a[4];
+            o[5] = a[5]; o[6] = a[6]; o[7] = std::tan(a[7]); o[8] = std::sin(a[8]);
+            o[9] = g[0]; o[10] = g[1]; o[11] = g[2]; o[12] = g[3];
+            o[13] = 1.0 / std::max(s->env[3] - g[2], g[2] - s->env[2]);
+            o[14] = s->kind[i] == SMC_ARRIVAL ? 0.0 : 1.0;
+        }
+        if (c->prec == SMC_FP64) {
+            INIT_HIP(hipMemcpy(c->d_acR, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> f(t.begin(), t.end());
+            INIT_HIP(hipMemcpy(c->d_acR, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
+    }
     if (c->d_pop)
         INIT_HIP(hipMemcpy(c->d_pop, s->popdense, (size_t)c->pop_nx * c->pop_ny * sizeof(float),
                            hipMemcpyHostToDevice));
@@ -603,7 +635,7 @@ smc_status smc_eval_cost(smc_ctx* c, int64_t mpc_step, int32_t iter, const doubl
     RolloutParams rp = c->rp;
     rp.H = horizon;
     rp.P = P;
-    HIP_OK(c, launch_rollout(c->prec, rp,
+    HIP_OK(c, do_rollout(c, rp,
                              rollout_arrays(c, c->d_ueval, c->d_W, c->d_states, c->d_kact, c->d_ecost,
                                             c->d_efeas, nullptr),
                              st));
@@ -667,7 +699,7 @@ smc_status smc_k_rollout(smc_ctx* c, const void* u, int32_t P, const void* W, co
     RolloutParams rp = c->rp;
     rp.H = horizon;
     rp.P = P;
-    HIP_OK(c, launch_rollout(c->prec, rp,
+    HIP_OK(c, do_rollout(c, rp,
                              rollout_arrays(c, u, W, states, k_active, cost, feas,
                                             (unsigned long long*)steps),
                              pick(c, stream)));
@@ -733,6 +765,14 @@ smc_status smc_k_accept(smc_ctx* c, int32_t P, void* u, const void* u_prop, doub
                             logw, logw_prop,
                             make_stream(c->seed, mpc_step, iter, P_ACCEPT, c->scen_id), accepted,
                             c->d_flags, pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_set_rollout_layout(smc_ctx* c, int32_t layout) {
+    if (!c || layout < 0 || layout > 2) return fail(c, SMC_EINVAL, "smc_set_rollout_layout: bad arguments");
+    if (layout == 2 && !rollout_wm_supported(c->N))
+        return fail(c, SMC_EINVAL, "world-per-lane rollout supports at most %d aircraft", kWorldLaneMaxN);
+    c->layout = layout;
     return SMC_OK;
 }
 

@@ -61,13 +61,15 @@ def test_eval_cost_matches_oracle(lib, prec):
     assert np.all(rel_err(cost, rc)[ok] < (1e-6 if prec == "fp64" else 2e-5))
 
 
-def test_full_size_c2_rollout_sampled(lib):
+@pytest.mark.parametrize("layout", [0, 1])
+def test_full_size_c2_rollout_sampled(lib, layout):
     """C2 at full size (8192 particles x 64 wind samples x 10 aircraft x 120
-    steps, the launch the benchmark times); 48 random worlds are checked
-    against the oracle one by one."""
+    steps; layout 0 is the launch the benchmark times); 48 random worlds are
+    checked against the oracle one by one."""
     import torch
     s = synth.c2()
     ctx = lib.smc_mpc_init(s)
+    lib.smc_set_rollout_layout(ctx, layout)
     P, M, N, S = s["L"], s["M"], s["N"], s["S"]
     rng = np.random.default_rng(11)
     u = rng.uniform(0, 1, (P, N, S, 3)).astype(np.float32)

@@ -110,9 +110,11 @@ def test_wind_gemm(lib, prec, grid, M):
 
 # ---- rollout ---------------------------------------------------------------------
 
-def _rollout_case(lib, s, P, seed=0, horizon=None, states=None, k_active=None, u=None, W=None):
+def _rollout_case(lib, s, P, seed=0, horizon=None, states=None, k_active=None, u=None, W=None,
+                  layout=0):
     import torch
     ctx = _ctx(lib, s)
+    lib.smc_set_rollout_layout(ctx, layout)
     rng = np.random.default_rng(seed)
     N, S, M = s["N"], s["S"], s["M"]
     H = s["H"] if horizon is None else horizon
@@ -127,13 +129,15 @@ def _rollout_case(lib, s, P, seed=0, horizon=None, states=None, k_active=None, u
     W = W.astype(rnp).astype(np.float64)
     cost = empty((M, P, N), torch.float64)
     feas = empty((M, P, N), torch.uint8)
-    steps = zeros((64,), torch.int64)
+    steps = zeros((128,), torch.int64)
     lib.smc_k_rollout(ctx, dev(u, ctx.real_dtype), P, dev(W, ctx.real_dtype), dev(states),
                       dev(np.asarray(k_active, np.int32)), H, cost, feas, steps)
     ref = oro.rollout(s, u, W, states, k_active, H, with_margins=True)
     got_c = host(cost).transpose(1, 0, 2)
     got_f = host(feas).transpose(1, 0, 2).astype(bool)
-    return ctx, got_c, got_f, int(host(steps).sum()), ref
+    cnt = host(steps)
+    assert int(cnt[64:].sum()) == ref["pair_tests"]
+    return ctx, got_c, got_f, int(cnt[:64].sum()), ref
 
 
 def _compare_rollout(got_c, got_f, ref, prec, near=None):
@@ -150,10 +154,14 @@ def _compare_rollout(got_c, got_f, ref, prec, near=None):
     return int(world_near[..., 0].sum())
 
 
+LAYOUTS = [1, 2]   # aircraft-per-lane, world-per-lane
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_rollout_c1_shape(lib, prec):
+def test_rollout_c1_shape(lib, prec, layout):
     s = small_scenario("c1", prec)
-    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=200)
+    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=200, layout=layout)
     n_near = _compare_rollout(gc, gf, ref, s["precision"])
     assert steps == ref["steps"]
     assert n_near < 0.05 * 200 * s["M"]
@@ -164,19 +172,22 @@ def test_rollout_c1_shape(lib, prec):
     assert err.max() < (1e-12 if prec == "fp64" else 1e-5)
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_rollout_c2_shape_ragged(lib, prec):
+def test_rollout_c2_shape_ragged(lib, prec, layout):
     """10 aircraft (worlds of 10 lanes, 6 per wave, 4 idle lanes), staggered
     departures, P not a multiple of the worlds per wave, grid 32x32x8."""
     s = synth.shrink(synth.c2(precision=prec), M=5)
-    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=37, seed=4)
+    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=37, seed=4, layout=layout)
     n_near = _compare_rollout(gc, gf, ref, s["precision"])
     assert steps == ref["steps"]
     assert n_near < 0.25 * 37 * 5
 
 
-@pytest.mark.parametrize("N", [1, 2, 3, 7, 16, 33, 64])
-def test_rollout_aircraft_counts(lib, N):
+@pytest.mark.parametrize("N,layout", [(1, 1), (2, 1), (3, 1), (7, 1), (16, 1), (33, 1), (64, 1),
+                                      (1, 2), (2, 2), (3, 2), (5, 2), (7, 2), (9, 2), (10, 2),
+                                      (11, 2), (13, 2), (16, 2)])
+def test_rollout_aircraft_counts(lib, N, layout):
     """Worlds from 1 lane to a full wave; mixed kinds and activation steps."""
     rng = np.random.default_rng(N)
     n_arr = min(max(1, N // 2), 12)
@@ -185,12 +196,14 @@ def test_rollout_aircraft_counts(lib, N):
                             M=3, L=8, K=2, precision="fp64", seed=N)
     k_act = s["k_active"].copy()
     k_act[rng.uniform(size=N) < 0.2] = -1
-    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=11, seed=N, horizon=27, k_active=k_act)
+    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=11, seed=N, horizon=27, k_active=k_act,
+                                            layout=layout)
     _compare_rollout(gc, gf, ref, 0)
     assert steps == ref["steps"]
 
 
-def test_rollout_close_traffic_separation(lib):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_rollout_close_traffic_separation(lib, layout):
     """Aircraft packed inside one separation cell so that many pair tests
     fire, exercising both the pair split and the mask reduction."""
     N = 12
@@ -204,19 +217,21 @@ def test_rollout_close_traffic_separation(lib):
     st[:, 3] = 150.0
     st[:, 4] = rng.uniform(-3, 3, N)
     st[:, 5] = 60e3
-    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=50, states=st, k_active=np.zeros(N, np.int32))
+    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=50, states=st, k_active=np.zeros(N, np.int32),
+                                            layout=layout)
     _compare_rollout(gc, gf, ref, 0)
     assert (~ref["feas"]).mean() > 0.2
 
 
-def test_rollout_noise_term(lib):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_rollout_noise_term(lib, layout):
     s = synth.shrink(synth.c5(precision="fp64"), M=2, H=30, S=3, grid=(8, 8, 4))
     s = dict(s)
     keep = [0, 1, 2, 24, 25]
     for k in ("kind", "aircraft", "targets", "states", "k_active"):
         s[k] = s[k][keep]
     s["N"] = len(keep)
-    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=20)
+    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=20, layout=layout)
     _compare_rollout(gc, gf, ref, 0)
 
 
