@@ -128,6 +128,38 @@ smc_status smc_k_select(smc_ctx* ctx, int32_t P, const double* logw,
                         const double* chat, double beta, int32_t* best,
                         void* stream);
 
+/* Adjoint of the fuel + time part of the cost (build addition; the paper's
+ * optimiser is derivative-free): grad[P][N][S][3] (double) =
+ * d/du_norm sum_m cost_ft[m][p][i], the sum over the M wind samples of W of
+ * the fuel element and the time-to-go element of each aircraft, by a
+ * hand-written reverse sweep with state checkpoints every 25 steps.
+ * Landing carries no derivative; clamps and max/min take the active branch.
+ * Limits: S <= 16, horizon <= 400 (SMC_EINVAL). */
+smc_status smc_k_rollout_grad(smc_ctx* ctx, const void* u, int32_t P, const void* W,
+                              const double* states, const int32_t* k_active,
+                              int32_t horizon, double* grad, void* stream);
+
+/* Langevin proposal u' = u + (eps^2/2) g + eps xi with g = -(beta/M) grad
+ * (grad as returned by smc_k_rollout_grad), eps = the scenario's mala_step,
+ * xi from the MALA stream of `iter`.  No clamping: a proposal outside the
+ * control box is rejected by smc_k_mala_accept. */
+smc_status smc_k_mala_propose(smc_ctx* ctx, int32_t P, const void* u,
+                              const double* grad, double beta, void* u_prop,
+                              int64_t mpc_step, int32_t iter, void* stream);
+
+/* Metropolis-adjusted acceptance of the Langevin proposal with the full
+ * target prod_i W_i: reject outside the box or if the proposal violates,
+ * accept if the current particle violates, otherwise accept iff
+ * log U < sum_i logw' - sum_i logw + log q(u|u') - log q(u'|u) (ACCEPT
+ * stream, element p).  Accepted rows of u, chat, feas_pn, logw are replaced;
+ * accepted[P] (device int32) receives the decisions. */
+smc_status smc_k_mala_accept(smc_ctx* ctx, int32_t P, void* u, const void* u_prop,
+                             const double* grad, const double* grad_prop, double beta,
+                             double* chat, const double* chat_prop, uint8_t* feas_pn,
+                             const uint8_t* feas_prop, double* logw,
+                             const double* logw_prop, int64_t mpc_step, int32_t iter,
+                             int32_t* accepted, void* stream);
+
 /* Rollout kernel layout used by every pass of this context:
  *  0 automatic (world-per-lane for N <= 16, aircraft-per-lane above),
  *  1 aircraft-per-lane: one lane per (particle, sample, aircraft), the world's

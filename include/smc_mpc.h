@@ -47,6 +47,10 @@ typedef enum {
 
 enum { SMC_ARRIVAL = 0, SMC_DEPARTURE = 1 };
 enum { SMC_FP64 = 0, SMC_FP32 = 1 };
+/* moves after weighting: the paper's clamped Gaussian jitter after
+ * resampling; random-walk Metropolis; Metropolis-adjusted Langevin with the
+ * gradient of the fuel + time cost (both Metropolis forms act before
+ * resampling, with the joint target prod_i W_i) */
 enum { SMC_MOVE_JITTER = 0, SMC_MOVE_RWMH = 1, SMC_MOVE_MALA = 2 };
 
 #define SMC_AC_NPAR 9   /* aircraft parameters per aircraft, see smc_scenario */

@@ -93,6 +93,19 @@ def landing_conditions(scen, x, y, z, v, chi):
             (np.abs(wrap(chi - math.pi)), p_chi), (v, p_vs)]
 
 
+def time_element(scen, x, y, v):
+    """Time-to-go element min(t_go / t_norm, 1): arrivals fly the remaining
+    flow-field arc, departures the remaining distance to the exit radius."""
+    kind = scen["kind"]
+    vv = np.maximum(v, scen["env"][2])
+    r = np.hypot(x, y)
+    s_arc = r * arc_ratio(np.abs(np.arctan2(y, x)))
+    dtma = scen["targets"][:, 3]
+    t_arr = np.minimum(s_arc / vv / scen["time_norm"], 1.0)
+    t_dep = np.minimum(np.maximum(dtma - r, 0.0) / vv / scen["time_norm"], 1.0)
+    return np.where(kind == 0, t_arr, t_dep)
+
+
 def step_cost(scen, j, x, y, z, v, chi, z_act):
     """Per-step cost (0 best, 1 worst) at a new state, for every aircraft.
 
@@ -144,7 +157,8 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
     """Roll out particles ``u_norm`` [L, N, S, 3] (normalised controls in
     [0, 1]) under wind fields ``W`` [M, G, 2].
 
-    Returns dict with cost [L, M, N], feas [L, M, N] (bool), steps (number of
+    Returns dict with cost [L, M, N], ft_cost [L, M, N] (its fuel + time part),
+    feas [L, M, N] (bool), steps (number of
     simulated aircraft-steps), pair_tests (separation tests with both aircraft
     present), and, if asked, margin [L, M, N]: the smallest
     relative distance of any discrete decision (unary check, landing test,
@@ -174,6 +188,7 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
     feas = np.ones(shape, dtype=bool)
     done = np.zeros(shape, dtype=bool)
     acc = np.zeros(shape)
+    acc_t = np.zeros(shape)
     margin = np.full(shape, np.inf)
     m_idx = np.arange(M)[None, :, None]
     steps = 0
@@ -248,6 +263,7 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
         j = np.maximum(k + 1 - kact, 1)           # steps since activation
         c = step_cost(scen, j, x, y, z, v, chi, z_act)
         acc += np.where(present & ~landed, c, 0.0)
+        acc_t += np.where(present & ~landed, time_element(scen, x, y, v), 0.0)
         done |= landed
 
         # pairwise separation among aircraft that have a state at k+1
@@ -276,7 +292,10 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
     fuel_term = (m_act - mass) / denom
     cost = np.where(active, mix * a_fuel * fuel_term + acc / np.maximum(n_steps, 1),
                     0.0)
-    out = dict(cost=cost, feas=feas, steps=steps, pair_tests=pair_tests,
+    # the differentiable part used by gradient-informed moves: fuel + time
+    ft_cost = np.where(active, mix * a_fuel * fuel_term
+                       + w[7] * acc_t / np.maximum(n_steps, 1), 0.0)
+    out = dict(cost=cost, feas=feas, steps=steps, pair_tests=pair_tests, ft_cost=ft_cost,
                final=np.stack([x, y, z, v, chi, mass], axis=-1))
     if with_margins:
         out["margin"] = margin

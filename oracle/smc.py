@@ -223,12 +223,21 @@ def select_best(logw, chat, b):
 
 # --- one MPC update ----------------------------------------------------------
 
+def mala_propose(scen, u, g, J, mpc_step=None):
+    """Langevin proposal u + (eps^2 / 2) g + eps xi (MALA stream)."""
+    eps = scen["mala_step"]
+    xi = move_normals(scen, J, u.shape, purpose=philox.MALA, mpc_step=mpc_step)
+    return u + 0.5 * eps * eps * g + eps * xi
+
+
 def run_smc(scen, evaluate, L, K, N, S, mpc_step=None, trace=None,
-            u_init=None):
+            u_init=None, grad=None):
     """Generic SMC optimiser (Alg. 1 with the readings above).
 
-    ``evaluate(u, J)`` -> (c_hat [L, N], feasible [L, N]).  Returns dict with
-    the final particles, c_hat, log-weights, the selected index and status."""
+    ``evaluate(u, J)`` -> (c_hat [L, N], feasible [L, N]); ``grad(u, J)`` ->
+    d/du sum_i c_hat_i of the differentiable (fuel + time) part, needed by the
+    Langevin move.  Returns dict with the final particles, c_hat,
+    log-weights, the selected index and status."""
     move = scen["move"]
     u = init_particles(scen, mpc_step, L) if u_init is None else u_init.copy()
     acc_rate = []
@@ -249,8 +258,24 @@ def run_smc(scen, evaluate, L, K, N, S, mpc_step=None, trace=None,
             acc_rate.append(float(acc.mean()))
             if trace is not None:
                 trace[-1].update(u_prop=up, acc=acc, logw_after=logw.copy())
-        elif move == 2:
-            raise NotImplementedError("gradient move lives in oracle.grad")
+        elif move == 2:   # Metropolis-adjusted Langevin on the joint particle
+            from .grad import mala_log_q
+            eps = scen["mala_step"]
+            g = -b * grad(u, J)
+            up = mala_propose(scen, u, g, J, mpc_step)
+            chat_p, feas_p = evaluate(up, J)
+            logw_p = log_weights(chat_p, feas_p, b)
+            gp = -b * grad(up, J)
+            lq = mala_log_q(u, up, gp, eps) - mala_log_q(up, u, g, eps)
+            inside = np.all(((up >= 0.0) & (up <= 1.0)).reshape(L, -1), axis=1)
+            logw_p_eff = np.where(inside[:, None], logw_p, -np.inf)
+            acc = mh_accept(scen, J, logw, logw_p_eff, mpc_step, log_q_ratio=lq)
+            u = np.where(acc[:, None, None, None], up, u)
+            chat = np.where(acc[:, None], chat_p, chat)
+            logw = np.where(acc[:, None], logw_p, logw)
+            acc_rate.append(float(acc.mean()))
+            if trace is not None:
+                trace[-1].update(u_prop=up, acc=acc, logw_after=logw.copy(), g=g, g_prop=gp)
         if J == K - 1:
             break
         anc = resample(logw, resample_offsets(scen, J, N, mpc_step))
@@ -280,12 +305,23 @@ def smc_mpc_step(scen, states=None, k_active=None, horizon=None, mpc_step=None,
     Lfac = _wind.kron_factor(scen["box"], scen["grid"], scen["wind_sigma"],
                              scen["wind_ell"], scen["wind_nugget"])
 
+    fields = {}
+
+    def field(J):
+        if J not in fields:
+            fields.clear()
+            fields[J] = _wind.sample_field(scen, J, step, Lfac)
+        return fields[J]
+
     def evaluate(u, J):
-        W = _wind.sample_field(scen, J, step, Lfac)
-        r = _rollout.rollout(scen, u, W, states, k_active, horizon)
+        r = _rollout.rollout(scen, u, field(J), states, k_active, horizon)
         return expected_cost(r["cost"], r["feas"])
 
-    res = run_smc(scen, evaluate, L, K, N, S, step, trace)
+    def grad(u, J):
+        from .grad import grad_fuel_time
+        return grad_fuel_time(scen, u, field(J), states, k_active, horizon)[1]
+
+    res = run_smc(scen, evaluate, L, K, N, S, step, trace, grad=grad)
     l = res["best"]
     per = res["chat"][l]
     total = 0.0

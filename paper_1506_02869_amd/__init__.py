@@ -99,6 +99,11 @@ _SIGS = {
                                C.c_int64, C.c_int32, _VP, _VP]),
     "smc_k_select": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, _VP, _VP]),
     "smc_set_rollout_layout": (C.c_int, [_VP, C.c_int32]),
+    "smc_k_rollout_grad": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, C.c_int32, _VP, _VP]),
+    "smc_k_mala_propose": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, _VP, C.c_int64,
+                                     C.c_int32, _VP]),
+    "smc_k_mala_accept": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, C.c_double, _VP, _VP,
+                                    _VP, _VP, _VP, _VP, C.c_int64, C.c_int32, _VP, _VP]),
 }
 
 _lib = None
@@ -371,3 +376,22 @@ def smc_k_select(ctx, P, logw, chat, beta, best, stream=None):
 def smc_set_rollout_layout(ctx, layout):
     """0 automatic, 1 aircraft-per-lane, 2 world-per-lane."""
     _check(lib().smc_set_rollout_layout(ctx.handle, int(layout)), ctx)
+
+
+def smc_k_rollout_grad(ctx, u, P, W, states, k_active, horizon, grad, stream=None):
+    _check(lib().smc_k_rollout_grad(ctx.handle, _ptr(u), int(P), _ptr(W), _ptr(states),
+                                    _ptr(k_active), int(horizon), _ptr(grad), _stream(stream)), ctx)
+
+
+def smc_k_mala_propose(ctx, P, u, grad, beta, u_prop, mpc_step, iter_, stream=None):
+    _check(lib().smc_k_mala_propose(ctx.handle, int(P), _ptr(u), _ptr(grad), float(beta),
+                                    _ptr(u_prop), int(mpc_step), int(iter_), _stream(stream)), ctx)
+
+
+def smc_k_mala_accept(ctx, P, u, u_prop, grad, grad_prop, beta, chat, chat_prop, feas_pn,
+                      feas_prop, logw, logw_prop, mpc_step, iter_, accepted, stream=None):
+    _check(lib().smc_k_mala_accept(ctx.handle, int(P), _ptr(u), _ptr(u_prop), _ptr(grad),
+                                   _ptr(grad_prop), float(beta), _ptr(chat), _ptr(chat_prop),
+                                   _ptr(feas_pn), _ptr(feas_prop), _ptr(logw), _ptr(logw_prop),
+                                   int(mpc_step), int(iter_), _ptr(accepted), _stream(stream)),
+           ctx)

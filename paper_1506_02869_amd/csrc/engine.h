@@ -64,6 +64,24 @@ bool rollout_wm_supported(int N);
 // kind (0 arrival, 1 departure), 0
 hipError_t launch_rollout_wm(int prec, const RolloutParams& p, const RolloutArrays& a,
                              const void* acR, hipStream_t st);
+// adjoint of the fuel + time cost (sum over wind samples) w.r.t. the
+// normalised controls; partial: chunk partials when M > 64
+bool grad_supported(int H, int S);
+size_t grad_partial_elems(int P, int N, int S, int M);
+hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u, const void* W,
+                               const double* states, const int32_t* k_active, const double* acpar,
+                               const double* targets, const int8_t* kind, double* partial,
+                               double* grad_out, hipStream_t st);
+hipError_t launch_mala_propose(int prec, int64_t count, const void* u, const double* gsum,
+                               double coef, double eps, Stream s, void* up, hipStream_t st);
+hipError_t launch_mala_decide(int prec, int P, int N, int D, const void* u, const void* up,
+                              const double* g, const double* gprop, double coef, double eps,
+                              const double* logw, const double* logw_prop, Stream s,
+                              int32_t* flags, hipStream_t st);
+hipError_t launch_accept_apply(int prec, int P, int N, int D, void* u, const void* u_prop,
+                               double* chat, const double* chat_prop, uint8_t* feas_pn,
+                               const uint8_t* feas_prop, double* logw, const double* logw_prop,
+                               const int32_t* flags, hipStream_t st);
 hipError_t launch_reduce(int P, int M, int N, const double* cost,
                          const uint8_t* feas, double beta, double* chat,
                          uint8_t* feas_pn, double* logw, hipStream_t st);

@@ -1,0 +1,508 @@
+// Hand-written adjoint of the rollout for the fuel + time part of the cost
+// (the differentiable elements used by the gradient-informed move), with
+// segment checkpointing, and the Langevin (MALA) proposal / acceptance.
+//
+// Lanes: one per (particle l, aircraft i, wind sample m), the samples of one
+// (l, i) in consecutive lanes (padded to a power of two up to 64, or to
+// multiples of 64), so the sum over samples is a wave reduction.  Forward:
+// the rollout of the aircraft, storing its state every CK steps and its
+// landing step.  Reverse: for each segment from the last, recompute the
+// segment's states from its checkpoint into a per-lane tape, then sweep the
+// steps backwards, recomputing each step's intermediates and applying the
+// chain rule to the adjoint (x, y, z, v, chi, burn) and to the segment's
+// controls.  Discrete events (landing) carry no derivative; clamps,
+// max(T, 0) and min(t, 1) take the derivative of the active branch.
+#include "rollout_math.h"
+
+namespace smc {
+
+constexpr int GR_CK = 25;        // checkpoint interval [steps]
+constexpr int GR_MAXSEG = 16;    // horizons up to 400 steps
+constexpr int GR_MAXS = 16;      // control segments
+
+struct GradParams {
+    RolloutParams rp;
+    int Mp;          // lanes per (particle, aircraft) group
+    int chunks;      // partial sums per group (Mp / 64 when Mp > 64, else 1)
+};
+
+template <typename R>
+struct StepFwd {     // intermediates of one step, recomputed in the reverse sweep
+    R wx, wy, dwx[3], dwy[3];
+    R sg, cg, tphi, icphi, rho, drho_dz, qd, mass, CL, D, vn, T, eta, f;
+    R sc, cc;
+};
+
+// Trilinear wind and its derivative with respect to (x, y, z) (zero along a
+// clamped coordinate).
+template <typename R>
+__device__ __forceinline__ void wind_and_grad(const typename V2<R>::t* Wm, const RolloutParams& p,
+                                              R x, R y, R z, StepFwd<R>& o) {
+    typedef typename V2<R>::t R2;
+    const R ux = (x + (R)p.half_wx) * (R)p.inv_hx;
+    const R uy = (y + (R)p.half_wy) * (R)p.inv_hy;
+    const R uz = z * (R)p.inv_hz;
+    const R fx = clampr(ux, (R)0, (R)(p.nx - 1));
+    const R fy = clampr(uy, (R)0, (R)(p.ny - 1));
+    const R fz = clampr(uz, (R)0, (R)(p.nz - 1));
+    const R jx = (ux >= (R)0 && ux <= (R)(p.nx - 1)) ? (R)p.inv_hx : (R)0;
+    const R jy = (uy >= (R)0 && uy <= (R)(p.ny - 1)) ? (R)p.inv_hy : (R)0;
+    const R jz = (uz >= (R)0 && uz <= (R)(p.nz - 1)) ? (R)p.inv_hz : (R)0;
+    const int ix = min((int)fx, p.nx - 2), iy = min((int)fy, p.ny - 2), iz = min((int)fz, p.nz - 2);
+    const R tx = fx - (R)ix, ty = fy - (R)iy, tz = fz - (R)iz;
+    const int nzz = p.nz, nyz = p.ny * p.nz;
+    const int g = (ix * p.ny + iy) * nzz + iz;
+    const R2 c000 = Wm[g], c001 = Wm[g + 1], c010 = Wm[g + nzz], c011 = Wm[g + nzz + 1];
+    const R2 c100 = Wm[g + nyz], c101 = Wm[g + nyz + 1], c110 = Wm[g + nyz + nzz],
+             c111 = Wm[g + nyz + nzz + 1];
+    // component x
+    {
+        const R a00 = c000.x + tz * (c001.x - c000.x), a01 = c010.x + tz * (c011.x - c010.x);
+        const R a10 = c100.x + tz * (c101.x - c100.x), a11 = c110.x + tz * (c111.x - c110.x);
+        const R b0 = a00 + ty * (a01 - a00), b1 = a10 + ty * (a11 - a10);
+        o.wx = b0 + tx * (b1 - b0);
+        const R d_tx = b1 - b0;
+        const R d_ty = ((R)1 - tx) * (a01 - a00) + tx * (a11 - a10);
+        const R dz0 = ((R)1 - ty) * (c001.x - c000.x) + ty * (c011.x - c010.x);
+        const R dz1 = ((R)1 - ty) * (c101.x - c100.x) + ty * (c111.x - c110.x);
+        const R d_tz = ((R)1 - tx) * dz0 + tx * dz1;
+        o.dwx[0] = d_tx * jx; o.dwx[1] = d_ty * jy; o.dwx[2] = d_tz * jz;
+    }
+    {
+        const R a00 = c000.y + tz * (c001.y - c000.y), a01 = c010.y + tz * (c011.y - c010.y);
+        const R a10 = c100.y + tz * (c101.y - c100.y), a11 = c110.y + tz * (c111.y - c110.y);
+        const R b0 = a00 + ty * (a01 - a00), b1 = a10 + ty * (a11 - a10);
+        o.wy = b0 + tx * (b1 - b0);
+        const R d_tx = b1 - b0;
+        const R d_ty = ((R)1 - tx) * (a01 - a00) + tx * (a11 - a10);
+        const R dz0 = ((R)1 - ty) * (c001.y - c000.y) + ty * (c011.y - c010.y);
+        const R dz1 = ((R)1 - ty) * (c101.y - c100.y) + ty * (c111.y - c110.y);
+        const R d_tz = ((R)1 - tx) * dz0 + tx * dz1;
+        o.dwy[0] = d_tx * jx; o.dwy[1] = d_ty * jy; o.dwy[2] = d_tz * jz;
+    }
+}
+
+struct AcConst {
+    double Sw, cd0, cd2, cf1, cf2, tmax, dtma, m0;
+    bool arr;
+};
+
+// One forward step (the rollout's arithmetic, full precision ops).
+template <typename R>
+__device__ __forceinline__ void step_forward(const typename V2<R>::t* Wm, const RolloutParams& p,
+                                             const AcConst& ac, R x, R y, R z, R v, R chi, R B,
+                                             R cd, R vc, R zd, R ir, StepFwd<R>& o) {
+    typedef Ops<R> O;
+    const R g0 = (R)kG0;
+    wind_and_grad<R>(Wm, p, x, y, z, o);
+    o.sg = zd * O::rcp(v);
+    o.cg = O::sqrt((R)1 - o.sg * o.sg);
+    o.tphi = v * cd * (R)(1.0 / kG0);
+    o.icphi = O::sqrt((R)1 + o.tphi * o.tphi);
+    const R isa_c = (R)(kLapse / kT0), isa_e = (R)(kG0 / (kRair * kLapse) - 1.0);
+    const bool zin = z > (R)0 && z < (R)11000;
+    const R zc = clampr(z, (R)0, (R)11000);
+    const R base = (R)1 - isa_c * zc;
+    o.rho = (R)kRho0 * O::pow_pos(base, isa_e);
+    o.drho_dz = zin ? -o.rho * isa_e * isa_c * O::rcp(base) : (R)0;
+    o.qd = (R)0.5 * o.rho * v * v;
+    o.mass = (R)ac.m0 - B;
+    o.CL = O::div(o.mass * g0 * o.icphi, o.qd * (R)ac.Sw);
+    o.D = o.qd * (R)ac.Sw * ((R)ac.cd0 + (R)ac.cd2 * o.CL * o.CL);
+    o.vn = v + (vc - v) * ir;
+    o.T = o.mass * (o.vn - v) * (R)(1.0 / p.dt) + o.D + o.mass * g0 * o.sg;
+    o.eta = (R)ac.cf1 * ((R)1 + v * (R)(1.0 / ac.cf2));
+    o.f = (R)p.dt * o.eta * m_max(o.T, (R)0);
+    O::sincos(chi, &o.sc, &o.cc);
+}
+
+// time-to-go element at a new state and its derivative w.r.t. (x, y, v)
+template <typename R>
+__device__ __forceinline__ R time_elem(const RolloutParams& p, const AcConst& ac, R x, R y, R v,
+                                       R* dx, R* dy, R* dv) {
+    typedef Ops<R> O;
+    const R vmin = (R)p.vmin;
+    const R vv = m_max(v, vmin);
+    const R ivv = O::rcp(vv);
+    const R itn = (R)(1.0 / p.time_norm);
+    const R r = O::sqrt(x * x + y * y);
+    R num, dn_dx, dn_dy;
+    if (ac.arr) {
+        const R th = O::atan2(y, x);
+        const R tha = m_abs(th);
+        const R sgn = th < (R)0 ? (R)-1 : (R)1;
+        R ratio, dratio;
+        if (tha > (R)1e-4) {
+            const R s = O::sin(tha);
+            if (s > (R)1e-6) {
+                ratio = tha * O::rcp(s);
+                R c, sdummy;
+                O::sincos(tha, &sdummy, &c);
+                dratio = (s - tha * c) * O::rcp(s * s);
+            } else {
+                ratio = tha * (R)1e6;
+                dratio = (R)1e6;
+            }
+        } else {
+            ratio = (R)1 + tha * tha * (R)(1.0 / 6.0);
+            dratio = tha * (R)(1.0 / 3.0);
+        }
+        num = r * ratio;
+        const R ir = r > (R)0 ? O::rcp(r) : (R)0;
+        const R ir2 = ir * ir;
+        // d theta / dx = -y / r^2, d theta / dy = x / r^2
+        dn_dx = x * ir * ratio + r * dratio * sgn * (-y * ir2);
+        dn_dy = y * ir * ratio + r * dratio * sgn * (x * ir2);
+    } else {
+        const R gap = (R)ac.dtma - r;
+        if (gap > (R)0) {
+            num = gap;
+            const R ir = r > (R)0 ? O::rcp(r) : (R)0;
+            dn_dx = -x * ir;
+            dn_dy = -y * ir;
+        } else {
+            num = (R)0; dn_dx = (R)0; dn_dy = (R)0;
+        }
+    }
+    const R t = num * ivv * itn;
+    if (t >= (R)1) { *dx = (R)0; *dy = (R)0; *dv = (R)0; return (R)1; }
+    *dx = dn_dx * ivv * itn;
+    *dy = dn_dy * ivv * itn;
+    *dv = v > vmin ? -t * ivv : (R)0;
+    return t;
+}
+
+template <typename R>
+__device__ __forceinline__ bool landed_at(const RolloutParams& p, R x, R y, R z, R v, R chi) {
+    typedef Ops<R> O;
+    const R r = O::sqrt(x * x + y * y);
+    const R th = O::atan2(y, x);
+    const R tha = m_abs(th);
+    const R ratio = tha > (R)1e-4 ? tha * O::rcp(m_max(O::sin(tha), (R)1e-6))
+                                  : (R)1 + tha * tha * (R)(1.0 / 6.0);
+    const R beta = O::atan2(z, r * ratio);
+    return r <= (R)p.p_run && beta <= (R)p.p_beta && tha <= (R)p.p_chi &&
+           m_abs(wrap_angle<R>(chi - Consts<R>::pi)) <= (R)p.p_chi && v <= (R)p.p_vs;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_rollout_grad(const GradParams gp, const R* __restrict__ u,
+                                                      const R* __restrict__ W,
+                                                      const double* __restrict__ states,
+                                                      const int32_t* __restrict__ k_active,
+                                                      const double* __restrict__ acpar,
+                                                      const double* __restrict__ targets,
+                                                      const int8_t* __restrict__ kind,
+                                                      double* __restrict__ out) {
+    typedef typename V2<R>::t R2;
+    const RolloutParams& p = gp.rp;
+    const int N = p.N, S = p.S, H = p.H, M = p.M, Mp = gp.Mp;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = (int)(t % Mp);
+    const int64_t grp = t / Mp;                 // (l, i)
+    const int64_t ngrp = (int64_t)p.P * N;
+    const bool valid = grp < ngrp && m < M;
+    const int l = grp < ngrp ? (int)(grp / N) : 0;
+    const int i = grp < ngrp ? (int)(grp % N) : 0;
+    const int mm = m < M ? m : 0;
+
+    AcConst ac;
+    ac.Sw = acpar[i * 9 + 0]; ac.cd0 = acpar[i * 9 + 1]; ac.cd2 = acpar[i * 9 + 2];
+    ac.cf1 = acpar[i * 9 + 3]; ac.cf2 = acpar[i * 9 + 4]; ac.tmax = acpar[i * 9 + 5];
+    ac.dtma = targets[i * 4 + 3]; ac.m0 = states[i * 6 + 5];
+    ac.arr = kind[i] == 0;
+    const int k0 = k_active[i];
+    const bool active = valid && k0 >= 0 && k0 < H;
+    const R2* Wm = (const R2*)W + (int64_t)mm * p.G;
+    const R* ub = u + ((int64_t)l * N + i) * S * 3;
+    const double lo[3] = {p.ctrl_lo[0], p.ctrl_lo[1], p.ctrl_lo[2]};
+    const double sp[3] = {p.ctrl_span[0], p.ctrl_span[1], p.ctrl_span[2]};
+
+    R gsum[GR_MAXS][3];
+#pragma unroll
+    for (int s = 0; s < GR_MAXS; ++s) gsum[s][0] = gsum[s][1] = gsum[s][2] = (R)0;
+
+    if (active) {
+        R ck[GR_MAXSEG][6];
+        R x = (R)states[i * 6 + 0], y = (R)states[i * 6 + 1], z = (R)states[i * 6 + 2];
+        R v = (R)states[i * 6 + 3], chi = (R)states[i * 6 + 4], B = (R)0;
+        int k_land = H;   // step whose new state lands
+        // forward: checkpoints and landing step
+        for (int k = k0; k < H; ++k) {
+            if (((k - k0) % GR_CK) == 0) {
+                R* c = ck[(k - k0) / GR_CK];
+                c[0] = x; c[1] = y; c[2] = z; c[3] = v; c[4] = chi; c[5] = B;
+            }
+            const int s = (k * S) / H;
+            const int k_end = ((s + 1) * H + S - 1) / S;
+            const R cd = (R)(lo[0] + (double)ub[s * 3 + 0] * sp[0]);
+            const R vc = (R)(lo[1] + (double)ub[s * 3 + 1] * sp[1]);
+            const R zd = (R)(lo[2] + (double)ub[s * 3 + 2] * sp[2]);
+            StepFwd<R> o;
+            step_forward<R>(Wm, p, ac, x, y, z, v, chi, B, cd, vc, zd, Ops<R>::rcp((R)(k_end - k)), o);
+            x = x + (R)p.dt * (v * o.cc * o.cg + o.wx);
+            y = y + (R)p.dt * (v * o.sc * o.cg + o.wy);
+            z = z + (R)p.dt * (v * o.sg);
+            chi = chi + (R)p.dt * cd;
+            v = o.vn;
+            B = B + o.f;
+            if (ac.arr && landed_at<R>(p, x, y, z, v, chi)) { k_land = k; break; }
+        }
+        // reverse sweep
+        const int nsteps = H - k0;
+        const double wf = ac.arr ? p.w[2] : p.w[4];
+        const double denom = p.dt * (double)nsteps * ac.tmax * (ac.cf1 * (1.0 + p.vmax / ac.cf2));
+        const R kf = (R)((1.0 - p.w[7] - p.w[8]) * wf / denom);
+        const R kt = (R)(p.w[7] / (double)nsteps);
+        R ax = 0, ay = 0, az = 0, av = 0, achi = 0, aB = kf;
+        const int k_last = min(k_land, H - 1);
+        const int nseg = (k_last - k0) / GR_CK + 1;
+        R tape[GR_CK][6];
+        for (int sg_i = nseg - 1; sg_i >= 0; --sg_i) {
+            const int ka = k0 + sg_i * GR_CK;
+            const int kb = min(k_last, ka + GR_CK - 1);
+            {   // recompute the segment's step-start states
+                const R* c = ck[sg_i];
+                R x1 = c[0], y1 = c[1], z1 = c[2], v1 = c[3], chi1 = c[4], B1 = c[5];
+                for (int k = ka; k <= kb; ++k) {
+                    R* tp = tape[k - ka];
+                    tp[0] = x1; tp[1] = y1; tp[2] = z1; tp[3] = v1; tp[4] = chi1; tp[5] = B1;
+                    if (k == kb) break;
+                    const int s = (k * S) / H;
+                    const int k_end = ((s + 1) * H + S - 1) / S;
+                    const R cd = (R)(lo[0] + (double)ub[s * 3 + 0] * sp[0]);
+                    const R vc = (R)(lo[1] + (double)ub[s * 3 + 1] * sp[1]);
+                    const R zd = (R)(lo[2] + (double)ub[s * 3 + 2] * sp[2]);
+                    StepFwd<R> o;
+                    step_forward<R>(Wm, p, ac, x1, y1, z1, v1, chi1, B1, cd, vc, zd,
+                                    Ops<R>::rcp((R)(k_end - k)), o);
+                    x1 = x1 + (R)p.dt * (v1 * o.cc * o.cg + o.wx);
+                    y1 = y1 + (R)p.dt * (v1 * o.sc * o.cg + o.wy);
+                    z1 = z1 + (R)p.dt * (v1 * o.sg);
+                    chi1 = chi1 + (R)p.dt * cd;
+                    v1 = o.vn;
+                    B1 = B1 + o.f;
+                }
+            }
+            for (int k = kb; k >= ka; --k) {
+                const R* tp = tape[k - ka];
+                const R x0 = tp[0], y0 = tp[1], z0 = tp[2], v0 = tp[3], chi0 = tp[4], B0 = tp[5];
+                const int s = (k * S) / H;
+                const int k_end = ((s + 1) * H + S - 1) / S;
+                const R ir = Ops<R>::rcp((R)(k_end - k));
+                const R cd = (R)(lo[0] + (double)ub[s * 3 + 0] * sp[0]);
+                const R vc = (R)(lo[1] + (double)ub[s * 3 + 1] * sp[1]);
+                const R zd = (R)(lo[2] + (double)ub[s * 3 + 2] * sp[2]);
+                StepFwd<R> o;
+                step_forward<R>(Wm, p, ac, x0, y0, z0, v0, chi0, B0, cd, vc, zd, ir, o);
+                const R dt = (R)p.dt;
+                const R xn = x0 + dt * (v0 * o.cc * o.cg + o.wx);
+                const R yn = y0 + dt * (v0 * o.sc * o.cg + o.wy);
+                // time element at the new state (counted unless this step lands)
+                if (k < k_land) {
+                    R dx, dy, dv;
+                    time_elem<R>(p, ac, xn, yn, o.vn, &dx, &dy, &dv);
+                    ax += kt * dx; ay += kt * dy; av += kt * dv;
+                }
+                // fuel f = dt eta max(T, 0)
+                R df_dv = 0, df_dvc = 0, df_dzd = 0, df_dcd = 0, df_dz = 0, df_dm = 0;
+                if (o.T > (R)0) {
+                    const R g0 = (R)kG0;
+                    const R A0 = o.qd * (R)ac.Sw;
+                    const R dD_dA0 = (R)ac.cd0 - (R)ac.cd2 * o.CL * o.CL;
+                    const R dD_dK = (R)2 * (R)ac.cd2 * o.CL;
+                    const R inv_dt = (R)(1.0 / p.dt);
+                    const R dT_dv = -o.mass * ir * inv_dt + dD_dA0 * ((R)2 * A0 * Ops<R>::rcp(v0)) +
+                                    dD_dK * o.mass * g0 * (o.tphi * Ops<R>::rcp(o.icphi)) * (cd * (R)(1.0 / kG0)) -
+                                    o.mass * g0 * o.sg * Ops<R>::rcp(v0);
+                    const R dT_dvc = o.mass * ir * inv_dt;
+                    const R dT_dzd = o.mass * g0 * Ops<R>::rcp(v0);
+                    const R dT_dcd = dD_dK * o.mass * g0 * (o.tphi * Ops<R>::rcp(o.icphi)) * (v0 * (R)(1.0 / kG0));
+                    const R dT_dz = dD_dA0 * (A0 * Ops<R>::rcp(o.rho)) * o.drho_dz;
+                    const R dT_dm = (o.vn - v0) * inv_dt + dD_dK * g0 * o.icphi + g0 * o.sg;
+                    const R dt_eta = dt * o.eta;
+                    df_dv = dt * (R)(ac.cf1 / ac.cf2) * o.T + dt_eta * dT_dv;
+                    df_dvc = dt_eta * dT_dvc;
+                    df_dzd = dt_eta * dT_dzd;
+                    df_dcd = dt_eta * dT_dcd;
+                    df_dz = dt_eta * dT_dz;
+                    df_dm = dt_eta * dT_dm;
+                }
+                const R icg = Ops<R>::rcp(o.cg);
+                // adjoints of the step's inputs
+                const R nx_ = ax * ((R)1 + dt * o.dwx[0]) + ay * dt * o.dwy[0];
+                const R ny_ = ax * dt * o.dwx[1] + ay * ((R)1 + dt * o.dwy[1]);
+                const R nz_ = az + ax * dt * o.dwx[2] + ay * dt * o.dwy[2] + aB * df_dz;
+                const R nchi = achi + ax * dt * (-v0 * o.sc * o.cg) + ay * dt * (v0 * o.cc * o.cg);
+                const R nv = av * ((R)1 - ir) + ax * dt * o.cc * icg + ay * dt * o.sc * icg + aB * df_dv;
+                const R nB = aB - aB * df_dm;
+                const R g_cd = achi * dt + aB * df_dcd;
+                const R g_vc = av * ir + aB * df_dvc;
+                const R g_zd = ax * dt * o.cc * (-o.sg * icg) + ay * dt * o.sc * (-o.sg * icg) + az * dt +
+                               aB * df_dzd;
+#pragma unroll
+                for (int q = 0; q < GR_MAXS; ++q)
+                    if (q == s) { gsum[q][0] += g_cd; gsum[q][1] += g_vc; gsum[q][2] += g_zd; }
+                ax = nx_; ay = ny_; az = nz_; achi = nchi; av = nv; aB = nB;
+            }
+        }
+    }
+
+    // sum over the wind samples of the group: wave reduction in FP64
+    const int width = Mp < 64 ? Mp : 64;
+#pragma unroll
+    for (int q = 0; q < GR_MAXS; ++q) {
+        if (q >= S) break;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double vsum = (double)gsum[q][c] * sp[c];   // d u_phys / d u_norm
+            for (int off = width >> 1; off > 0; off >>= 1) vsum += __shfl_xor(vsum, off, width);
+            if ((m % width) == 0 && grp < ngrp) {
+                const int chunk = m / width;
+                out[(((int64_t)chunk * p.P + l) * N + i) * S * 3 + q * 3 + c] = vsum;
+            }
+        }
+    }
+}
+
+// Sum of chunk partials (only when more than 64 samples).
+__global__ void k_grad_chunks(int64_t n, int chunks, const double* __restrict__ part,
+                              double* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * n + e];
+    out[e] = s;
+}
+
+int grad_lanes_per_group(int M) {
+    if (M > 64) return ((M + 63) / 64) * 64;
+    int mp = 1;
+    while (mp < M) mp <<= 1;
+    return mp;
+}
+
+size_t grad_partial_elems(int P, int N, int S, int M) {
+    const int mp = grad_lanes_per_group(M);
+    const int chunks = mp > 64 ? mp / 64 : 1;
+    return (size_t)chunks * P * N * S * 3;
+}
+
+bool grad_supported(int H, int S) {
+    return S <= GR_MAXS && (H + GR_CK - 1) / GR_CK <= GR_MAXSEG;
+}
+
+hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u, const void* W,
+                               const double* states, const int32_t* k_active, const double* acpar,
+                               const double* targets, const int8_t* kind, double* partial,
+                               double* grad_out, hipStream_t st) {
+    if (!grad_supported(rp.H, rp.S)) return hipErrorInvalidValue;
+    GradParams gp;
+    gp.rp = rp;
+    gp.Mp = grad_lanes_per_group(rp.M);
+    gp.chunks = gp.Mp > 64 ? gp.Mp / 64 : 1;
+    const int64_t lanes = (int64_t)rp.P * rp.N * gp.Mp;
+    const unsigned blocks = (unsigned)((lanes + 255) / 256);
+    double* dst = gp.chunks > 1 ? partial : grad_out;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_rollout_grad<double>, dim3(blocks), dim3(256), 0, st, gp,
+                           (const double*)u, (const double*)W, states, k_active, acpar, targets,
+                           kind, dst);
+    else
+        hipLaunchKernelGGL(k_rollout_grad<float>, dim3(blocks), dim3(256), 0, st, gp,
+                           (const float*)u, (const float*)W, states, k_active, acpar, targets,
+                           kind, dst);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || gp.chunks == 1) return e;
+    const int64_t n = (int64_t)rp.P * rp.N * rp.S * 3;
+    hipLaunchKernelGGL(k_grad_chunks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+                       gp.chunks, partial, grad_out);
+    return hipGetLastError();
+}
+
+// ---- Langevin proposal and acceptance -----------------------------------------------
+
+// u' = u + (eps^2 / 2) g + eps xi with g = -(beta / M) * grad_sum (the drift
+// of the tempered fuel + time target), xi from the MALA stream.
+template <typename R>
+__global__ void k_mala_propose(int64_t count, const R* __restrict__ u, const double* __restrict__ gsum,
+                               double coef, double eps, Stream s, R* __restrict__ up) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double z0, z1;
+    normal_pair(draw(s, (uint32_t)e), z0, z1);
+    const double g = coef * gsum[e];
+    up[e] = (R)((double)u[e] + 0.5 * eps * eps * g + eps * z0);
+}
+
+// Per particle: reject a proposal outside the control box or violating;
+// accept one if the current particle violates; otherwise accept iff
+// log U < sum_i logw' - sum_i logw + log q(u | u') - log q(u' | u).
+template <typename R>
+__global__ void k_mala_decide(int P, int N, int D, const R* __restrict__ u, const R* __restrict__ up,
+                              const double* __restrict__ g, const double* __restrict__ gp_,
+                              double coef, double eps, const double* __restrict__ logw,
+                              const double* __restrict__ logw_prop, Stream s,
+                              int32_t* __restrict__ flags) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int64_t base = (int64_t)p * N * D;
+    const int64_t n = (int64_t)N * D;
+    bool inside = true;
+    double fwd = 0.0, bwd = 0.0;
+    const double h = 0.5 * eps * eps;
+    for (int64_t e = 0; e < n; ++e) {
+        const double a = (double)u[base + e], b = (double)up[base + e];
+        if (!(b >= 0.0 && b <= 1.0)) inside = false;
+        const double d1 = b - a - h * coef * g[base + e];      // u' given u
+        const double d2 = a - b - h * coef * gp_[base + e];    // u given u'
+        fwd += d1 * d1;
+        bwd += d2 * d2;
+    }
+    double s_new = 0.0, s_old = 0.0;
+    for (int i = 0; i < N; ++i) {
+        s_new += logw_prop[(int64_t)p * N + i];
+        s_old += logw[(int64_t)p * N + i];
+    }
+    int acc;
+    if (!inside || s_new == -INFINITY) {
+        acc = 0;
+    } else if (s_old == -INFINITY) {
+        acc = 1;
+    } else {
+        const double lq = (fwd - bwd) / (2.0 * eps * eps);   // log q(u|u') - log q(u'|u)
+        const Words4 w = draw(s, (uint32_t)p);
+        acc = log(uniform01(w.w0, w.w1)) < (s_new - s_old) + lq ? 1 : 0;
+    }
+    flags[p] = acc;
+}
+
+hipError_t launch_mala_propose(int prec, int64_t count, const void* u, const double* gsum,
+                               double coef, double eps, Stream s, void* up, hipStream_t st) {
+    const unsigned blocks = (unsigned)((count + 255) / 256);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_mala_propose<double>, dim3(blocks), dim3(256), 0, st, count,
+                           (const double*)u, gsum, coef, eps, s, (double*)up);
+    else
+        hipLaunchKernelGGL(k_mala_propose<float>, dim3(blocks), dim3(256), 0, st, count,
+                           (const float*)u, gsum, coef, eps, s, (float*)up);
+    return hipGetLastError();
+}
+
+hipError_t launch_mala_decide(int prec, int P, int N, int D, const void* u, const void* up,
+                              const double* g, const double* gprop, double coef, double eps,
+                              const double* logw, const double* logw_prop, Stream s,
+                              int32_t* flags, hipStream_t st) {
+    const unsigned blocks = (unsigned)((P + 255) / 256);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_mala_decide<double>, dim3(blocks), dim3(256), 0, st, P, N, D,
+                           (const double*)u, (const double*)up, g, gprop, coef, eps, logw,
+                           logw_prop, s, flags);
+    else
+        hipLaunchKernelGGL(k_mala_decide<float>, dim3(blocks), dim3(256), 0, st, P, N, D,
+                           (const float*)u, (const float*)up, g, gprop, coef, eps, logw,
+                           logw_prop, s, flags);
+    return hipGetLastError();
+}
+
+}  // namespace smc

@@ -201,6 +201,22 @@ hipError_t launch_propose(int prec, int64_t count, const void* u, void* u_prop,
     return hipGetLastError();
 }
 
+hipError_t launch_accept_apply(int prec, int P, int N, int D, void* u, const void* u_prop,
+                               double* chat, const double* chat_prop, uint8_t* feas_pn,
+                               const uint8_t* feas_prop, double* logw, const double* logw_prop,
+                               const int32_t* flags, hipStream_t st) {
+    const int64_t n = (int64_t)P * N * D;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_accept_apply<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st, P,
+                           N, D, (double*)u, (const double*)u_prop, chat, chat_prop, feas_pn,
+                           feas_prop, logw, logw_prop, flags);
+    else
+        hipLaunchKernelGGL(k_accept_apply<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st, P,
+                           N, D, (float*)u, (const float*)u_prop, chat, chat_prop, feas_pn,
+                           feas_prop, logw, logw_prop, flags);
+    return hipGetLastError();
+}
+
 hipError_t launch_accept(int prec, int P, int N, int D, void* u,
                          const void* u_prop, double* chat,
                          const double* chat_prop, uint8_t* feas_pn,

@@ -65,6 +65,7 @@ struct smc_ctx {
     double* d_scan = nullptr;
     double* d_ess = nullptr;
     int32_t* d_flags = nullptr;
+    double *d_g = nullptr, *d_g2 = nullptr, *d_gpart = nullptr;   // gradients (sum over samples)
     int32_t* d_best = nullptr;
     int32_t* d_status = nullptr;
     unsigned long long* d_steps = nullptr;
@@ -192,8 +193,12 @@ smc_status validate(const smc_scenario* s) {
         return fail(nullptr, SMC_EINVAL, "population grid needs >= 2 nodes per axis");
     if (s->precision != SMC_FP64 && s->precision != SMC_FP32)
         return fail(nullptr, SMC_EINVAL, "precision must be SMC_FP64 or SMC_FP32");
-    if (s->move != SMC_MOVE_JITTER && s->move != SMC_MOVE_RWMH)
-        return fail(nullptr, SMC_EINVAL, "move must be SMC_MOVE_JITTER or SMC_MOVE_RWMH");
+    if (s->move != SMC_MOVE_JITTER && s->move != SMC_MOVE_RWMH && s->move != SMC_MOVE_MALA)
+        return fail(nullptr, SMC_EINVAL, "move must be SMC_MOVE_JITTER, SMC_MOVE_RWMH or SMC_MOVE_MALA");
+    if (s->move == SMC_MOVE_MALA && !grad_supported(s->horizon_max, s->n_segments))
+        return fail(nullptr, SMC_EINVAL, "gradient move supports at most 16 segments and 400 steps");
+    if (s->move == SMC_MOVE_MALA && !(s->mala_step > 0))
+        return fail(nullptr, SMC_EINVAL, "mala_step must be > 0");
     if (!(s->kappa >= 0) || !(s->sigma_move >= 0))
         return fail(nullptr, SMC_EINVAL, "kappa and sigma_move must be >= 0");
     const double D = (double)s->n_particles * s->n_aircraft * s->n_segments * 3;
@@ -316,6 +321,45 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
                                     c->d_feaspn, c->d_feaspn2, c->d_logw, c->d_logw2,
                                     make_stream(c->seed, mpc_step, J, P_ACCEPT, c->scen_id),
                                     nullptr, c->d_flags, st));
+            if (info) {
+                hflags.resize(L);
+                HIP_OK(c, hipMemcpyAsync(hflags.data(), c->d_flags, sizeof(int32_t) * L,
+                                         hipMemcpyDeviceToHost, st));
+                HIP_OK(c, hipStreamSynchronize(st));
+                long a = 0;
+                for (int l = 0; l < L; ++l) a += hflags[l];
+                acc_sum += (double)a / L;
+                ++acc_n;
+            }
+        }
+        if (c->move == SMC_MOVE_MALA) {
+            // Langevin proposal with the drift of the tempered fuel + time
+            // cost; acceptance with the full target and the q ratio
+            const double coef = -beta / (double)c->M;
+            const double eps = c->mala_step;
+            HIP_OK(c, launch_rollout_grad(c->prec, rp, u, c->d_W, d_states, d_kact, c->d_acpar,
+                                          c->d_targets, c->d_kind, c->d_gpart, c->d_g, st));
+            HIP_OK(c, launch_mala_propose(c->prec, count, u, c->d_g, coef, eps,
+                                          make_stream(c->seed, mpc_step, J, P_MALA, c->scen_id),
+                                          c->d_up, st));
+            if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J + 2], st));
+            HIP_OK(c, do_rollout(c, rp,
+                                 rollout_arrays(c, c->d_up, c->d_W, d_states, d_kact, c->d_cost,
+                                                c->d_feas, steps),
+                                 st));
+            if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J + 3], st));
+            ++n_roll2;
+            HIP_OK(c, launch_reduce(L, c->M, N, c->d_cost, c->d_feas, beta, c->d_chat2,
+                                    c->d_feaspn2, c->d_logw2, st));
+            HIP_OK(c, launch_rollout_grad(c->prec, rp, c->d_up, c->d_W, d_states, d_kact, c->d_acpar,
+                                          c->d_targets, c->d_kind, c->d_gpart, c->d_g2, st));
+            HIP_OK(c, launch_mala_decide(c->prec, L, N, D, u, c->d_up, c->d_g, c->d_g2, coef, eps,
+                                         c->d_logw, c->d_logw2,
+                                         make_stream(c->seed, mpc_step, J, P_ACCEPT, c->scen_id),
+                                         c->d_flags, st));
+            HIP_OK(c, launch_accept_apply(c->prec, L, N, D, u, c->d_up, c->d_chat, c->d_chat2,
+                                          c->d_feaspn, c->d_feaspn2, c->d_logw, c->d_logw2,
+                                          c->d_flags, st));
             if (info) {
                 hflags.resize(L);
                 HIP_OK(c, hipMemcpyAsync(hflags.data(), c->d_flags, sizeof(int32_t) * L,
@@ -506,7 +550,7 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         (st = dalloc(c, &c->d_Lfac, G * G * c->rsz)) || (st = dalloc(c, &c->d_Z, G * 2 * M * c->rsz)) ||
         (st = dalloc(c, &c->d_W, M * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_u, L * N * D * c->rsz)) ||
         (st = dalloc(c, &c->d_u2, L * N * D * c->rsz)) ||
-        (st = dalloc(c, &c->d_up, (c->move == SMC_MOVE_RWMH ? L : 1) * N * D * c->rsz)) ||
+        (st = dalloc(c, &c->d_up, (c->move != SMC_MOVE_JITTER ? L : 1) * N * D * c->rsz)) ||
         (st = dalloc_t(c, &c->d_cost, M * L * N)) || (st = dalloc_t(c, &c->d_feas, M * L * N)) ||
         (st = dalloc_t(c, &c->d_chat, L * N)) || (st = dalloc_t(c, &c->d_logw, L * N)) ||
         (st = dalloc_t(c, &c->d_chat2, L * N)) || (st = dalloc_t(c, &c->d_logw2, L * N)) ||
@@ -521,6 +565,12 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         (st = dalloc_t(c, &d_Lz, (size_t)c->nz * c->nz)))
         return bail(st);
     if ((st = dalloc(c, &c->d_acR, N * kAcR * c->rsz))) return bail(st);
+    {
+        const size_t gl = (c->move == SMC_MOVE_MALA ? L : 1) * N * D;
+        if ((st = dalloc_t(c, &c->d_g, gl)) || (st = dalloc_t(c, &c->d_g2, gl)) ||
+            (st = dalloc_t(c, &c->d_gpart, c->M > 64 ? grad_partial_elems((int)L, (int)N, c->S, (int)M) : 1)))
+            return bail(st);
+    }
     if (c->use_noise || s->popdense) {
         if ((st = dalloc_t(c, &c->d_pop, (size_t)c->pop_nx * c->pop_ny))) return bail(st);
     }
@@ -765,6 +815,55 @@ smc_status smc_k_accept(smc_ctx* c, int32_t P, void* u, const void* u_prop, doub
                             logw, logw_prop,
                             make_stream(c->seed, mpc_step, iter, P_ACCEPT, c->scen_id), accepted,
                             c->d_flags, pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_rollout_grad(smc_ctx* c, const void* u, int32_t P, const void* W,
+                              const double* states, const int32_t* k_active, int32_t horizon,
+                              double* grad, void* stream) {
+    if (!c || !u || !W || !states || !k_active || !grad || P < 1)
+        return fail(c, SMC_EINVAL, "smc_k_rollout_grad: bad arguments");
+    smc_status vs = check_horizon(c, horizon);
+    if (vs) return vs;
+    if (!grad_supported(horizon, c->S))
+        return fail(c, SMC_EINVAL, "gradient supports at most 16 segments and 400 steps");
+    if (c->M > 64 && P > c->L)
+        return fail(c, SMC_EINVAL, "smc_k_rollout_grad: P exceeds n_particles with more than 64 samples");
+    RolloutParams rp = c->rp;
+    rp.H = horizon;
+    rp.P = P;
+    HIP_OK(c, launch_rollout_grad(c->prec, rp, u, W, states, k_active, c->d_acpar, c->d_targets,
+                                  c->d_kind, c->d_gpart, grad, pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_mala_propose(smc_ctx* c, int32_t P, const void* u, const double* grad,
+                              double beta, void* u_prop, int64_t mpc_step, int32_t iter,
+                              void* stream) {
+    if (!c || !u || !grad || !u_prop || P < 1) return fail(c, SMC_EINVAL, "smc_k_mala_propose: bad arguments");
+    HIP_OK(c, launch_mala_propose(c->prec, (int64_t)P * c->N * c->S * 3, u, grad,
+                                  -beta / (double)c->M, c->mala_step,
+                                  make_stream(c->seed, mpc_step, iter, P_MALA, c->scen_id), u_prop,
+                                  pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_mala_accept(smc_ctx* c, int32_t P, void* u, const void* u_prop, const double* grad,
+                             const double* grad_prop, double beta, double* chat,
+                             const double* chat_prop, uint8_t* feas_pn, const uint8_t* feas_prop,
+                             double* logw, const double* logw_prop, int64_t mpc_step, int32_t iter,
+                             int32_t* accepted, void* stream) {
+    if (!c || !u || !u_prop || !grad || !grad_prop || !chat || !chat_prop || !feas_pn || !feas_prop ||
+        !logw || !logw_prop || !accepted || P < 1)
+        return fail(c, SMC_EINVAL, "smc_k_mala_accept: bad arguments");
+    const int D = c->S * 3;
+    hipStream_t st = pick(c, stream);
+    HIP_OK(c, launch_mala_decide(c->prec, P, c->N, D, u, u_prop, grad, grad_prop, -beta / (double)c->M,
+                                 c->mala_step, logw, logw_prop,
+                                 make_stream(c->seed, mpc_step, iter, P_ACCEPT, c->scen_id), accepted,
+                                 st));
+    HIP_OK(c, launch_accept_apply(c->prec, P, c->N, D, u, u_prop, chat, chat_prop, feas_pn, feas_prop,
+                                  logw, logw_prop, accepted, st));
     return SMC_OK;
 }
 

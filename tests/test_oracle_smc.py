@@ -59,3 +59,24 @@ def test_jitter_stays_in_box_and_init_uniform():
     assert abs(d.std() - s["sigma_move"]) < 0.001
     r = smc.reflect(np.array([-0.25, 0.5, 1.25, 2.5, -1.5]))
     assert np.allclose(r, [0.25, 0.5, 0.75, 0.5, 0.5])
+
+
+def test_toy_quadratic_mala():
+    """Langevin moves with the exact toy gradient recover the minimiser."""
+    s = mini(N=2, S=2, L=256)
+    s.update(K=30, move=2, seed=5, kappa=1.0, mala_step=0.05)
+    rng = np.random.default_rng(9)
+    target = rng.uniform(0.25, 0.75, (2, 2, 3))
+    A = rng.uniform(40.0, 120.0, (2, 6))
+
+    def evaluate(u, J):
+        d = (u - target[None]).reshape(u.shape[0], 2, 6)
+        return 0.5 * (A[None] * d * d).sum(-1), np.ones((u.shape[0], 2), bool)
+
+    def grad(u, J):
+        d = (u - target[None]).reshape(u.shape[0], 2, 6)
+        return (A[None] * d).reshape(u.shape)
+
+    res = smc.run_smc(s, evaluate, 256, 30, 2, 2, grad=grad)
+    assert np.abs(res["u"][res["best"]] - target).max() < 0.06
+    assert 0.0 < np.mean(res["acc_rate"]) < 1.0
