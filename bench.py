@@ -55,7 +55,7 @@ def _src_hash(*names):
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel_src: str, key: str, launches_bytes_alg: float):
+def traffic_for(kernel_src: tuple, key: str, launches_bytes_alg: float):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, or
     None when absent or taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", "rollout_c2_traffic.json")
@@ -63,7 +63,7 @@ def traffic_for(kernel_src: str, key: str, launches_bytes_alg: float):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_hash") != _src_hash(kernel_src):
+    if t.get("source_hash") != _src_hash(*kernel_src):
         return None
     return t.get(key)
 
@@ -182,8 +182,9 @@ def main():
     fp64 = scen["precision"] == 0
     peak = PEAK_FP64_VECTOR_TFLOPS if fp64 else PEAK_FP32_VECTOR_TFLOPS
     wm = N <= 16     # the library picks the world-per-lane rollout up to 16 aircraft
-    kname, ksrc = (("k_rollout_wm", "kernels_rollout_wm.hip") if wm
-                   else ("k_rollout", "kernels_rollout.hip"))
+    kname, ksrc = ((
+        "k_rollout_wm", ("kernels_rollout_wm.hip", "rollout_wm_body.inc", "rollout_math.h"))
+        if wm else ("k_rollout", ("kernels_rollout.hip", "rollout_math.h")))
     roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 3),
             "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": traffic_for(ksrc, "bytes_per_launch", flops_launch),

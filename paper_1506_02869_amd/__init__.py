@@ -1,8 +1,8 @@
 """Python binding of the MI355X SMC-MPC engine (libsmc_mpc.so).
 
 Argument marshalling only: every step of the optimiser runs in the HIP
-kernels behind the C ABI declared in include/smc_mpc.h and
-include/smc_kernels.h.  Function names follow the C ABI.  Device arrays are
+kernels behind the C ABI declared in include/smc_mpc.h,
+include/smc_kernels.h and include/smc_batch.h.  Function names follow the C ABI.  Device arrays are
 torch tensors on a HIP device (PyTorch provides device memory and streams);
 host arrays are NumPy arrays.
 
@@ -69,7 +69,41 @@ class StepInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+BATCH_BUCKETS = 8
+BATCH_BUCKET_NMAX = (2, 4, 6, 8, 10, 12, 16, 20)
+BATCH_ITEM_WORLDS = 64
+
+
+class BatchTuning(C.Structure):
+    _fields_ = [("block", C.c_int32 * BATCH_BUCKETS), ("grid_mult", C.c_int32 * BATCH_BUCKETS),
+                ("order", C.c_int32)]
+
+    def as_dict(self):
+        return {"block": list(self.block), "grid_mult": list(self.grid_mult),
+                "order": int(self.order)}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        t.block[:] = [int(v) for v in d.get("block", [0] * BATCH_BUCKETS)]
+        t.grid_mult[:] = [int(v) for v in d.get("grid_mult", [0] * BATCH_BUCKETS)]
+        t.order = int(d.get("order", 0))
+        return t
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("n_scenarios", C.c_int32), ("iterations", C.c_int32),
+                ("aircraft_steps", C.c_int64), ("pair_tests", C.c_int64),
+                ("ms_total", C.c_double), ("accept_rate", C.c_double),
+                ("feasible_frac", C.c_double), ("graph", C.c_int32),
+                ("rollout_launches", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _VP = C.c_void_p
+_I32P = C.POINTER(C.c_int32)
 _SIGS = {
     "smc_version": (C.c_char_p, []),
     "smc_last_error": (C.c_char_p, [_VP]),
@@ -104,6 +138,20 @@ _SIGS = {
                                      C.c_int32, _VP]),
     "smc_k_mala_accept": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, C.c_double, _VP, _VP,
                                     _VP, _VP, _VP, _VP, C.c_int64, C.c_int32, _VP, _VP]),
+    "smc_batch_init": (C.c_int, [C.POINTER(Scenario), C.c_int32, C.POINTER(_VP)]),
+    "smc_batch_step": (C.c_int, [_VP, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                 C.POINTER(BatchInfo)]),
+    "smc_batch_step_dev": (C.c_int, [_VP, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                     C.POINTER(BatchInfo), _VP]),
+    "smc_batch_set_graph": (C.c_int, [_VP, C.c_int32]),
+    "smc_batch_get_tuning": (C.c_int, [_VP, C.POINTER(BatchTuning)]),
+    "smc_batch_set_tuning": (C.c_int, [_VP, C.POINTER(BatchTuning)]),
+    "smc_batch_autotune": (C.c_int, [_VP, C.c_int64, _VP, _VP, _VP, _VP, C.c_int32,
+                                     C.POINTER(BatchTuning)]),
+    "smc_batch_plan": (C.c_int, [C.c_int32, _VP, _VP, C.c_int32, C.c_int32, C.c_int32, _VP, _VP,
+                                 _VP, _VP, C.c_int64, C.POINTER(C.c_int64)]),
+    "smc_batch_last_error": (C.c_char_p, [_VP]),
+    "smc_batch_destroy": (None, [_VP]),
 }
 
 _lib = None
@@ -395,3 +443,220 @@ def smc_k_mala_accept(ctx, P, u, u_prop, grad, grad_prop, beta, chat, chat_prop,
                                    _ptr(feas_pn), _ptr(feas_prop), _ptr(logw), _ptr(logw_prop),
                                    int(mpc_step), int(iter_), _ptr(accepted), _stream(stream)),
            ctx)
+
+
+# ---- batched form (include/smc_batch.h) --------------------------------------
+
+def _bcheck(status, batch=None):
+    if status < 0:
+        msg = lib().smc_batch_last_error(batch.handle if batch is not None else None)
+        raise SmcError(status, (msg or b"").decode())
+    return status
+
+
+class Batch:
+    """Owns an smc_batch*; created by smc_batch_init.  Per-scenario arrays
+    are concatenated in scenario order (see include/smc_batch.h)."""
+
+    def __init__(self, handle, scens):
+        self.handle = handle
+        self.scens = scens
+        self.ns = len(scens)
+        self.N = [int(s["N"]) for s in scens]
+        self.S = [int(s["S"]) for s in scens]
+        self.H = [int(s["H"]) for s in scens]
+        self.ctrl_off = np.concatenate([[0], np.cumsum([n * k * 3 for n, k in
+                                                        zip(self.N, self.S)])]).astype(np.int64)
+        self.cost_off = np.concatenate([[0], np.cumsum([1 + n for n in self.N])]).astype(np.int64)
+        self.row_off = np.concatenate([[0], np.cumsum(self.N)]).astype(np.int64)
+
+    def split(self, controls, costs):
+        """Per-scenario ([N, S, 3] controls, [1 + N] costs) from the
+        concatenated outputs."""
+        out = []
+        for s in range(self.ns):
+            c = controls[self.ctrl_off[s]:self.ctrl_off[s + 1]].reshape(self.N[s], self.S[s], 3)
+            out.append((c, costs[self.cost_off[s]:self.cost_off[s + 1]]))
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().smc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def smc_batch_init(scens) -> Batch:
+    arr = (Scenario * len(scens))()
+    keep = []
+    for k, s in enumerate(scens):
+        sc, kp = make_scenario_struct(s)
+        arr[k] = sc
+        keep.append(kp)
+    h = C.c_void_p()
+    st = lib().smc_batch_init(arr, len(scens), C.byref(h))
+    if st < 0:
+        raise SmcError(st, (lib().smc_batch_last_error(None) or b"").decode())
+    b = Batch(h, scens)
+    b._keep = keep
+    return b
+
+
+def _batch_inputs(b: Batch, states, k_active, wind_mean, horizons):
+    sc = b.scens
+    states = np.concatenate([s["states"] for s in sc]) if states is None else states
+    k_active = np.concatenate([s["k_active"] for s in sc]) if k_active is None else k_active
+    wind_mean = np.stack([s["wind_mean"] for s in sc]) if wind_mean is None else wind_mean
+    horizons = np.array(b.H) if horizons is None else horizons
+    return (_hp(states, np.float64), _hp(k_active, np.int32), _hp(wind_mean, np.float64),
+            _hp(horizons, np.int32))
+
+
+def smc_batch_step(b: Batch, mpc_step=0, states=None, k_active=None, wind_mean=None,
+                   horizons=None):
+    """Host form: returns (controls [sum N S 3], costs [sum (1 + N)],
+    status [n_scen], return code, info dict)."""
+    (st_a, p_st), (ka_a, p_ka), (wm_a, p_wm), (h_a, p_h) = _batch_inputs(
+        b, states, k_active, wind_mean, horizons)
+    ctrl = np.zeros(int(b.ctrl_off[-1]))
+    cost = np.zeros(int(b.cost_off[-1]))
+    status = np.zeros(b.ns, dtype=np.int32)
+    info = BatchInfo()
+    r = lib().smc_batch_step(b.handle, int(mpc_step), p_st, p_ka, p_wm, p_h,
+                             ctrl.ctypes.data_as(C.c_void_p), cost.ctypes.data_as(C.c_void_p),
+                             status.ctypes.data_as(C.c_void_p), C.byref(info))
+    _bcheck(r, b)
+    return ctrl, cost, status, r, info.as_dict()
+
+
+def smc_batch_step_dev(b: Batch, mpc_step, states, k_active, wind_mean, horizons, controls_out,
+                       cost_out, status_out=None, want_info=False, stream=None):
+    """Device form: states [sum N, 6] f64, k_active [sum N] i32 and the
+    outputs are device tensors; wind_mean [n_scen, 2] and horizons are host."""
+    wm_a, p_wm = _hp(wind_mean, np.float64)
+    h_a, p_h = _hp(horizons, np.int32)
+    info = BatchInfo() if want_info else None
+    r = lib().smc_batch_step_dev(b.handle, int(mpc_step), _ptr(states), _ptr(k_active), p_wm,
+                                 p_h, _ptr(controls_out), _ptr(cost_out), _ptr(status_out),
+                                 C.byref(info) if info is not None else None, _stream(stream))
+    _bcheck(r, b)
+    return r, (info.as_dict() if info is not None else None)
+
+
+def smc_batch_set_graph(b: Batch, enable: bool):
+    _bcheck(lib().smc_batch_set_graph(b.handle, 1 if enable else 0), b)
+
+
+def smc_batch_get_tuning(b: Batch) -> dict:
+    t = BatchTuning()
+    _bcheck(lib().smc_batch_get_tuning(b.handle, C.byref(t)), b)
+    return t.as_dict()
+
+
+def smc_batch_set_tuning(b: Batch, tuning: dict):
+    t = BatchTuning.from_dict(tuning)
+    _bcheck(lib().smc_batch_set_tuning(b.handle, C.byref(t)), b)
+
+
+def smc_batch_autotune(b: Batch, mpc_step=0, states=None, k_active=None, wind_mean=None,
+                       horizons=None, reps=3) -> dict:
+    (st_a, p_st), (ka_a, p_ka), (wm_a, p_wm), (h_a, p_h) = _batch_inputs(
+        b, states, k_active, wind_mean, horizons)
+    t = BatchTuning()
+    _bcheck(lib().smc_batch_autotune(b.handle, int(mpc_step), p_st, p_ka, p_wm, p_h, int(reps),
+                                     C.byref(t)), b)
+    return t.as_dict()
+
+
+def smc_batch_plan(n_aircraft, horizons, n_particles, n_wind, order=0):
+    """Host-only work plan: (bucket_start [8], bucket_count [8], item_scen,
+    item_world0)."""
+    na, p_na = _hp(n_aircraft, np.int32)
+    hz, p_hz = _hp(horizons, np.int32)
+    bs = np.zeros(BATCH_BUCKETS, dtype=np.int32)
+    bc = np.zeros(BATCH_BUCKETS, dtype=np.int32)
+    n = C.c_int64()
+    per = -(-int(n_particles) * int(n_wind) // BATCH_ITEM_WORLDS)
+    cap = per * len(na)
+    isc = np.zeros(cap, dtype=np.int32)
+    iw = np.zeros(cap, dtype=np.int32)
+    _bcheck(lib().smc_batch_plan(len(na), p_na, p_hz, int(n_particles), int(n_wind), int(order),
+                                 bs.ctypes.data_as(C.c_void_p), bc.ctypes.data_as(C.c_void_p),
+                                 isc.ctypes.data_as(C.c_void_p), iw.ctypes.data_as(C.c_void_p),
+                                 cap, C.byref(n)))
+    return bs, bc, isc[:n.value], iw[:n.value]
+
+
+# ---- autotune cache (host logic) -----------------------------------------------
+
+def tuning_key(scens, device_name: str) -> str:
+    """Cache key of a batch's launch shapes: device, precision, sizes and
+    the bucket histogram with horizons (what the rollout's speed depends on)."""
+    import hashlib
+    s0 = scens[0]
+    parts = [device_name, f"p{int(s0['precision'])}", f"L{int(s0['L'])}", f"M{int(s0['M'])}",
+             f"m{int(s0['move'])}"]
+    parts += [f"{int(s['N'])}x{int(s['H'])}" for s in sorted(
+        scens, key=lambda s: (int(s["N"]), int(s["H"])))]
+    return hashlib.sha256("|".join(parts).encode()).hexdigest()[:24]
+
+
+def load_tuning(path: str, key: str):
+    """Tuning dict stored under key in the JSON cache at path, or None."""
+    import json
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        try:
+            data = json.load(f)
+        except json.JSONDecodeError:
+            return None
+    t = data.get(key)
+    if not isinstance(t, dict):
+        return None
+    ok = (len(t.get("block", [])) == BATCH_BUCKETS and
+          len(t.get("grid_mult", [])) == BATCH_BUCKETS and
+          all(v in (0, 64, 128, 256) for v in t["block"]) and
+          all(0 <= v <= 4 for v in t["grid_mult"]) and t.get("order", 0) in (0, 1))
+    return t if ok else None
+
+
+def save_tuning(path: str, key: str, tuning: dict):
+    """Store tuning under key in the JSON cache at path (atomic replace)."""
+    import json
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            try:
+                data = json.load(f)
+            except json.JSONDecodeError:
+                data = {}
+    data[key] = {"block": [int(v) for v in tuning["block"]],
+                 "grid_mult": [int(v) for v in tuning["grid_mult"]],
+                 "order": int(tuning.get("order", 0))}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def batch_tune(b: Batch, cache_path=None, device_name=None, reps=3, **inputs) -> dict:
+    """Install a cached tuning for this batch shape, or autotune and cache it."""
+    if cache_path:
+        if device_name is None:
+            import torch
+            device_name = torch.cuda.get_device_name(0)
+        key = tuning_key(b.scens, device_name)
+        t = load_tuning(cache_path, key)
+        if t is not None:
+            smc_batch_set_tuning(b, t)
+            return t
+    t = smc_batch_autotune(b, reps=reps, **inputs)
+    if cache_path:
+        save_tuning(cache_path, key, t)
+    return t

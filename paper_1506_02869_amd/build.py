@@ -20,8 +20,8 @@ OUT = os.path.join(PKG, "libsmc_mpc.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["kernels_rng.hip", "kernels_wind.hip", "kernels_rollout.hip",
-           "kernels_rollout_wm.hip", "kernels_grad.hip", "kernels_smc.hip",
-           "smc_mpc.cpp"]
+           "kernels_rollout_wm.hip", "kernels_rollout_batch.hip", "kernels_grad.hip",
+           "kernels_smc.hip", "kernels_batch.hip", "smc_mpc.cpp", "smc_batch.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -10,7 +10,7 @@ namespace smc {
 
 constexpr int kMaxAircraft = 64;
 constexpr int kStepSlots = 64;   // striped counters of simulated aircraft-steps
-constexpr int kWorldLaneMaxN = 16;  // largest N of the world-per-lane rollout
+constexpr int kWorldLaneMaxN = 20;  // largest N of the world-per-lane rollout
 constexpr int kAcR = 16;            // per-aircraft parameters in the rollout's precision
 
 // Scalars of one rollout launch (uniform over the grid; kernel argument).
@@ -41,6 +41,55 @@ struct RolloutArrays {
     double* cost;             // [M][P][N]
     uint8_t* feas;            // [M][P][N]
     unsigned long long* steps;  // [2 kStepSlots] or null: aircraft-steps, pair tests
+};
+
+// Control box: physical control c = lo[c] + normalised * sp[c].
+struct Ctrl3 {
+    double lo[3], sp[3];
+};
+
+// ---- batched form: many scenarios per launch ---------------------------------
+// Buckets of the world-per-lane rollout (compile-time aircraft capacity).
+constexpr int kNumBuckets = 8;
+__host__ __device__ constexpr int bucket_nmax(int b) {
+    return b == 0 ? 2 : b == 1 ? 4 : b == 2 ? 6 : b == 3 ? 8 : b == 4 ? 10 : b == 5 ? 12
+         : b == 6 ? 16 : 20;
+}
+inline int bucket_of(int N) {
+    for (int b = 0; b < kNumBuckets; ++b)
+        if (N <= bucket_nmax(b)) return b;
+    return -1;
+}
+constexpr int kItemWorlds = 64;   // worlds (particle, wind sample) per work item: one wave
+
+// One scenario of a batch (device table).  The rollout's scalars and arrays
+// (ra.u unused: each launch passes the control base pointer, and the
+// scenario's controls start off_u elements after it), its per-aircraft rows,
+// the tempering of every iteration and the offsets of its slices in the
+// concatenated buffers of the batch.
+struct BatchScen {
+    RolloutParams rp;      // P = particles, H = this step's horizon
+    RolloutArrays ra;      // cost / feas: this scenario's [M][P][N] slices
+    const void* acR;       // [N][kAcR] real
+    const double* beta;    // [K] beta_J = kappa floor(3 + 5 exp(0.05 J))
+    uint64_t seed;
+    int scen_id, N, S, D;  // D = 3 S controls per aircraft
+    int off_n;             // first aircraft row of the scenario (states, k_active, resampling)
+    int64_t off_u;         // controls [P][N][D]
+    int64_t off_pn;        // per-particle rows [P][N] (c_hat, log-weights, feasibility)
+    int64_t off_ctrl;      // returned controls [N][D]
+    int64_t off_cost;      // returned expected costs [1 + N]
+    double sigma_move;
+    Ctrl3 box;
+};
+
+struct BatchItem {
+    int scen;              // scenario of the item
+    int world0;            // first world (l + P m) of the item's kItemWorlds
+};
+
+struct BatchStep {
+    int64_t mpc_step;      // Philox counter word 3 of every draw of the step
 };
 
 // precision: 0 = double, 1 = float
@@ -102,6 +151,45 @@ hipError_t launch_accept(int prec, int P, int N, int D, void* u,
                          int32_t* flags, hipStream_t st);
 hipError_t launch_select(int P, int N, const double* logw, const double* chat,
                          double beta, int32_t* best, hipStream_t st);
+hipError_t launch_wind_gemm_grouped(int prec, const void* Lfac, const void* Z,
+                                    const double* wmean, int mper, int G, int M, void* W,
+                                    hipStream_t st);
+
+// batched launches: grids span every scenario of the table (ns entries)
+hipError_t launch_b_fill(uint32_t* p, int64_t n, hipStream_t st);
+hipError_t launch_b_init(int prec, const BatchScen* tab, const BatchStep* hdr, int ns,
+                         int64_t max_count, void* u, hipStream_t st);
+hipError_t launch_b_normals(int prec, const BatchScen* tab, const BatchStep* hdr, int ns, int J,
+                            int G, int M, void* Z, hipStream_t st);
+// persistent world-per-lane rollout over the items of one bucket
+hipError_t launch_b_rollout(int prec, int bucket, const BatchScen* tab, const BatchItem* items,
+                            int n_items, uint32_t* queue, const void* u,
+                            unsigned long long* steps, int block, int grid, hipStream_t st);
+int b_rollout_resident(int prec, int bucket, int block);   // workgroups per CU
+hipError_t launch_b_reduce(const BatchScen* tab, int ns, int J, int64_t max_pn, double* chat,
+                           uint8_t* feas_pn, double* logw, hipStream_t st);
+hipError_t launch_b_resample_offsets(const BatchScen* tab, const BatchStep* hdr,
+                                     const int32_t* row_scen, int rows, int J, uint32_t* U,
+                                     hipStream_t st);
+hipError_t launch_b_resample(const BatchScen* tab, const int32_t* row_scen, int rows, int P,
+                             const double* logw, const uint32_t* U, double* scan, int32_t* anc,
+                             hipStream_t st);
+hipError_t launch_b_gather_move(int prec, const BatchScen* tab, const BatchStep* hdr, int ns,
+                                int J, int64_t max_count, const void* u_in, const int32_t* anc,
+                                void* u_out, int jitter, hipStream_t st);
+hipError_t launch_b_propose(int prec, const BatchScen* tab, const BatchStep* hdr, int ns, int J,
+                            int64_t max_count, const void* u, void* u_prop, hipStream_t st);
+hipError_t launch_b_accept(int prec, const BatchScen* tab, const BatchStep* hdr, int ns, int J,
+                           int P, int64_t max_count, void* u, const void* u_prop, double* chat,
+                           const double* chat_prop, uint8_t* feas_pn, const uint8_t* feas_prop,
+                           double* logw, const double* logw_prop, int32_t* flags,
+                           uint32_t* accepted, hipStream_t st);
+hipError_t launch_b_select(const BatchScen* tab, int ns, int J, int P, const double* logw,
+                           const double* chat, int32_t* best, hipStream_t st);
+hipError_t launch_b_write_result(int prec, const BatchScen* tab, int ns, const void* u,
+                                 const int32_t* best, const double* chat, double* controls_out,
+                                 double* cost_out, int32_t* status_out, hipStream_t st);
+
 hipError_t launch_write_result(int prec, int N, int S, const void* u,
                                const int32_t* best, const double* chat,
                                const double* ctrl_lo, const double* ctrl_span,

@@ -1,12 +1,9 @@
 // Counter-based random draws of the SMC loop and the moves built on them:
 // Philox words, particle initialisation, wind normals, resampling offsets,
 // gather + jitter, random-walk proposals and Metropolis acceptance.
-#include "engine.h"
+#include "smc_steps.h"
 
 namespace smc {
-
-template <typename R>
-__device__ __forceinline__ R to_real(double x) { return (R)x; }
 
 __global__ void k_philox_words(Stream s, uint32_t e0, int64_t n, uint32_t* out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -21,8 +18,7 @@ template <typename R>
 __global__ void k_init_particles(Stream s, int64_t count, R* u) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
-    const Words4 w = draw(s, (uint32_t)e);
-    u[e] = to_real<R>(uniform01(w.w0, w.w1));
+    u[e] = to_real<R>(init_value(s, (uint32_t)e));
 }
 
 // Z[g][2m + c]: thread per (g, m) with m fastest so that the pair of
@@ -33,12 +29,7 @@ __global__ void k_wind_normals(Stream s, int G, int M, R* Z) {
     if (t >= (int64_t)G * M) return;
     const int m = (int)(t % M);
     const int g = (int)(t / M);
-    const Words4 w = draw(s, (uint32_t)((int64_t)m * G + g));
-    double z0, z1;
-    normal_pair(w, z0, z1);
-    R* dst = Z + (int64_t)g * (2 * M) + 2 * m;
-    dst[0] = to_real<R>(z0);
-    dst[1] = to_real<R>(z1);
+    normals_at<R>(s, G, g, m, Z + (int64_t)g * (2 * M) + 2 * m);
 }
 
 __global__ void k_resample_offsets(Stream s, int N, uint32_t* U) {
@@ -47,8 +38,6 @@ __global__ void k_resample_offsets(Stream s, int N, uint32_t* U) {
     U[i] = draw(s, (uint32_t)i).w0;
 }
 
-// u_out[k][i][:] = u_in[anc[i][k]][i][:], then the paper's Gaussian
-// white-noise perturbation (clamped to the control box) if jitter != 0.
 // Thread per element (k, i, d), d over the D = 3 S controls of an aircraft.
 template <typename R>
 __global__ void k_gather_move(int P, int N, int D, const R* __restrict__ u_in,
@@ -56,61 +45,26 @@ __global__ void k_gather_move(int P, int N, int D, const R* __restrict__ u_in,
                               R* __restrict__ u_out, Stream s, double sigma,
                               int jitter) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)P * N * D;
-    if (e >= total) return;
-    const int d = (int)(e % D);
-    const int64_t ki = e / D;
-    const int i = (int)(ki % N);
-    const int k = (int)(ki / N);
-    const int src = anc[(int64_t)i * P + k];
-    double v = (double)u_in[((int64_t)src * N + i) * D + d];
-    if (jitter) {
-        double z0, z1;
-        normal_pair(draw(s, (uint32_t)e), z0, z1);
-        v = fmin(fmax(v + sigma * z0, 0.0), 1.0);
-    }
-    u_out[e] = to_real<R>(v);
+    if (e >= (int64_t)P * N * D) return;
+    gather_move_at<R>(e, P, N, D, u_in, anc, u_out, s, sigma, jitter);
 }
 
-// u' = reflect(u + sigma xi): reflection of the real line into [0, 1]
-// (period 2), so the proposal density stays symmetric.
 template <typename R>
 __global__ void k_propose(int64_t count, const R* __restrict__ u,
                           R* __restrict__ up, Stream s, double sigma) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
-    double z0, z1;
-    normal_pair(draw(s, (uint32_t)e), z0, z1);
-    const double v = (double)u[e] + sigma * z0;
-    double r = v - 2.0 * floor(v * 0.5);
-    if (r > 1.0) r = 2.0 - r;
-    up[e] = to_real<R>(r);
+    propose_at<R>(e, u, up, s, sigma);
 }
 
-// Metropolis decision per particle on the joint target prod_i W_i.
 __global__ void k_accept_decide(int P, int N, const double* __restrict__ logw,
                                 const double* __restrict__ logw_prop, Stream s,
                                 int32_t* __restrict__ flags) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    double s_new = 0.0, s_old = 0.0;
-    for (int i = 0; i < N; ++i) {
-        s_new += logw_prop[(int64_t)p * N + i];
-        s_old += logw[(int64_t)p * N + i];
-    }
-    int acc;
-    if (s_new == -INFINITY) {
-        acc = 0;
-    } else if (s_old == -INFINITY) {
-        acc = 1;
-    } else {
-        const Words4 w = draw(s, (uint32_t)p);
-        acc = log(uniform01(w.w0, w.w1)) < (s_new - s_old) ? 1 : 0;
-    }
-    flags[p] = acc;
+    flags[p] = accept_decide_at(p, N, logw, logw_prop, s);
 }
 
-// Replace accepted particles' controls and per-aircraft rows.
 template <typename R>
 __global__ void k_accept_apply(int P, int N, int D, R* __restrict__ u,
                                const R* __restrict__ up,
@@ -122,18 +76,8 @@ __global__ void k_accept_apply(int P, int N, int D, R* __restrict__ u,
                                const double* __restrict__ logw_prop,
                                const int32_t* __restrict__ flags) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per = (int64_t)N * D;
-    if (e >= (int64_t)P * per) return;
-    const int p = (int)(e / per);
-    if (!flags[p]) return;
-    u[e] = up[e];
-    const int64_t r = e - (int64_t)p * per;
-    if (r < N) {
-        const int64_t j = (int64_t)p * N + r;
-        chat[j] = chat_prop[j];
-        feas[j] = feas_prop[j];
-        logw[j] = logw_prop[j];
-    }
+    if (e >= (int64_t)P * N * D) return;
+    accept_apply_at<R>(e, N, D, u, up, chat, chat_prop, feas, feas_prop, logw, logw_prop, flags);
 }
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }

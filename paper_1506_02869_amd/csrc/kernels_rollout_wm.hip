@@ -19,10 +19,6 @@
 
 namespace smc {
 
-// Occupancy target per bucket: the state takes about 8 VGPRs per aircraft.
-template <typename R, int NMAX>
-constexpr int wm_waves() { return sizeof(R) == 4 ? (NMAX <= 4 ? 4 : (NMAX <= 10 ? 3 : 2)) : 1; }
-
 template <typename R, int NMAX>
 __global__ void __launch_bounds__(256, (wm_waves<R, NMAX>()))
 k_rollout_wm(const RolloutParams p, const RolloutArrays a, const R* __restrict__ acR) {
@@ -36,7 +32,7 @@ k_rollout_wm(const RolloutParams p, const RolloutArrays a, const R* __restrict__
 }
 
 // 256 lanes per block in FP32, 128 in FP64: the staged controls take
-// N * 3 * block * sizeof(R) bytes of LDS (48 KB at N = 16 either way).
+// N * 3 * block * sizeof(R) bytes of LDS (60 KB at N = 20 either way).
 template <typename R, int NMAX>
 static hipError_t launch_wm_n(const RolloutParams& p, const RolloutArrays& a, const void* acR,
                               hipStream_t st) {
@@ -58,7 +54,8 @@ static hipError_t launch_wm_t(const RolloutParams& p, const RolloutArrays& a, co
     if (p.N <= 8) return launch_wm_n<R, 8>(p, a, acR, st);
     if (p.N <= 10) return launch_wm_n<R, 10>(p, a, acR, st);
     if (p.N <= 12) return launch_wm_n<R, 12>(p, a, acR, st);
-    return launch_wm_n<R, 16>(p, a, acR, st);
+    if (p.N <= 16) return launch_wm_n<R, 16>(p, a, acR, st);
+    return launch_wm_n<R, 20>(p, a, acR, st);
 }
 
 bool rollout_wm_supported(int N) { return N >= 1 && N <= kWorldLaneMaxN; }

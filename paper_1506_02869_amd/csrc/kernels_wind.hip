@@ -122,7 +122,8 @@ __device__ __forceinline__ void gemm_store(const GemmStage<T>& st, T* As, T* Bs)
 template <typename T>
 __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* __restrict__ Z,
                                               int G, int NC, int rb, int cb, double wm0,
-                                              double wm1, T* __restrict__ W, T* As, T* Bs) {
+                                              double wm1, const double* __restrict__ wmean,
+                                              int mper, T* __restrict__ W, T* As, T* Bs) {
     typedef typename Mfma<T>::acc_t acc_t;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -157,7 +158,8 @@ __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* 
                                        Bs + (cur ^ 1) * (GB_K * GBB_LD));
         __syncthreads();
     }
-    // epilogue: element (g, col) -> W[m][g][c] with col = 2 m + c
+    // epilogue: element (g, col) -> W[m][g][c] with col = 2 m + c; the mean
+    // is (wm0, wm1), or wmean[2 (m / mper) + c] per group of mper samples
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int g = row0 + wr + Mfma<T>::row(lane, r);
@@ -166,11 +168,13 @@ __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* 
         const int c1 = c0 + 16;
         if (c0 < NC) {
             const int m = c0 >> 1, c = c0 & 1;
-            W[((int64_t)m * G + g) * 2 + c] = (T)((c ? wm1 : wm0) + (double)acc0[r]);
+            const double base = wmean ? wmean[2 * (m / mper) + c] : (c ? wm1 : wm0);
+            W[((int64_t)m * G + g) * 2 + c] = (T)(base + (double)acc0[r]);
         }
         if (c1 < NC) {
             const int m = c1 >> 1, c = c1 & 1;
-            W[((int64_t)m * G + g) * 2 + c] = (T)((c ? wm1 : wm0) + (double)acc1[r]);
+            const double base = wmean ? wmean[2 * (m / mper) + c] : (c ? wm1 : wm0);
+            W[((int64_t)m * G + g) * 2 + c] = (T)(base + (double)acc1[r]);
         }
     }
 }
@@ -178,17 +182,19 @@ __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* 
 template <typename T>
 __global__ void __launch_bounds__(256) k_wind_gemm(const T* __restrict__ A,
                                                    const T* __restrict__ Z, int G, int NC,
-                                                   double wm0, double wm1, T* __restrict__ W) {
+                                                   double wm0, double wm1,
+                                                   const double* __restrict__ wmean, int mper,
+                                                   T* __restrict__ W) {
     __shared__ T As[2 * GB_K * GA_LD];
     __shared__ T Bs[2 * GB_K * GBB_LD];
     const int R = (G + GB_M - 1) / GB_M;
     const int rb = blockIdx.x;
     const int rb2 = R - 1 - rb;
     const int cb = blockIdx.y;
-    gemm_rowblock<T>(A, Z, G, NC, rb2, cb, wm0, wm1, W, As, Bs);   // heavy block first
+    gemm_rowblock<T>(A, Z, G, NC, rb2, cb, wm0, wm1, wmean, mper, W, As, Bs);   // heavy first
     if (rb2 != rb) {
         __syncthreads();
-        gemm_rowblock<T>(A, Z, G, NC, rb, cb, wm0, wm1, W, As, Bs);
+        gemm_rowblock<T>(A, Z, G, NC, rb, cb, wm0, wm1, wmean, mper, W, As, Bs);
     }
 }
 
@@ -207,19 +213,32 @@ hipError_t launch_kron_expand(int prec, const double* Lx, const double* Ly,
     return hipGetLastError();
 }
 
-hipError_t launch_wind_gemm(int prec, const void* Lfac, const void* Z, double wm0,
-                            double wm1, int G, int M, void* W, hipStream_t st) {
+static hipError_t wind_gemm(int prec, const void* Lfac, const void* Z, double wm0, double wm1,
+                            const double* wmean, int mper, int G, int M, void* W,
+                            hipStream_t st) {
     const int NC = 2 * M;
     const int R = (G + GB_M - 1) / GB_M;
     dim3 grid((unsigned)((R + 1) / 2), (unsigned)((NC + GB_N - 1) / GB_N));
     if (prec == 0)
         hipLaunchKernelGGL(k_wind_gemm<double>, grid, dim3(256), 0, st,
-                           (const double*)Lfac, (const double*)Z, G, NC, wm0, wm1,
-                           (double*)W);
+                           (const double*)Lfac, (const double*)Z, G, NC, wm0, wm1, wmean,
+                           mper, (double*)W);
     else
         hipLaunchKernelGGL(k_wind_gemm<float>, grid, dim3(256), 0, st, (const float*)Lfac,
-                           (const float*)Z, G, NC, wm0, wm1, (float*)W);
+                           (const float*)Z, G, NC, wm0, wm1, wmean, mper, (float*)W);
     return hipGetLastError();
+}
+
+hipError_t launch_wind_gemm(int prec, const void* Lfac, const void* Z, double wm0,
+                            double wm1, int G, int M, void* W, hipStream_t st) {
+    return wind_gemm(prec, Lfac, Z, wm0, wm1, nullptr, 1, G, M, W, st);
+}
+
+hipError_t launch_wind_gemm_grouped(int prec, const void* Lfac, const void* Z,
+                                    const double* wmean, int mper, int G, int M, void* W,
+                                    hipStream_t st) {
+    if (!wmean || mper < 1) return hipErrorInvalidValue;
+    return wind_gemm(prec, Lfac, Z, 0.0, 0.0, wmean, mper, G, M, W, st);
 }
 
 }  // namespace smc

@@ -13,6 +13,11 @@ template <typename R> struct V4;
 template <> struct V4<float> { typedef float4 t; };
 template <> struct V4<double> { typedef double4 t; };
 
+// Occupancy target (waves per SIMD) of the world-per-lane rollout per
+// aircraft bucket: the state takes about 8 VGPRs per aircraft.
+template <typename R, int NMAX>
+constexpr int wm_waves() { return sizeof(R) == 4 ? (NMAX <= 4 ? 4 : (NMAX <= 10 ? 3 : 2)) : 1; }
+
 constexpr double kG0 = 9.80665;
 constexpr double kRho0 = 1.225, kT0 = 288.15, kLapse = 0.0065, kRair = 287.05287;
 

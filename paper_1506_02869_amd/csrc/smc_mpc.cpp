@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "host_common.h"
 #include "smc_kernels.h"
 #include "smc_mpc.h"
 
@@ -120,34 +121,7 @@ smc_status dalloc_t(smc_ctx* c, T** p, size_t count) {
 
 hipStream_t pick(smc_ctx* c, void* stream) { return stream ? (hipStream_t)stream : c->stream; }
 
-double sample_schedule(int J) { return std::floor(3.0 + 5.0 * std::exp(0.05 * J)); }
-double beta_of(const smc_ctx* c, int J) { return c->kappa * sample_schedule(J); }
-
-// Lower Cholesky factor of the 1-D squared-exponential Gram matrix plus the
-// nugget (FP64); false if not positive definite.
-bool axis_factor(int n, double lo, double hi, double ell, double nugget, std::vector<double>& Lo) {
-    std::vector<double> nodes(n), K((size_t)n * n);
-    for (int a = 0; a < n; ++a) nodes[a] = (n == 1) ? lo : lo + (hi - lo) * a / (n - 1);
-    for (int a = 0; a < n; ++a)
-        for (int b = 0; b < n; ++b) {
-            const double d = nodes[a] - nodes[b];
-            K[(size_t)a * n + b] = std::exp(-d * d / (2.0 * ell * ell)) + (a == b ? nugget : 0.0);
-        }
-    Lo.assign((size_t)n * n, 0.0);
-    for (int j = 0; j < n; ++j) {
-        double s = K[(size_t)j * n + j];
-        for (int k = 0; k < j; ++k) s -= Lo[(size_t)j * n + k] * Lo[(size_t)j * n + k];
-        if (!(s > 0.0)) return false;
-        const double d = std::sqrt(s);
-        Lo[(size_t)j * n + j] = d;
-        for (int i = j + 1; i < n; ++i) {
-            double t = K[(size_t)i * n + j];
-            for (int k = 0; k < j; ++k) t -= Lo[(size_t)i * n + k] * Lo[(size_t)j * n + k];
-            Lo[(size_t)i * n + j] = t / d;
-        }
-    }
-    return true;
-}
+double beta_of(const smc_ctx* c, int J) { return c->kappa * host::sample_schedule(J); }
 
 smc_status validate(const smc_scenario* s) {
     if (!s) return fail(nullptr, SMC_EINVAL, "scenario is NULL");
@@ -438,6 +412,86 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
 
 }  // namespace
 
+namespace smc {
+namespace host {
+
+double sample_schedule(int J) { return std::floor(3.0 + 5.0 * std::exp(0.05 * J)); }
+
+bool axis_factor(int n, double lo, double hi, double ell, double nugget, std::vector<double>& Lo) {
+    std::vector<double> nodes(n), K((size_t)n * n);
+    for (int a = 0; a < n; ++a) nodes[a] = (n == 1) ? lo : lo + (hi - lo) * a / (n - 1);
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            const double d = nodes[a] - nodes[b];
+            K[(size_t)a * n + b] = std::exp(-d * d / (2.0 * ell * ell)) + (a == b ? nugget : 0.0);
+        }
+    Lo.assign((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double s = K[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) s -= Lo[(size_t)j * n + k] * Lo[(size_t)j * n + k];
+        if (!(s > 0.0)) return false;
+        const double d = std::sqrt(s);
+        Lo[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double t = K[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= Lo[(size_t)i * n + k] * Lo[(size_t)j * n + k];
+            Lo[(size_t)i * n + j] = t / d;
+        }
+    }
+    return true;
+}
+
+smc_status validate_scenario(const smc_scenario* s, std::string& msg) {
+    const smc_status r = validate(s);
+    if (r) msg = g_init_error;
+    return r;
+}
+
+void fill_rollout_params(const smc_scenario* s, RolloutParams& rp) {
+    std::memset(&rp, 0, sizeof rp);
+    const int nx = s->grid_n[0], ny = s->grid_n[1], nz = s->grid_n[2];
+    const int use_noise = (s->popdense != nullptr && s->cost_w[8] != 0.0) ? 1 : 0;
+    const int pop_nx = s->popdense ? s->pop_n[0] : 0, pop_ny = s->popdense ? s->pop_n[1] : 0;
+    rp.N = s->n_aircraft; rp.S = s->n_segments; rp.H = s->horizon_max; rp.P = s->n_particles;
+    rp.M = s->n_wind; rp.G = nx * ny * nz;
+    rp.nx = nx; rp.ny = ny; rp.nz = nz;
+    rp.use_noise = use_noise; rp.pop_nx = pop_nx; rp.pop_ny = pop_ny;
+    rp.half_wx = 0.5 * s->box[0]; rp.half_wy = 0.5 * s->box[1];
+    rp.inv_hx = (nx - 1) / s->box[0]; rp.inv_hy = (ny - 1) / s->box[1];
+    rp.inv_hz = (nz - 1) / s->box[2];
+    rp.pop_inv_hx = pop_nx > 1 ? (pop_nx - 1) / s->box[0] : 0.0;
+    rp.pop_inv_hy = pop_ny > 1 ? (pop_ny - 1) / s->box[1] : 0.0;
+    rp.dt = s->dt; rp.sep_h2 = s->sep_h * s->sep_h; rp.sep_v = s->sep_v;
+    for (int a = 0; a < 3; ++a) {
+        rp.ctrl_lo[a] = s->ctrl_lo[a];
+        rp.ctrl_span[a] = s->ctrl_hi[a] - s->ctrl_lo[a];
+    }
+    rp.zmin = s->env[0]; rp.zmax = s->env[1]; rp.vmin = s->env[2]; rp.vmax = s->env[3];
+    rp.p_run = s->landing[0]; rp.p_beta = s->landing[1]; rp.p_chi = s->landing[2];
+    rp.p_vs = s->landing[3]; rp.beta_f = s->landing[4];
+    for (int a = 0; a < 9; ++a) rp.w[a] = s->cost_w[a];
+    rp.time_norm = s->time_norm; rp.noise_alt = s->noise_alt;
+    rp.zdot_max = std::max(std::fabs(s->ctrl_lo[2]), std::fabs(s->ctrl_hi[2]));
+}
+
+void fill_acR(const smc_scenario* s, std::vector<double>& t) {
+    const size_t N = (size_t)s->n_aircraft;
+    t.assign(N * kAcR, 0.0);
+    for (size_t i = 0; i < N; ++i) {
+        const double* a = s->aircraft + i * SMC_AC_NPAR;
+        const double* g = s->targets + i * 4;
+        double* o = t.data() + i * kAcR;
+        o[0] = a[0]; o[1] = a[1]; o[2] = a[2]; o[3] = a[3]; o[4] = 1.0 / a[4];
+        o[5] = a[5]; o[6] = a[6]; o[7] = std::tan(a[7]); o[8] = std::sin(a[8]);
+        o[9] = g[0]; o[10] = g[1]; o[11] = g[2]; o[12] = g[3];
+        o[13] = 1.0 / std::max(s->env[3] - g[2], g[2] - s->env[2]);
+        o[14] = s->kind[i] == SMC_ARRIVAL ? 0.0 : 1.0;
+    }
+}
+
+}  // namespace host
+}  // namespace smc
+
 extern "C" {
 
 const char* smc_version(void) { return "smc-mpc-gfx950 0.1"; }
@@ -490,31 +544,13 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     c->pop_ny = s->popdense ? s->pop_n[1] : 0;
     c->rsz = c->prec == SMC_FP64 ? sizeof(double) : sizeof(float);
 
-    // rollout scalars
-    RolloutParams& rp = c->rp;
-    std::memset(&rp, 0, sizeof rp);
-    rp.N = c->N; rp.S = c->S; rp.H = c->Hmax; rp.P = c->L; rp.M = c->M; rp.G = c->G;
-    rp.nx = c->nx; rp.ny = c->ny; rp.nz = c->nz;
-    rp.use_noise = c->use_noise; rp.pop_nx = c->pop_nx; rp.pop_ny = c->pop_ny;
-    rp.half_wx = 0.5 * c->box[0]; rp.half_wy = 0.5 * c->box[1];
-    rp.inv_hx = (c->nx - 1) / c->box[0]; rp.inv_hy = (c->ny - 1) / c->box[1];
-    rp.inv_hz = (c->nz - 1) / c->box[2];
-    rp.pop_inv_hx = c->pop_nx > 1 ? (c->pop_nx - 1) / c->box[0] : 0.0;
-    rp.pop_inv_hy = c->pop_ny > 1 ? (c->pop_ny - 1) / c->box[1] : 0.0;
-    rp.dt = c->dt; rp.sep_h2 = c->sep_h * c->sep_h; rp.sep_v = c->sep_v;
-    for (int a = 0; a < 3; ++a) { rp.ctrl_lo[a] = c->ctrl_lo[a]; rp.ctrl_span[a] = c->ctrl_span[a]; }
-    rp.zmin = c->env[0]; rp.zmax = c->env[1]; rp.vmin = c->env[2]; rp.vmax = c->env[3];
-    rp.p_run = c->landing[0]; rp.p_beta = c->landing[1]; rp.p_chi = c->landing[2];
-    rp.p_vs = c->landing[3]; rp.beta_f = c->landing[4];
-    for (int a = 0; a < 9; ++a) rp.w[a] = c->cost_w[a];
-    rp.time_norm = c->time_norm; rp.noise_alt = c->noise_alt;
-    rp.zdot_max = std::max(std::fabs(c->ctrl_lo[2]), std::fabs(c->ctrl_hi[2]));
+    host::fill_rollout_params(s, c->rp);
 
     // wind factor per axis (FP64, host)
     std::vector<double> Lx, Ly, Lz;
-    if (!axis_factor(c->nx, -0.5 * c->box[0], 0.5 * c->box[0], c->ell, c->nugget, Lx) ||
-        !axis_factor(c->ny, -0.5 * c->box[1], 0.5 * c->box[1], c->ell, c->nugget, Ly) ||
-        !axis_factor(c->nz, 0.0, c->box[2], c->ell, c->nugget, Lz)) {
+    if (!host::axis_factor(c->nx, -0.5 * c->box[0], 0.5 * c->box[0], c->ell, c->nugget, Lx) ||
+        !host::axis_factor(c->ny, -0.5 * c->box[1], 0.5 * c->box[1], c->ell, c->nugget, Ly) ||
+        !host::axis_factor(c->nz, 0.0, c->box[2], c->ell, c->nugget, Lz)) {
         g_init_error = "wind covariance not positive definite (raise wind_nugget)";
         delete c;
         return SMC_ENOTSPD;
@@ -586,17 +622,8 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     INIT_HIP(hipMemcpy(c->d_targets, s->targets, N * 4 * sizeof(double), hipMemcpyHostToDevice));
     INIT_HIP(hipMemcpy(c->d_kind, s->kind, N, hipMemcpyHostToDevice));
     {
-        std::vector<double> t(N * kAcR, 0.0);
-        for (size_t i = 0; i < N; ++i) {
-            const double* a = s->aircraft + i * SMC_AC_NPAR;
-            const double* g = s->targets + i * 4;
-            double* o = t.data() + i * kAcR;
-            o[0] = a[0]; o[1] = a[1]; o[2] = a[2]; o[3] = a[3]; o[4] = 1.0 / a[4];
-            o[5] = a[5]; o[6] = a[6]; o[7] = std::tan(a[7]); o[8] = std::sin(a[8]);
-            o[9] = g[0]; o[10] = g[1]; o[11] = g[2]; o[12] = g[3];
-            o[13] = 1.0 / std::max(s->env[3] - g[2], g[2] - s->env[2]);
-            o[14] = s->kind[i] == SMC_ARRIVAL ? 0.0 : 1.0;
-        }
+        std::vector<double> t;
+        host::fill_acR(s, t);
         if (c->prec == SMC_FP64) {
             INIT_HIP(hipMemcpy(c->d_acR, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
         } else {

@@ -203,7 +203,9 @@ def c3(seed: int = 0, n_scen: int = 64, **kw) -> list:
                     grid=(32, 32, 8), H=H, dt=5.0, S=S, M=32, L=4096, K=40,
                     precision="fp32", seed=seed * 1000 + s)
         args.update(kw)
-        out.append(make_scenario(f"C3.{s}", **args))
+        sc = make_scenario(f"C3.{s}", **args)
+        sc["scenario_id"] = s
+        out.append(sc)
     return out
 
 

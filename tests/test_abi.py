@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     names = set()
-    for h in ("smc_mpc.h", "smc_kernels.h"):
+    for h in ("smc_mpc.h", "smc_kernels.h", "smc_batch.h"):
         txt = open(os.path.join(ROOT, "include", h)).read()
         txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
         names |= set(re.findall(r"\b(smc_[a-z0-9_]+)\s*\(", txt))
