@@ -45,7 +45,9 @@ typedef struct smc_batch smc_batch;
 
 /* Launch shape of the persistent rollout, per aircraft bucket.  Any value
  * gives the same results; only the speed differs.
- *  block[b]: lanes per workgroup, 64, 128 or 256 (0 = default 256).
+ *  block[b]: lanes per workgroup, 64, 128 or 256 (0 = default: 256 in FP32,
+ *     128 in FP64); the segment's staged controls, NMAX x 3 x block reals,
+ *     must fit 64 KB of LDS (smc_batch_set_tuning rejects shapes that do not).
  *  grid_mult[b]: workgroups = resident capacity of the chip x grid_mult
  *     (1..4; 0 = default 1).
  *  order: 0 = items by decreasing N^2 H (default), 1 = scenario order. */
@@ -66,6 +68,9 @@ typedef struct {
     double feasible_frac;      /* feasible (particle, aircraft) rows, last pass */
     int32_t graph;             /* 1 if the update replayed the captured graph   */
     int32_t rollout_launches;  /* persistent rollout launches in the update     */
+    int32_t rollout_passes;    /* rollout passes (all buckets) in the update    */
+    double ms_rollout;         /* summed duration of the rollout passes (device
+                                  events; 0 when the update replayed a graph)  */
 } smc_batch_info;
 
 /* Create a batch of n_scen (1..SMC_BATCH_MAX_SCENARIOS) scenarios.  Each

@@ -96,7 +96,8 @@ class BatchInfo(C.Structure):
                 ("aircraft_steps", C.c_int64), ("pair_tests", C.c_int64),
                 ("ms_total", C.c_double), ("accept_rate", C.c_double),
                 ("feasible_frac", C.c_double), ("graph", C.c_int32),
-                ("rollout_launches", C.c_int32)]
+                ("rollout_launches", C.c_int32), ("rollout_passes", C.c_int32),
+                ("ms_rollout", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -78,6 +78,7 @@ struct smc_batch {
 
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_up = nullptr;
+    std::vector<hipEvent_t> ev_pass;   // pairs bracketing the rollout passes (timed updates)
     bool up_pending = false;
     bool use_graph = false;
     hipGraph_t graph = nullptr;
@@ -256,9 +257,10 @@ hipError_t rollout_pass(smc_batch* b, int pass, const void* u, int* launches, hi
 
 // The device work of one update; every per-update input is already in the
 // batch's device buffers (table, header, wind means, states, items).
-hipError_t enqueue_update(smc_batch* b, hipStream_t st, int* launches) {
+hipError_t enqueue_update(smc_batch* b, hipStream_t st, int* launches, bool timed) {
     hipError_t e;
 #define Q(expr) do { if ((e = (expr)) != hipSuccess) return e; } while (0)
+    auto mark = [&](int q) { return timed ? hipEventRecord(b->ev_pass[q], st) : hipSuccess; };
     const int ns = b->ns, L = b->L, M = b->M, K = b->K;
     Q(launch_b_fill(b->d_cnt, b->n_cnt, st));
     void* u = b->d_u;
@@ -269,11 +271,17 @@ hipError_t enqueue_update(smc_batch* b, hipStream_t st, int* launches) {
         Q(launch_b_normals(b->prec, b->d_tab, b->d_hdr, ns, J, b->G, M, b->d_Z, st));
         Q(launch_wind_gemm_grouped(b->prec, b->d_Lfac, b->d_Z, b->d_wmean, M, b->G, ns * M,
                                    b->d_W, st));
-        Q(rollout_pass(b, pass++, u, launches, st));
+        Q(mark(2 * pass));
+        Q(rollout_pass(b, pass, u, launches, st));
+        Q(mark(2 * pass + 1));
+        ++pass;
         Q(launch_b_reduce(b->d_tab, ns, J, b->max_pn, b->d_chat, b->d_feaspn, b->d_logw, st));
         if (b->move == SMC_MOVE_RWMH) {
             Q(launch_b_propose(b->prec, b->d_tab, b->d_hdr, ns, J, b->max_count, u, b->d_up, st));
-            Q(rollout_pass(b, pass++, b->d_up, launches, st));
+            Q(mark(2 * pass));
+            Q(rollout_pass(b, pass, b->d_up, launches, st));
+            Q(mark(2 * pass + 1));
+            ++pass;
             Q(launch_b_reduce(b->d_tab, ns, J, b->max_pn, b->d_chat2, b->d_feaspn2, b->d_logw2, st));
             Q(launch_b_accept(b->prec, b->d_tab, b->d_hdr, ns, J, L, b->max_count, u, b->d_up,
                               b->d_chat, b->d_chat2, b->d_feaspn, b->d_feaspn2, b->d_logw,
@@ -357,7 +365,7 @@ smc_status run_update(smc_batch* b, int64_t mpc_step, const double* states, cons
     if (b->use_graph) {
         if (!b->gexec) {
             BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-            const hipError_t e = enqueue_update(b, b->stream, nullptr);
+            const hipError_t e = enqueue_update(b, b->stream, nullptr, false);
             hipGraph_t g = nullptr;
             const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
@@ -376,7 +384,7 @@ smc_status run_update(smc_batch* b, int64_t mpc_step, const double* states, cons
         for (int bk = 0; bk < kNumBuckets; ++bk)
             if (b->bcount[bk]) launches += b->K * (b->move == SMC_MOVE_RWMH ? 2 : 1);
     } else {
-        BHIP(b, enqueue_update(b, st, &launches));
+        BHIP(b, enqueue_update(b, st, &launches, info != nullptr));
     }
     if (!info) return SMC_OK;
     BHIP(b, hipEventRecord(b->ev1, st));
@@ -405,6 +413,14 @@ smc_status run_update(smc_batch* b, int64_t mpc_step, const double* states, cons
     info->feasible_frac = fe.empty() ? 0.0 : (double)nf / (double)fe.size();
     info->graph = b->use_graph ? 1 : 0;
     info->rollout_launches = launches;
+    info->rollout_passes = b->K * (b->move == SMC_MOVE_RWMH ? 2 : 1);
+    info->ms_rollout = 0.0;
+    if (!b->use_graph)
+        for (int q = 0; q < info->rollout_passes; ++q) {
+            float t = 0.f;
+            BHIP(b, hipEventElapsedTime(&t, b->ev_pass[2 * q], b->ev_pass[2 * q + 1]));
+            info->ms_rollout += t;
+        }
     return SMC_OK;
 }
 
@@ -435,6 +451,8 @@ void smc_batch_destroy(smc_batch* b) {
     for (void* p : b->bufs) (void)hipFree(p);
     for (void* p : b->pinned) (void)hipHostFree(p);
     for (hipEvent_t e : {b->ev0, b->ev1, b->ev_up})
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->ev_pass)
         if (e) (void)hipEventDestroy(e);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
@@ -523,6 +541,12 @@ smc_status smc_batch_init(const smc_scenario* sc, int32_t ns, smc_batch** out) {
         bfail(b, SMC_EDEVICE, "stream / event creation failed");
         return bail(SMC_EDEVICE);
     }
+    b->ev_pass.assign((size_t)4 * b->K, nullptr);
+    for (auto& e : b->ev_pass)
+        if (hipEventCreate(&e) != hipSuccess) {
+            bfail(b, SMC_EDEVICE, "event creation failed");
+            return bail(SMC_EDEVICE);
+        }
     const size_t L = b->L, M = b->M, G = b->G, rows = b->rows, nsz = ns;
     const size_t nu = (size_t)b->off_u[ns], npn = (size_t)b->off_pn[ns];
     b->cnt_steps = 2 * (int64_t)b->K * kNumBuckets;           // even: 8-byte aligned u64 slots
