@@ -259,10 +259,10 @@ def main():
     achieved = flops_launch / (ms_roll * 1e-3) / 1e12
     fp64 = scen["precision"] == 0
     peak = PEAK_FP64_VECTOR_TFLOPS if fp64 else PEAK_FP32_VECTOR_TFLOPS
-    wm = N <= 16     # the library picks the world-per-lane rollout up to 16 aircraft
+    world_lane = N <= 20   # the library picks the world-per-lane rollout up to 20 aircraft
     kname, ksrc = ((
         "k_rollout_wm", ("kernels_rollout_wm.hip", "rollout_wm_body.inc", "rollout_math.h"))
-        if wm else ("k_rollout", ("kernels_rollout.hip", "rollout_math.h")))
+        if world_lane else ("k_rollout", ("kernels_rollout.hip", "rollout_math.h")))
     roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 3),
             "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
             "traffic": traffic_for(ksrc, "bytes_per_launch", flops_launch),

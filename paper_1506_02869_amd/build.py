@@ -28,6 +28,9 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions stay disabled (see the design notes)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # a*b+c is fused only within one source expression, so kernels that
+         # share arithmetic (single-scenario and batched) round identically
+         "-ffp-contract=on",
          "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 
 

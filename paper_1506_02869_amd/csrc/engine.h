@@ -13,6 +13,21 @@ constexpr int kStepSlots = 64;   // striped counters of simulated aircraft-steps
 constexpr int kWorldLaneMaxN = 20;  // largest N of the world-per-lane rollout
 constexpr int kAcR = 16;            // per-aircraft parameters in the rollout's precision
 
+// Constants of the world-per-lane rollout in its own precision, derived on
+// the host from the scalars of RolloutParams (so the kernel's step loop
+// converts and combines nothing).  o* = offset of the grid map
+// f = x inv_h + o; fn*1 / fn*2 = nodes - 1 / nodes - 2; c_* = cost weights
+// with the normalisations folded in.
+template <typename R>
+struct RollConst {
+    R ox, oy, inv_hx, inv_hy, inv_hz, fnx1, fny1, fnz1, fnx2, fny2, fnz2, fny, fnz;
+    R inv_dt, g0, inv_g, sep_h2, sep_v, zmin, zmax, vmin, vmax;
+    R p_run, p_beta, p_chi, p_vs, beta_f;
+    R c_hdg, c_gl, c_brg, c_alt, a_time, a_noise, inv_tnorm, zdm_dt, inv_Ac;
+    R isa_c, isa_e, rho0, dt, lo[3], span[3];
+    R pop_ox, pop_oy, pop_inv_hx, pop_inv_hy, fpnx1, fpny1;
+};
+
 // Scalars of one rollout launch (uniform over the grid; kernel argument).
 struct RolloutParams {
     int N, S, H, P, M, G;
@@ -26,6 +41,8 @@ struct RolloutParams {
     double p_run, p_beta, p_chi, p_vs, beta_f;
     double w[9];
     double time_norm, noise_alt, zdot_max;
+    RollConst<float> cf;    // world-per-lane constants, FP32
+    RollConst<double> cd;   // world-per-lane constants, FP64
 };
 
 // Device arrays of one rollout launch.
@@ -108,9 +125,10 @@ hipError_t launch_wind_gemm(int prec, const void* Lfac, const void* Z,
 hipError_t launch_rollout(int prec, const RolloutParams& p,
                           const RolloutArrays& a, hipStream_t st);
 bool rollout_wm_supported(int N);
-// acR: [N][kAcR] real: wing area, C_D0, C_D2, C_f1, 1/C_f2, T_max, empty
-// mass, tan(phi_max), sin(gamma_max), theta_F, Z, v_D, D_TMA, 1/speed span,
-// kind (0 arrival, 1 departure), 0
+// acR: [N][kAcR] real: wing area, C_D0, C_D2, dt C_f1, dt C_f1 / C_f2,
+// T_max, empty mass, tan(phi_max), sin(gamma_max), theta_F, Z, v_D, D_TMA,
+// (1 - alpha_time - alpha_noise) w_speed / speed span, kind (0 arrival,
+// 1 departure), 0
 hipError_t launch_rollout_wm(int prec, const RolloutParams& p, const RolloutArrays& a,
                              const void* acR, hipStream_t st);
 // adjoint of the fuel + time cost (sum over wind samples) w.r.t. the

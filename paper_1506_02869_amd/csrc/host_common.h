@@ -27,6 +27,10 @@ smc_status validate_scenario(const smc_scenario* s, std::string& msg);
 // Rollout scalars of a scenario (H = horizon_max, P = n_particles).
 void fill_rollout_params(const smc_scenario* s, RolloutParams& rp);
 
+// Constants of the world-per-lane rollout (both precisions) from the
+// scalars already in rp.
+void fill_rollout_consts(RolloutParams& rp);
+
 // Per-aircraft parameter rows [N][kAcR] of the world-per-lane rollout.
 void fill_acR(const smc_scenario* s, std::vector<double>& t);
 

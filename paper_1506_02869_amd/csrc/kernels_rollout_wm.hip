@@ -32,14 +32,15 @@ k_rollout_wm(const RolloutParams p, const RolloutArrays a, const R* __restrict__
 }
 
 // 256 lanes per block in FP32, 128 in FP64: the staged controls take
-// N * 3 * block * sizeof(R) bytes of LDS (60 KB at N = 20 either way).
+// NMAX * 3 * block * sizeof(R) bytes of LDS (one NMAX x 3 x 64 slice per
+// wave; 60 KB at NMAX = 20 either way).
 template <typename R, int NMAX>
 static hipError_t launch_wm_n(const RolloutParams& p, const RolloutArrays& a, const void* acR,
                               hipStream_t st) {
     const int block = sizeof(R) == 4 ? 256 : 128;
     const int64_t nworld = (int64_t)p.P * p.M;
     const unsigned blocks = (unsigned)((nworld + block - 1) / block);
-    const size_t lds = (size_t)p.N * 3 * block * sizeof(R);
+    const size_t lds = (size_t)NMAX * 3 * block * sizeof(R);
     hipLaunchKernelGGL((k_rollout_wm<R, NMAX>), dim3(blocks), dim3(block), lds, st, p, a,
                        (const R*)acR);
     return hipGetLastError();

@@ -18,6 +18,24 @@ template <> struct V4<double> { typedef double4 t; };
 template <typename R, int NMAX>
 constexpr int wm_waves() { return sizeof(R) == 4 ? (NMAX <= 4 ? 4 : (NMAX <= 10 ? 3 : 2)) : 1; }
 
+// An aircraft that has landed is parked at x = kGoneX + i kGoneDX: far from
+// every other aircraft, parked or not, so pair tests need no presence check.
+constexpr double kGoneX = 1.0e9, kGoneDX = 1.0e8;
+
+__device__ __forceinline__ float m_fma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double m_fma(double a, double b, double c) { return fma(a, b, c); }
+
+// A wave-uniform real moved to scalar registers.
+__device__ __forceinline__ float uniform_real(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double uniform_real(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
 constexpr double kG0 = 9.80665;
 constexpr double kRho0 = 1.225, kT0 = 288.15, kLapse = 0.0065, kRair = 287.05287;
 
@@ -81,8 +99,22 @@ __device__ __forceinline__ R wrap_angle(R a) {
     return a - Consts<R>::two_pi * m_floor((a + Consts<R>::pi) * Consts<R>::inv_two_pi);
 }
 
+// v clamped to [lo, hi] (lo <= hi).  FP32: one v_med3_f32, which needs no
+// canonicalisation of loop-invariant bounds (min / max in IEEE mode do).
 template <typename R>
 __device__ __forceinline__ R clampr(R v, R lo, R hi) { return m_min(m_max(v, lo), hi); }
+template <>
+__device__ __forceinline__ float clampr<float>(float v, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(v, lo, hi);
+}
+
+// max(v, lo) for a loop-invariant bound: a median with +inf in FP32.
+template <typename R>
+__device__ __forceinline__ R maxr(R v, R lo) { return m_max(v, lo); }
+template <>
+__device__ __forceinline__ float maxr<float>(float v, float lo) {
+    return __builtin_amdgcn_fmed3f(v, lo, __builtin_inff());
+}
 
 // Kahan-compensated accumulation.
 template <typename R>

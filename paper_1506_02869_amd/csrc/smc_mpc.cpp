@@ -472,6 +472,46 @@ void fill_rollout_params(const smc_scenario* s, RolloutParams& rp) {
     for (int a = 0; a < 9; ++a) rp.w[a] = s->cost_w[a];
     rp.time_norm = s->time_norm; rp.noise_alt = s->noise_alt;
     rp.zdot_max = std::max(std::fabs(s->ctrl_lo[2]), std::fabs(s->ctrl_hi[2]));
+    fill_rollout_consts(rp);
+}
+
+namespace {
+template <typename R>
+void fill_consts(const RolloutParams& p, RollConst<R>& c) {
+    const double pi = 3.14159265358979323846;
+    const double mix = 1.0 - p.w[7] - p.w[8];
+    c.ox = (R)(p.half_wx * p.inv_hx); c.oy = (R)(p.half_wy * p.inv_hy);
+    c.inv_hx = (R)p.inv_hx; c.inv_hy = (R)p.inv_hy; c.inv_hz = (R)p.inv_hz;
+    c.fnx1 = (R)(p.nx - 1); c.fny1 = (R)(p.ny - 1); c.fnz1 = (R)(p.nz - 1);
+    c.fnx2 = (R)(p.nx - 2); c.fny2 = (R)(p.ny - 2); c.fnz2 = (R)(p.nz - 2);
+    c.fny = (R)p.ny; c.fnz = (R)p.nz;
+    c.inv_dt = (R)(1.0 / p.dt); c.g0 = (R)9.80665; c.inv_g = (R)(1.0 / 9.80665);
+    c.sep_h2 = (R)p.sep_h2; c.sep_v = (R)p.sep_v;
+    c.zmin = (R)p.zmin; c.zmax = (R)p.zmax; c.vmin = (R)p.vmin; c.vmax = (R)p.vmax;
+    c.p_run = (R)p.p_run; c.p_beta = (R)p.p_beta; c.p_chi = (R)p.p_chi; c.p_vs = (R)p.p_vs;
+    c.beta_f = (R)p.beta_f;
+    c.c_hdg = (R)(mix * p.w[0] / pi);
+    c.c_gl = (R)(mix * p.w[1] * 2.0 / pi);
+    c.c_brg = (R)(mix * p.w[3] / pi);
+    c.c_alt = (R)(mix * p.w[5]);
+    c.a_time = (R)p.w[7]; c.a_noise = (R)p.w[8];
+    c.inv_tnorm = (R)(1.0 / p.time_norm);
+    c.zdm_dt = (R)(p.zdot_max * p.dt);
+    c.inv_Ac = (R)(1.0 / p.noise_alt);
+    c.isa_c = (R)(0.0065 / 288.15);
+    c.isa_e = (R)(9.80665 / (287.05287 * 0.0065) - 1.0);
+    c.rho0 = (R)1.225;
+    c.dt = (R)p.dt;
+    for (int a = 0; a < 3; ++a) { c.lo[a] = (R)p.ctrl_lo[a]; c.span[a] = (R)p.ctrl_span[a]; }
+    c.pop_ox = (R)(p.half_wx * p.pop_inv_hx); c.pop_oy = (R)(p.half_wy * p.pop_inv_hy);
+    c.pop_inv_hx = (R)p.pop_inv_hx; c.pop_inv_hy = (R)p.pop_inv_hy;
+    c.fpnx1 = (R)(p.pop_nx - 1); c.fpny1 = (R)(p.pop_ny - 1);
+}
+}  // namespace
+
+void fill_rollout_consts(RolloutParams& rp) {
+    fill_consts<float>(rp, rp.cf);
+    fill_consts<double>(rp, rp.cd);
 }
 
 void fill_acR(const smc_scenario* s, std::vector<double>& t) {
@@ -481,10 +521,11 @@ void fill_acR(const smc_scenario* s, std::vector<double>& t) {
         const double* a = s->aircraft + i * SMC_AC_NPAR;
         const double* g = s->targets + i * 4;
         double* o = t.data() + i * kAcR;
-        o[0] = a[0]; o[1] = a[1]; o[2] = a[2]; o[3] = a[3]; o[4] = 1.0 / a[4];
+        const double mix = 1.0 - s->cost_w[7] - s->cost_w[8];
+        o[0] = a[0]; o[1] = a[1]; o[2] = a[2]; o[3] = s->dt * a[3]; o[4] = s->dt * a[3] / a[4];
         o[5] = a[5]; o[6] = a[6]; o[7] = std::tan(a[7]); o[8] = std::sin(a[8]);
         o[9] = g[0]; o[10] = g[1]; o[11] = g[2]; o[12] = g[3];
-        o[13] = 1.0 / std::max(s->env[3] - g[2], g[2] - s->env[2]);
+        o[13] = mix * s->cost_w[6] / std::max(s->env[3] - g[2], g[2] - s->env[2]);
         o[14] = s->kind[i] == SMC_ARRIVAL ? 0.0 : 1.0;
     }
 }

@@ -224,6 +224,33 @@ def test_rollout_close_traffic_separation(lib, layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rollout_landed_aircraft_leave_the_airspace(lib, prec, layout):
+    """Arrivals queued on the final approach 6.5 km apart at one altitude:
+    each lands where the one before it landed.  A landed aircraft no longer
+    takes part in separation (Sec. "Constraint Handling"), so no world may
+    report a conflict; any residual presence of landed aircraft would make
+    every world infeasible."""
+    n, H = 4, 40
+    s = synth.make_scenario("Q", n_arr=n, n_dep=0, box=(80e3, 80e3, 6e3), grid=(4, 4, 3),
+                            H=H, dt=5.0, S=4, M=2, L=4, K=2, precision=prec, seed=3)
+    s = dict(s)
+    s["ctrl_lo"] = np.array([-0.1 * np.pi / 180, 110.0, -0.5])
+    s["ctrl_hi"] = np.array([0.1 * np.pi / 180, 128.0, 0.5])
+    st = np.zeros((n, 6))
+    st[:, 0] = 8.3e3 + 6.5e3 * np.arange(n)
+    st[:, 2] = 500.0
+    st[:, 3] = 120.0
+    st[:, 4] = np.pi
+    st[:, 5] = 60e3
+    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=64, states=st,
+                                            k_active=np.zeros(n, np.int32), layout=layout)
+    _compare_rollout(gc, gf, ref, s["precision"])
+    assert steps == ref["steps"] < 64 * 2 * n * H        # aircraft did land
+    assert ref["feas"].all() and gf.all()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 def test_rollout_noise_term(lib, layout):
     s = synth.shrink(synth.c5(precision="fp64"), M=2, H=30, S=3, grid=(8, 8, 4))
     s = dict(s)
