@@ -36,6 +36,10 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 # aircraft; the table is in the design notes.
 FLOPS_PER_AIRCRAFT_STEP = 170
 FLOPS_PER_PAIR_TEST = 10
+# Adjoint of the fuel + time cost: one primal step plus one reverse step per
+# (particle, aircraft, wind sample, step); the recomputation from checkpoints
+# is overhead and not counted.
+FLOPS_PER_ADJOINT_STEP = 334
 
 
 WORKLOADS = {
@@ -48,6 +52,11 @@ WORKLOADS = {
            "S = ceil(H/15), 100x100x8 km, wind 32x32x8 (one shared factor) M=32, L=4096, "
            "K=40, FP32 rollout with FP64 weights and scan, jitter moves; persistent "
            "rollout per aircraft bucket, graph-captured update", "c3"),
+    "c4": ("differentiable form: 20 aircraft (12 arrivals, 8 departures), 100x100x8 km, "
+           "H=150 dt=4 s, S=10 (600 parameters), wind 32x32x8 M=64, L=16384, K=40, "
+           "FP32 rollout and adjoint with FP64 weights, scan and gradient sums, MALA moves "
+           "(step 1e-2) driven by the adjoint of the fuel + time cost, checkpoint every "
+           "25 steps", "c4"),
 }
 
 
@@ -59,17 +68,18 @@ def _src_hash(*names):
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel_src: tuple, key: str, launches_bytes_alg: float):
+def traffic_for(kernel_src: tuple, workload: str):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, or
-    None when absent or taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", "rollout_c2_traffic.json")
+    None when absent, taken on another workload or on a different kernel
+    source."""
+    path = os.path.join(ROOT, "profiles", f"rollout_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
     if t.get("source_hash") != _src_hash(*kernel_src):
         return None
-    return t.get(key)
+    return t.get("bytes_per_launch")
 
 
 def cpu_baseline(scen, particles: int):
@@ -85,6 +95,12 @@ def cpu_baseline(scen, particles: int):
     from oracle import wind as owind
 
     s = synth.shrink(scen, L=particles, K=2)
+    note = ""
+    if s["move"] == 2:
+        # the oracle's Langevin move needs its autograd gradient; the baseline
+        # times the oracle's rollout under random-walk moves instead
+        s = synth.shrink(s, move=1)
+        note = ", random-walk moves in place of MALA"
     steps = 0
 
     with threadpool_limits(limits=1):
@@ -104,7 +120,7 @@ def cpu_baseline(scen, particles: int):
     return {"value": steps / dt, "unit": "aircraft-steps/s", "cores": 1, "kind": "oracle",
             "sample": (f"oracle smc loop on {particles} particles x {s['M']} wind samples x "
                        f"{s['N']} aircraft x {s['H']} steps, 2 SMC iterations "
-                       f"({steps} aircraft-steps in {dt:.1f} s, wind factor included)"),
+                       f"({steps} aircraft-steps in {dt:.1f} s, wind factor included{note})"),
             "seconds": round(dt, 2)}
 
 
@@ -265,7 +281,7 @@ def main():
         if world_lane else ("k_rollout", ("kernels_rollout.hip", "rollout_math.h")))
     roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 3),
             "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": traffic_for(ksrc, "bytes_per_launch", flops_launch),
+            "traffic": traffic_for(ksrc, args.workload) if world_lane else None,
             "ms_per_launch": round(ms_roll, 4),
             "aircraft_steps_per_launch": int(as_per_launch),
             "pair_tests_per_launch": int(pt_per_launch),
@@ -277,6 +293,20 @@ def main():
     wind_roof = {"kernel": "k_wind_gemm", "bound": "mfma", "achieved": round(gemm_ach, 3),
                  "peak": gpeak, "unit": "TFLOP/s", "frac": round(gemm_ach / gpeak, 4),
                  "ms_per_launch": round(ms_wind, 4)}
+    grad_roof = None
+    n_grad = sum(i["grad_launches"] for i in infos)
+    if n_grad:
+        # the adjoint runs on the particles of each rollout pass, so its
+        # (particle, aircraft, sample) steps equal that pass's aircraft-steps
+        ms_grad = sum(i["ms_grad"] for i in infos) / n_grad
+        ls_launch = aircraft_steps / info0["grad_launches"]
+        gflops = ls_launch * FLOPS_PER_ADJOINT_STEP
+        gach = gflops / (ms_grad * 1e-3) / 1e12
+        grad_roof = {"kernel": "k_rollout_grad", "bound": "alu", "achieved": round(gach, 3),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(gach / peak, 4),
+                     "ms_per_launch": round(ms_grad, 4), "lane_steps_per_launch": int(ls_launch),
+                     "flops_per_launch": gflops,
+                     "ms_per_mpc_step_in_adjoint": round(ms_grad * info0["grad_launches"], 2)}
 
     check = None
     if not args.no_check:
@@ -308,9 +338,9 @@ def main():
                       "segments": scen["S"], "grid": [int(g) for g in scen["grid"]],
                       "aircraft_steps_per_mpc_step": aircraft_steps},
            "roofline": roof, "cpu_baseline": cpu, "wind_gemm_roofline": wind_roof,
-           "cost_check": check,
+           "adjoint_roofline": grad_roof, "cost_check": check,
            "step_info": {k: info0[k] for k in ("feasible_frac", "ess_min", "best_particle",
-                                              "ms_total")}}
+                                              "ms_total", "accept_rate")}}
     print(json.dumps(out), flush=True)
 
 

@@ -133,6 +133,8 @@ typedef struct {
     double ms_wind;           /* summed duration of the wind GEMM launches      */
     int32_t rollout_launches; /* rollout launches in the update                 */
     int32_t wind_launches;    /* wind GEMM launches in the update               */
+    double ms_grad;           /* summed duration of the adjoint launches (MALA) */
+    int32_t grad_launches;    /* adjoint launches in the update (MALA: 2 K)     */
 } smc_step_info;
 
 /* Create a context: validates the scenario, factors the wind covariance

@@ -63,7 +63,8 @@ class StepInfo(C.Structure):
                 ("pair_tests", C.c_int64),
                 ("ms_total", C.c_double), ("ms_rollout", C.c_double),
                 ("ms_wind", C.c_double), ("rollout_launches", C.c_int32),
-                ("wind_launches", C.c_int32)]
+                ("wind_launches", C.c_int32), ("ms_grad", C.c_double),
+                ("grad_launches", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -44,7 +44,7 @@ struct smc_ctx {
 
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    std::vector<hipEvent_t> ev_roll, ev_wind;  // pairs bracketing launches
+    std::vector<hipEvent_t> ev_roll, ev_wind, ev_grad;  // pairs bracketing launches
     std::vector<DevBuf> bufs;
     std::string err;
 
@@ -311,8 +311,10 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
             // cost; acceptance with the full target and the q ratio
             const double coef = -beta / (double)c->M;
             const double eps = c->mala_step;
+            if (info) HIP_OK(c, hipEventRecord(c->ev_grad[4 * J], st));
             HIP_OK(c, launch_rollout_grad(c->prec, rp, u, c->d_W, d_states, d_kact, c->d_acpar,
                                           c->d_targets, c->d_kind, c->d_gpart, c->d_g, st));
+            if (info) HIP_OK(c, hipEventRecord(c->ev_grad[4 * J + 1], st));
             HIP_OK(c, launch_mala_propose(c->prec, count, u, c->d_g, coef, eps,
                                           make_stream(c->seed, mpc_step, J, P_MALA, c->scen_id),
                                           c->d_up, st));
@@ -325,8 +327,10 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
             ++n_roll2;
             HIP_OK(c, launch_reduce(L, c->M, N, c->d_cost, c->d_feas, beta, c->d_chat2,
                                     c->d_feaspn2, c->d_logw2, st));
+            if (info) HIP_OK(c, hipEventRecord(c->ev_grad[4 * J + 2], st));
             HIP_OK(c, launch_rollout_grad(c->prec, rp, c->d_up, c->d_W, d_states, d_kact, c->d_acpar,
                                           c->d_targets, c->d_kind, c->d_gpart, c->d_g2, st));
+            if (info) HIP_OK(c, hipEventRecord(c->ev_grad[4 * J + 3], st));
             HIP_OK(c, launch_mala_decide(c->prec, L, N, D, u, c->d_up, c->d_g, c->d_g2, coef, eps,
                                          c->d_logw, c->d_logw2,
                                          make_stream(c->seed, mpc_step, J, P_ACCEPT, c->scen_id),
@@ -391,8 +395,16 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     info->aircraft_steps = (int64_t)tot;
     info->pair_tests = (int64_t)totp;
     info->ms_total = ms;
-    double ms_r = 0.0, ms_w = 0.0;
+    double ms_r = 0.0, ms_w = 0.0, ms_g = 0.0;
+    const bool grad = c->move == SMC_MOVE_MALA;
     for (int J = 0; J < c->K; ++J) {
+        if (grad) {
+            for (int h = 0; h < 2; ++h) {
+                float t = 0.f;
+                HIP_OK(c, hipEventElapsedTime(&t, c->ev_grad[4 * J + 2 * h], c->ev_grad[4 * J + 2 * h + 1]));
+                ms_g += t;
+            }
+        }
         float t = 0.f;
         HIP_OK(c, hipEventElapsedTime(&t, c->ev_wind[2 * J], c->ev_wind[2 * J + 1]));
         ms_w += t;
@@ -407,6 +419,8 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     info->ms_wind = ms_w;
     info->rollout_launches = n_roll + n_roll2;
     info->wind_launches = c->K;
+    info->ms_grad = ms_g;
+    info->grad_launches = grad ? 2 * c->K : 0;
     return best[1] ? SMC_INFEASIBLE : SMC_OK;
 }
 
@@ -547,6 +561,7 @@ void smc_destroy(smc_ctx* c) {
     for (auto& b : c->bufs) (void)hipFree(b.p);
     for (hipEvent_t e : c->ev_roll) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_wind) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_grad) (void)hipEventDestroy(e);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -614,7 +629,8 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     }
     c->ev_roll.assign((size_t)4 * c->K, nullptr);
     c->ev_wind.assign((size_t)2 * c->K, nullptr);
-    for (auto* v : {&c->ev_roll, &c->ev_wind})
+    c->ev_grad.assign(c->move == SMC_MOVE_MALA ? (size_t)4 * c->K : 0, nullptr);
+    for (auto* v : {&c->ev_roll, &c->ev_wind, &c->ev_grad})
         for (auto& e : *v)
             if (hipEventCreate(&e) != hipSuccess) {
                 fail(c, SMC_EDEVICE, "hipEventCreate failed");

@@ -77,3 +77,33 @@ def test_valid_scenario_without_device_reports_device_error():
     st = smc.lib().smc_mpc_init(C.byref(sc), C.byref(h))
     assert st in (smc.SMC_EDEVICE, smc.SMC_ENOMEM)
     assert h.value is None
+
+
+@pytest.mark.parametrize("cname,pyname", [
+    ("smc_scenario", "Scenario"), ("smc_step_info", "StepInfo"),
+    ("smc_batch_tuning", "BatchTuning"), ("smc_batch_info", "BatchInfo"),
+])
+def test_struct_layouts_match_the_headers(tmp_path, cname, pyname):
+    """The binding's ctypes mirrors have the C structs' size and field offsets
+    (the headers compiled by the host C compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    py = getattr(smc, pyname)
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "smc_batch.h"',
+             "int main(void) {", f'  printf("size %zu\\n", sizeof({cname}));']
+    for f, _ in py._fields_:
+        lines.append(f'  printf("{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    assert int(out["size"]) == C.sizeof(py)
+    for f, _ in py._fields_:
+        assert int(out[f]) == getattr(py, f).offset, f
