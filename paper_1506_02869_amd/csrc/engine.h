@@ -135,9 +135,11 @@ hipError_t launch_rollout_wm(int prec, const RolloutParams& p, const RolloutArra
 // normalised controls; partial: chunk partials when M > 64
 bool grad_supported(int H, int S);
 size_t grad_partial_elems(int P, int N, int S, int M);
+// W [M][G] pairs; Wt: workspace of the same size (the sample-interleaved
+// copy the adjoint reads).
 hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u, const void* W,
                                const double* states, const int32_t* k_active, const double* acpar,
-                               const double* targets, const int8_t* kind, double* partial,
+                               const double* targets, const int8_t* kind, void* Wt, double* partial,
                                double* grad_out, hipStream_t st);
 hipError_t launch_mala_propose(int prec, int64_t count, const void* u, const double* gsum,
                                double coef, double eps, Stream s, void* up, hipStream_t st);

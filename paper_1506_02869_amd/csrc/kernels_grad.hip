@@ -34,7 +34,10 @@ struct StepFwd {     // intermediates of one step, recomputed in the reverse swe
 };
 
 // Trilinear wind and its derivative with respect to (x, y, z) (zero along a
-// clamped coordinate).
+// clamped coordinate).  Wm points at the lane's sample in the sample-
+// interleaved field Wt[g][m] (row stride M), so the lanes of a wave, which
+// hold the samples of one (particle, aircraft), read adjacent elements
+// wherever their positions share a grid cell.
 template <typename R>
 __device__ __forceinline__ void wind_and_grad(const typename V2<R>::t* Wm, const RolloutParams& p,
                                               R x, R y, R z, StepFwd<R>& o) {
@@ -50,11 +53,10 @@ __device__ __forceinline__ void wind_and_grad(const typename V2<R>::t* Wm, const
     const R jz = (uz >= (R)0 && uz <= (R)(p.nz - 1)) ? (R)p.inv_hz : (R)0;
     const int ix = min((int)fx, p.nx - 2), iy = min((int)fy, p.ny - 2), iz = min((int)fz, p.nz - 2);
     const R tx = fx - (R)ix, ty = fy - (R)iy, tz = fz - (R)iz;
-    const int nzz = p.nz, nyz = p.ny * p.nz;
-    const int g = (ix * p.ny + iy) * nzz + iz;
-    const R2 c000 = Wm[g], c001 = Wm[g + 1], c010 = Wm[g + nzz], c011 = Wm[g + nzz + 1];
-    const R2 c100 = Wm[g + nyz], c101 = Wm[g + nyz + 1], c110 = Wm[g + nyz + nzz],
-             c111 = Wm[g + nyz + nzz + 1];
+    const int M = p.M, nzz = p.nz * M, nyz = p.ny * p.nz * M;
+    const R2* Wg = Wm + (int64_t)((ix * p.ny + iy) * p.nz + iz) * M;
+    const R2 c000 = Wg[0], c001 = Wg[M], c010 = Wg[nzz], c011 = Wg[nzz + M];
+    const R2 c100 = Wg[nyz], c101 = Wg[nyz + M], c110 = Wg[nyz + nzz], c111 = Wg[nyz + nzz + M];
     // component x
     {
         const R a00 = c000.x + tz * (c001.x - c000.x), a01 = c010.x + tz * (c011.x - c010.x);
@@ -87,24 +89,54 @@ struct AcConst {
     bool arr;
 };
 
-// One forward step (the rollout's arithmetic, full precision ops).
+// Trilinear wind value only, by the same expressions as wind_and_grad, so
+// the light steps of the forward sweep and of the recomputation produce the
+// same states as the full step of the reverse sweep.
 template <typename R>
-__device__ __forceinline__ void step_forward(const typename V2<R>::t* Wm, const RolloutParams& p,
-                                             const AcConst& ac, R x, R y, R z, R v, R chi, R B,
-                                             R cd, R vc, R zd, R ir, StepFwd<R>& o) {
+__device__ __forceinline__ void wind_value(const typename V2<R>::t* Wm, const RolloutParams& p,
+                                           R x, R y, R z, R& wx, R& wy) {
+    typedef typename V2<R>::t R2;
+    const R ux = (x + (R)p.half_wx) * (R)p.inv_hx;
+    const R uy = (y + (R)p.half_wy) * (R)p.inv_hy;
+    const R uz = z * (R)p.inv_hz;
+    const R fx = clampr(ux, (R)0, (R)(p.nx - 1));
+    const R fy = clampr(uy, (R)0, (R)(p.ny - 1));
+    const R fz = clampr(uz, (R)0, (R)(p.nz - 1));
+    const int ix = min((int)fx, p.nx - 2), iy = min((int)fy, p.ny - 2), iz = min((int)fz, p.nz - 2);
+    const R tx = fx - (R)ix, ty = fy - (R)iy, tz = fz - (R)iz;
+    const int M = p.M, nzz = p.nz * M, nyz = p.ny * p.nz * M;
+    const R2* Wg = Wm + (int64_t)((ix * p.ny + iy) * p.nz + iz) * M;
+    const R2 c000 = Wg[0], c001 = Wg[M], c010 = Wg[nzz], c011 = Wg[nzz + M];
+    const R2 c100 = Wg[nyz], c101 = Wg[nyz + M], c110 = Wg[nyz + nzz], c111 = Wg[nyz + nzz + M];
+    {
+        const R a00 = c000.x + tz * (c001.x - c000.x), a01 = c010.x + tz * (c011.x - c010.x);
+        const R a10 = c100.x + tz * (c101.x - c100.x), a11 = c110.x + tz * (c111.x - c110.x);
+        const R b0 = a00 + ty * (a01 - a00), b1 = a10 + ty * (a11 - a10);
+        wx = b0 + tx * (b1 - b0);
+    }
+    {
+        const R a00 = c000.y + tz * (c001.y - c000.y), a01 = c010.y + tz * (c011.y - c010.y);
+        const R a10 = c100.y + tz * (c101.y - c100.y), a11 = c110.y + tz * (c111.y - c110.y);
+        const R b0 = a00 + ty * (a01 - a00), b1 = a10 + ty * (a11 - a10);
+        wy = b0 + tx * (b1 - b0);
+    }
+}
+
+// Climb, bank, density, drag, thrust and fuel of one step (the rollout's
+// arithmetic), shared by the light and the full step.
+template <typename R>
+__device__ __forceinline__ void step_core(const RolloutParams& p, const AcConst& ac, R z, R v,
+                                          R chi, R B, R cd, R vc, R zd, R ir, StepFwd<R>& o) {
     typedef Ops<R> O;
     const R g0 = (R)kG0;
-    wind_and_grad<R>(Wm, p, x, y, z, o);
     o.sg = zd * O::rcp(v);
     o.cg = O::sqrt((R)1 - o.sg * o.sg);
     o.tphi = v * cd * (R)(1.0 / kG0);
     o.icphi = O::sqrt((R)1 + o.tphi * o.tphi);
     const R isa_c = (R)(kLapse / kT0), isa_e = (R)(kG0 / (kRair * kLapse) - 1.0);
-    const bool zin = z > (R)0 && z < (R)11000;
     const R zc = clampr(z, (R)0, (R)11000);
     const R base = (R)1 - isa_c * zc;
     o.rho = (R)kRho0 * O::pow_pos(base, isa_e);
-    o.drho_dz = zin ? -o.rho * isa_e * isa_c * O::rcp(base) : (R)0;
     o.qd = (R)0.5 * o.rho * v * v;
     o.mass = (R)ac.m0 - B;
     o.CL = O::div(o.mass * g0 * o.icphi, o.qd * (R)ac.Sw);
@@ -114,6 +146,38 @@ __device__ __forceinline__ void step_forward(const typename V2<R>::t* Wm, const 
     o.eta = (R)ac.cf1 * ((R)1 + v * (R)(1.0 / ac.cf2));
     o.f = (R)p.dt * o.eta * m_max(o.T, (R)0);
     O::sincos(chi, &o.sc, &o.cc);
+}
+
+// One full step: the intermediates the reverse sweep needs, with the wind's
+// spatial derivative and the density's altitude derivative.
+template <typename R>
+__device__ __forceinline__ void step_forward(const typename V2<R>::t* Wm, const RolloutParams& p,
+                                             const AcConst& ac, R x, R y, R z, R v, R chi, R B,
+                                             R cd, R vc, R zd, R ir, StepFwd<R>& o) {
+    typedef Ops<R> O;
+    wind_and_grad<R>(Wm, p, x, y, z, o);
+    step_core<R>(p, ac, z, v, chi, B, cd, vc, zd, ir, o);
+    const R isa_c = (R)(kLapse / kT0), isa_e = (R)(kG0 / (kRair * kLapse) - 1.0);
+    const bool zin = z > (R)0 && z < (R)11000;
+    const R zc = clampr(z, (R)0, (R)11000);
+    const R base = (R)1 - isa_c * zc;
+    o.drho_dz = zin ? -o.rho * isa_e * isa_c * O::rcp(base) : (R)0;
+}
+
+// One light step: the next state (x, y, z, v, chi, burn) only.
+template <typename R>
+__device__ __forceinline__ void step_state(const typename V2<R>::t* Wm, const RolloutParams& p,
+                                           const AcConst& ac, R& x, R& y, R& z, R& v, R& chi,
+                                           R& B, R cd, R vc, R zd, R ir) {
+    StepFwd<R> o;
+    wind_value<R>(Wm, p, x, y, z, o.wx, o.wy);
+    step_core<R>(p, ac, z, v, chi, B, cd, vc, zd, ir, o);
+    x = x + (R)p.dt * (v * o.cc * o.cg + o.wx);
+    y = y + (R)p.dt * (v * o.sc * o.cg + o.wy);
+    z = z + (R)p.dt * (v * o.sg);
+    chi = chi + (R)p.dt * cd;
+    v = o.vn;
+    B = B + o.f;
 }
 
 // time-to-go element at a new state and its derivative w.r.t. (x, y, v)
@@ -176,6 +240,7 @@ template <typename R>
 __device__ __forceinline__ bool landed_at(const RolloutParams& p, R x, R y, R z, R v, R chi) {
     typedef Ops<R> O;
     const R r = O::sqrt(x * x + y * y);
+    if (!(r <= (R)p.p_run)) return false;   // outside the runway radius: the angles are not needed
     const R th = O::atan2(y, x);
     const R tha = m_abs(th);
     const R ratio = tha > (R)1e-4 ? tha * O::rcp(m_max(O::sin(tha), (R)1e-6))
@@ -185,8 +250,43 @@ __device__ __forceinline__ bool landed_at(const RolloutParams& p, R x, R y, R z,
            m_abs(wrap_angle<R>(chi - Consts<R>::pi)) <= (R)p.p_chi && v <= (R)p.p_vs;
 }
 
+// Physical controls of segment s of a lane's particle.
 template <typename R>
-__global__ void __launch_bounds__(256) k_rollout_grad(const GradParams gp, const R* __restrict__ u,
+__device__ __forceinline__ void seg_controls(const R* ub, int s, const double* lo, const double* sp,
+                                             R& cd, R& vc, R& zd) {
+    cd = (R)(lo[0] + (double)ub[s * 3 + 0] * sp[0]);
+    vc = (R)(lo[1] + (double)ub[s * 3 + 1] * sp[1]);
+    zd = (R)(lo[2] + (double)ub[s * 3 + 2] * sp[2]);
+}
+
+// Sum of a segment's gradient over the wind samples of each group (a wave
+// reduction in FP64), written by the group's first lane.
+template <typename R>
+__device__ __forceinline__ void flush_segment(const GradParams& gp, int s, const R* gc,
+                                              const double* sp, int m, int64_t grp, int64_t ngrp,
+                                              int l, int i, double* __restrict__ out) {
+    const RolloutParams& p = gp.rp;
+    const int width = gp.Mp < 64 ? gp.Mp : 64;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double vsum = (double)gc[c] * sp[c];   // d u_phys / d u_norm
+        for (int off = width >> 1; off > 0; off >>= 1) vsum += __shfl_xor(vsum, off, width);
+        if ((m % width) == 0 && grp < ngrp) {
+            const int chunk = m / width;
+            out[(((int64_t)chunk * p.P + l) * p.N + i) * p.S * 3 + s * 3 + c] = vsum;
+        }
+    }
+}
+
+// Adjoint of the fuel + time cost of one (particle, aircraft, wind sample)
+// per lane.  The step loops run over absolute steps, the same for every lane
+// of a wave (a lane takes part in the steps k0 <= k <= its last step), so the
+// checkpoints sit at multiples of GR_CK and the tape of a segment's states is
+// indexed by a wave-uniform step: it stays in registers.  A control
+// segment's gradient is summed over its steps in three registers and reduced
+// over the wind samples when the reverse sweep leaves the segment.
+template <typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_rollout_grad(const GradParams gp, const R* __restrict__ u,
                                                       const R* __restrict__ W,
                                                       const double* __restrict__ states,
                                                       const int32_t* __restrict__ k_active,
@@ -213,155 +313,158 @@ __global__ void __launch_bounds__(256) k_rollout_grad(const GradParams gp, const
     ac.arr = kind[i] == 0;
     const int k0 = k_active[i];
     const bool active = valid && k0 >= 0 && k0 < H;
-    const R2* Wm = (const R2*)W + (int64_t)mm * p.G;
+    const R2* Wm = (const R2*)W + mm;           // sample-interleaved field Wt[g][m]
     const R* ub = u + ((int64_t)l * N + i) * S * 3;
     const double lo[3] = {p.ctrl_lo[0], p.ctrl_lo[1], p.ctrl_lo[2]};
     const double sp[3] = {p.ctrl_span[0], p.ctrl_span[1], p.ctrl_span[2]};
+    const R dt = (R)p.dt;
 
-    R gsum[GR_MAXS][3];
-#pragma unroll
-    for (int s = 0; s < GR_MAXS; ++s) gsum[s][0] = gsum[s][1] = gsum[s][2] = (R)0;
-
-    if (active) {
-        R ck[GR_MAXSEG][6];
-        R x = (R)states[i * 6 + 0], y = (R)states[i * 6 + 1], z = (R)states[i * 6 + 2];
-        R v = (R)states[i * 6 + 3], chi = (R)states[i * 6 + 4], B = (R)0;
-        int k_land = H;   // step whose new state lands
-        // forward: checkpoints and landing step
-        for (int k = k0; k < H; ++k) {
-            if (((k - k0) % GR_CK) == 0) {
-                R* c = ck[(k - k0) / GR_CK];
-                c[0] = x; c[1] = y; c[2] = z; c[3] = v; c[4] = chi; c[5] = B;
-            }
-            const int s = (k * S) / H;
-            const int k_end = ((s + 1) * H + S - 1) / S;
-            const R cd = (R)(lo[0] + (double)ub[s * 3 + 0] * sp[0]);
-            const R vc = (R)(lo[1] + (double)ub[s * 3 + 1] * sp[1]);
-            const R zd = (R)(lo[2] + (double)ub[s * 3 + 2] * sp[2]);
-            StepFwd<R> o;
-            step_forward<R>(Wm, p, ac, x, y, z, v, chi, B, cd, vc, zd, Ops<R>::rcp((R)(k_end - k)), o);
-            x = x + (R)p.dt * (v * o.cc * o.cg + o.wx);
-            y = y + (R)p.dt * (v * o.sc * o.cg + o.wy);
-            z = z + (R)p.dt * (v * o.sg);
-            chi = chi + (R)p.dt * cd;
-            v = o.vn;
-            B = B + o.f;
-            if (ac.arr && landed_at<R>(p, x, y, z, v, chi)) { k_land = k; break; }
+    // forward sweep: checkpoints at every GR_CK-th step and the landing step
+    R ck[GR_MAXSEG][6];
+    R x = (R)states[i * 6 + 0], y = (R)states[i * 6 + 1], z = (R)states[i * 6 + 2];
+    R v = (R)states[i * 6 + 3], chi = (R)states[i * 6 + 4], B = (R)0;
+    int k_land = H;   // step whose new state lands (H: none)
+    bool flying = active;
+    int s_cur = -1, k_end = 0;
+    R cd = 0, vc = 0, zd = 0;
+    for (int k = 0; k < H; ++k) {
+        if ((k % GR_CK) == 0) {
+            R* c = ck[k / GR_CK];
+            c[0] = x; c[1] = y; c[2] = z; c[3] = v; c[4] = chi; c[5] = B;
         }
-        // reverse sweep
-        const int nsteps = H - k0;
-        const double wf = ac.arr ? p.w[2] : p.w[4];
-        const double denom = p.dt * (double)nsteps * ac.tmax * (ac.cf1 * (1.0 + p.vmax / ac.cf2));
-        const R kf = (R)((1.0 - p.w[7] - p.w[8]) * wf / denom);
-        const R kt = (R)(p.w[7] / (double)nsteps);
-        R ax = 0, ay = 0, az = 0, av = 0, achi = 0, aB = kf;
-        const int k_last = min(k_land, H - 1);
-        const int nseg = (k_last - k0) / GR_CK + 1;
-        R tape[GR_CK][6];
-        for (int sg_i = nseg - 1; sg_i >= 0; --sg_i) {
-            const int ka = k0 + sg_i * GR_CK;
-            const int kb = min(k_last, ka + GR_CK - 1);
-            {   // recompute the segment's step-start states
-                const R* c = ck[sg_i];
-                R x1 = c[0], y1 = c[1], z1 = c[2], v1 = c[3], chi1 = c[4], B1 = c[5];
-                for (int k = ka; k <= kb; ++k) {
-                    R* tp = tape[k - ka];
-                    tp[0] = x1; tp[1] = y1; tp[2] = z1; tp[3] = v1; tp[4] = chi1; tp[5] = B1;
-                    if (k == kb) break;
-                    const int s = (k * S) / H;
-                    const int k_end = ((s + 1) * H + S - 1) / S;
-                    const R cd = (R)(lo[0] + (double)ub[s * 3 + 0] * sp[0]);
-                    const R vc = (R)(lo[1] + (double)ub[s * 3 + 1] * sp[1]);
-                    const R zd = (R)(lo[2] + (double)ub[s * 3 + 2] * sp[2]);
-                    StepFwd<R> o;
-                    step_forward<R>(Wm, p, ac, x1, y1, z1, v1, chi1, B1, cd, vc, zd,
-                                    Ops<R>::rcp((R)(k_end - k)), o);
-                    x1 = x1 + (R)p.dt * (v1 * o.cc * o.cg + o.wx);
-                    y1 = y1 + (R)p.dt * (v1 * o.sc * o.cg + o.wy);
-                    z1 = z1 + (R)p.dt * (v1 * o.sg);
-                    chi1 = chi1 + (R)p.dt * cd;
-                    v1 = o.vn;
-                    B1 = B1 + o.f;
-                }
-            }
-            for (int k = kb; k >= ka; --k) {
-                const R* tp = tape[k - ka];
-                const R x0 = tp[0], y0 = tp[1], z0 = tp[2], v0 = tp[3], chi0 = tp[4], B0 = tp[5];
-                const int s = (k * S) / H;
-                const int k_end = ((s + 1) * H + S - 1) / S;
-                const R ir = Ops<R>::rcp((R)(k_end - k));
-                const R cd = (R)(lo[0] + (double)ub[s * 3 + 0] * sp[0]);
-                const R vc = (R)(lo[1] + (double)ub[s * 3 + 1] * sp[1]);
-                const R zd = (R)(lo[2] + (double)ub[s * 3 + 2] * sp[2]);
-                StepFwd<R> o;
-                step_forward<R>(Wm, p, ac, x0, y0, z0, v0, chi0, B0, cd, vc, zd, ir, o);
-                const R dt = (R)p.dt;
-                const R xn = x0 + dt * (v0 * o.cc * o.cg + o.wx);
-                const R yn = y0 + dt * (v0 * o.sc * o.cg + o.wy);
-                // time element at the new state (counted unless this step lands)
-                if (k < k_land) {
-                    R dx, dy, dv;
-                    time_elem<R>(p, ac, xn, yn, o.vn, &dx, &dy, &dv);
-                    ax += kt * dx; ay += kt * dy; av += kt * dv;
-                }
-                // fuel f = dt eta max(T, 0)
-                R df_dv = 0, df_dvc = 0, df_dzd = 0, df_dcd = 0, df_dz = 0, df_dm = 0;
-                if (o.T > (R)0) {
-                    const R g0 = (R)kG0;
-                    const R A0 = o.qd * (R)ac.Sw;
-                    const R dD_dA0 = (R)ac.cd0 - (R)ac.cd2 * o.CL * o.CL;
-                    const R dD_dK = (R)2 * (R)ac.cd2 * o.CL;
-                    const R inv_dt = (R)(1.0 / p.dt);
-                    const R dT_dv = -o.mass * ir * inv_dt + dD_dA0 * ((R)2 * A0 * Ops<R>::rcp(v0)) +
-                                    dD_dK * o.mass * g0 * (o.tphi * Ops<R>::rcp(o.icphi)) * (cd * (R)(1.0 / kG0)) -
-                                    o.mass * g0 * o.sg * Ops<R>::rcp(v0);
-                    const R dT_dvc = o.mass * ir * inv_dt;
-                    const R dT_dzd = o.mass * g0 * Ops<R>::rcp(v0);
-                    const R dT_dcd = dD_dK * o.mass * g0 * (o.tphi * Ops<R>::rcp(o.icphi)) * (v0 * (R)(1.0 / kG0));
-                    const R dT_dz = dD_dA0 * (A0 * Ops<R>::rcp(o.rho)) * o.drho_dz;
-                    const R dT_dm = (o.vn - v0) * inv_dt + dD_dK * g0 * o.icphi + g0 * o.sg;
-                    const R dt_eta = dt * o.eta;
-                    df_dv = dt * (R)(ac.cf1 / ac.cf2) * o.T + dt_eta * dT_dv;
-                    df_dvc = dt_eta * dT_dvc;
-                    df_dzd = dt_eta * dT_dzd;
-                    df_dcd = dt_eta * dT_dcd;
-                    df_dz = dt_eta * dT_dz;
-                    df_dm = dt_eta * dT_dm;
-                }
-                const R icg = Ops<R>::rcp(o.cg);
-                // adjoints of the step's inputs
-                const R nx_ = ax * ((R)1 + dt * o.dwx[0]) + ay * dt * o.dwy[0];
-                const R ny_ = ax * dt * o.dwx[1] + ay * ((R)1 + dt * o.dwy[1]);
-                const R nz_ = az + ax * dt * o.dwx[2] + ay * dt * o.dwy[2] + aB * df_dz;
-                const R nchi = achi + ax * dt * (-v0 * o.sc * o.cg) + ay * dt * (v0 * o.cc * o.cg);
-                const R nv = av * ((R)1 - ir) + ax * dt * o.cc * icg + ay * dt * o.sc * icg + aB * df_dv;
-                const R nB = aB - aB * df_dm;
-                const R g_cd = achi * dt + aB * df_dcd;
-                const R g_vc = av * ir + aB * df_dvc;
-                const R g_zd = ax * dt * o.cc * (-o.sg * icg) + ay * dt * o.sc * (-o.sg * icg) + az * dt +
-                               aB * df_dzd;
-#pragma unroll
-                for (int q = 0; q < GR_MAXS; ++q)
-                    if (q == s) { gsum[q][0] += g_cd; gsum[q][1] += g_vc; gsum[q][2] += g_zd; }
-                ax = nx_; ay = ny_; az = nz_; achi = nchi; av = nv; aB = nB;
-            }
+        const int s = (k * S) / H;
+        if (s != s_cur) {   // wave-uniform
+            s_cur = s;
+            k_end = ((s + 1) * H + S - 1) / S;
+            seg_controls<R>(ub, s, lo, sp, cd, vc, zd);
+        }
+        if (flying && k >= k0) {
+            step_state<R>(Wm, p, ac, x, y, z, v, chi, B, cd, vc, zd, Ops<R>::rcp((R)(k_end - k)));
+            if (ac.arr && landed_at<R>(p, x, y, z, v, chi)) { k_land = k; flying = false; }
         }
     }
 
-    // sum over the wind samples of the group: wave reduction in FP64
-    const int width = Mp < 64 ? Mp : 64;
-#pragma unroll
-    for (int q = 0; q < GR_MAXS; ++q) {
-        if (q >= S) break;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double vsum = (double)gsum[q][c] * sp[c];   // d u_phys / d u_norm
-            for (int off = width >> 1; off > 0; off >>= 1) vsum += __shfl_xor(vsum, off, width);
-            if ((m % width) == 0 && grp < ngrp) {
-                const int chunk = m / width;
-                out[(((int64_t)chunk * p.P + l) * N + i) * S * 3 + q * 3 + c] = vsum;
+    // reverse sweep, segment by segment from the last
+    const int k_last = min(k_land, H - 1);
+    const int nsteps = H - k0;
+    const double wf = ac.arr ? p.w[2] : p.w[4];
+    const double denom = p.dt * (double)nsteps * ac.tmax * (ac.cf1 * (1.0 + p.vmax / ac.cf2));
+    const R kf = (R)((1.0 - p.w[7] - p.w[8]) * wf / denom);
+    const R kt = (R)(p.w[7] / (double)nsteps);
+    R ax = 0, ay = 0, az = 0, av = 0, achi = 0, aB = kf;
+    R gc[3] = {(R)0, (R)0, (R)0};
+    R tx_[GR_CK], ty_[GR_CK], tz_[GR_CK], tv_[GR_CK], tchi_[GR_CK], tB_[GR_CK];
+    const int nseg = (H + GR_CK - 1) / GR_CK;
+    int s_grad = S - 1;      // segment whose gradient gc holds
+    s_cur = -1;
+    for (int j = nseg - 1; j >= 0; --j) {
+        const int ka = j * GR_CK;
+        const int kb = min(H, ka + GR_CK) - 1;
+        {   // the segment's step-start states from its checkpoint
+            R x1 = ck[j][0], y1 = ck[j][1], z1 = ck[j][2], v1 = ck[j][3], chi1 = ck[j][4],
+              B1 = ck[j][5];
+            for (int k = ka; k <= kb; ++k) {
+                const int q = k - ka;
+                tx_[q] = x1; ty_[q] = y1; tz_[q] = z1; tv_[q] = v1; tchi_[q] = chi1; tB_[q] = B1;
+                if (k == kb) break;
+                const int s = (k * S) / H;
+                if (s != s_cur) {
+                    s_cur = s;
+                    k_end = ((s + 1) * H + S - 1) / S;
+                    seg_controls<R>(ub, s, lo, sp, cd, vc, zd);
+                }
+                if (active && k >= k0 && k <= k_last)
+                    step_state<R>(Wm, p, ac, x1, y1, z1, v1, chi1, B1, cd, vc, zd,
+                                  Ops<R>::rcp((R)(k_end - k)));
             }
         }
+        for (int k = kb; k >= ka; --k) {
+            const int q = k - ka;
+            const int s = (k * S) / H;
+            if (s != s_grad) {   // wave-uniform: the reverse sweep leaves segment s_grad
+                flush_segment<R>(gp, s_grad, gc, sp, m, grp, ngrp, l, i, out);
+                gc[0] = gc[1] = gc[2] = (R)0;
+                s_grad = s;
+            }
+            if (s != s_cur) {
+                s_cur = s;
+                k_end = ((s + 1) * H + S - 1) / S;
+                seg_controls<R>(ub, s, lo, sp, cd, vc, zd);
+            }
+            if (!(active && k >= k0 && k <= k_last)) continue;
+            const R x0 = tx_[q], y0 = ty_[q], z0 = tz_[q], v0 = tv_[q], chi0 = tchi_[q],
+                    B0 = tB_[q];
+            const R ir = Ops<R>::rcp((R)(k_end - k));
+            StepFwd<R> o;
+            step_forward<R>(Wm, p, ac, x0, y0, z0, v0, chi0, B0, cd, vc, zd, ir, o);
+            const R xn = x0 + dt * (v0 * o.cc * o.cg + o.wx);
+            const R yn = y0 + dt * (v0 * o.sc * o.cg + o.wy);
+            // time element at the new state (counted unless this step lands)
+            if (k < k_land) {
+                R dx, dy, dv;
+                time_elem<R>(p, ac, xn, yn, o.vn, &dx, &dy, &dv);
+                ax += kt * dx; ay += kt * dy; av += kt * dv;
+            }
+            // fuel f = dt eta max(T, 0)
+            R df_dv = 0, df_dvc = 0, df_dzd = 0, df_dcd = 0, df_dz = 0, df_dm = 0;
+            if (o.T > (R)0) {
+                const R g0 = (R)kG0;
+                const R A0 = o.qd * (R)ac.Sw;
+                const R dD_dA0 = (R)ac.cd0 - (R)ac.cd2 * o.CL * o.CL;
+                const R dD_dK = (R)2 * (R)ac.cd2 * o.CL;
+                const R inv_dt = (R)(1.0 / p.dt);
+                const R dT_dv = -o.mass * ir * inv_dt + dD_dA0 * ((R)2 * A0 * Ops<R>::rcp(v0)) +
+                                dD_dK * o.mass * g0 * (o.tphi * Ops<R>::rcp(o.icphi)) * (cd * (R)(1.0 / kG0)) -
+                                o.mass * g0 * o.sg * Ops<R>::rcp(v0);
+                const R dT_dvc = o.mass * ir * inv_dt;
+                const R dT_dzd = o.mass * g0 * Ops<R>::rcp(v0);
+                const R dT_dcd = dD_dK * o.mass * g0 * (o.tphi * Ops<R>::rcp(o.icphi)) * (v0 * (R)(1.0 / kG0));
+                const R dT_dz = dD_dA0 * (A0 * Ops<R>::rcp(o.rho)) * o.drho_dz;
+                const R dT_dm = (o.vn - v0) * inv_dt + dD_dK * g0 * o.icphi + g0 * o.sg;
+                const R dt_eta = dt * o.eta;
+                df_dv = dt * (R)(ac.cf1 / ac.cf2) * o.T + dt_eta * dT_dv;
+                df_dvc = dt_eta * dT_dvc;
+                df_dzd = dt_eta * dT_dzd;
+                df_dcd = dt_eta * dT_dcd;
+                df_dz = dt_eta * dT_dz;
+                df_dm = dt_eta * dT_dm;
+            }
+            const R icg = Ops<R>::rcp(o.cg);
+            // adjoints of the step's inputs
+            const R nx_ = ax * ((R)1 + dt * o.dwx[0]) + ay * dt * o.dwy[0];
+            const R ny_ = ax * dt * o.dwx[1] + ay * ((R)1 + dt * o.dwy[1]);
+            const R nz_ = az + ax * dt * o.dwx[2] + ay * dt * o.dwy[2] + aB * df_dz;
+            const R nchi = achi + ax * dt * (-v0 * o.sc * o.cg) + ay * dt * (v0 * o.cc * o.cg);
+            const R nv = av * ((R)1 - ir) + ax * dt * o.cc * icg + ay * dt * o.sc * icg + aB * df_dv;
+            const R nB = aB - aB * df_dm;
+            gc[0] += achi * dt + aB * df_dcd;
+            gc[1] += av * ir + aB * df_dvc;
+            gc[2] += ax * dt * o.cc * (-o.sg * icg) + ay * dt * o.sc * (-o.sg * icg) + az * dt +
+                     aB * df_dzd;
+            ax = nx_; ay = ny_; az = nz_; achi = nchi; av = nv; aB = nB;
+        }
+    }
+    flush_segment<R>(gp, s_grad, gc, sp, m, grp, ngrp, l, i, out);
+}
+
+// W[m][g] -> Wt[g][m] (pairs of reals), one 32 x 32 tile per workgroup
+// through LDS so that both the reads and the writes are coalesced.
+template <typename R>
+__global__ void __launch_bounds__(256) k_wind_transpose(const typename V2<R>::t* __restrict__ W,
+                                                        int M, int G,
+                                                        typename V2<R>::t* __restrict__ Wt) {
+    typedef typename V2<R>::t R2;
+    __shared__ R2 tile[32][33];
+    const int g0 = blockIdx.x * 32, m0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int m = m0 + r, g = g0 + tx;
+        if (m < M && g < G) tile[r][tx] = W[(int64_t)m * G + g];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int g = g0 + r, m = m0 + tx;
+        if (m < M && g < G) Wt[(int64_t)g * M + m] = tile[tx][r];
     }
 }
 
@@ -394,9 +497,20 @@ bool grad_supported(int H, int S) {
 
 hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u, const void* W,
                                const double* states, const int32_t* k_active, const double* acpar,
-                               const double* targets, const int8_t* kind, double* partial,
+                               const double* targets, const int8_t* kind, void* Wt, double* partial,
                                double* grad_out, hipStream_t st) {
     if (!grad_supported(rp.H, rp.S)) return hipErrorInvalidValue;
+    {
+        const dim3 tg((unsigned)((rp.G + 31) / 32), (unsigned)((rp.M + 31) / 32));
+        if (prec == 0)
+            hipLaunchKernelGGL(k_wind_transpose<double>, tg, dim3(256), 0, st, (const double2*)W,
+                               rp.M, rp.G, (double2*)Wt);
+        else
+            hipLaunchKernelGGL(k_wind_transpose<float>, tg, dim3(256), 0, st, (const float2*)W,
+                               rp.M, rp.G, (float2*)Wt);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     GradParams gp;
     gp.rp = rp;
     gp.Mp = grad_lanes_per_group(rp.M);
@@ -406,11 +520,11 @@ hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u,
     double* dst = gp.chunks > 1 ? partial : grad_out;
     if (prec == 0)
         hipLaunchKernelGGL(k_rollout_grad<double>, dim3(blocks), dim3(256), 0, st, gp,
-                           (const double*)u, (const double*)W, states, k_active, acpar, targets,
+                           (const double*)u, (const double*)Wt, states, k_active, acpar, targets,
                            kind, dst);
     else
         hipLaunchKernelGGL(k_rollout_grad<float>, dim3(blocks), dim3(256), 0, st, gp,
-                           (const float*)u, (const float*)W, states, k_active, acpar, targets,
+                           (const float*)u, (const float*)Wt, states, k_active, acpar, targets,
                            kind, dst);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || gp.chunks == 1) return e;

@@ -55,7 +55,7 @@ struct smc_ctx {
     int8_t* d_kind = nullptr;
     float* d_pop = nullptr;
     void* d_Lfac = nullptr;
-    void *d_Z = nullptr, *d_W = nullptr;
+    void *d_Z = nullptr, *d_W = nullptr, *d_Wt = nullptr;
     void *d_u = nullptr, *d_u2 = nullptr, *d_up = nullptr;
     double* d_cost = nullptr;
     uint8_t* d_feas = nullptr;
@@ -313,7 +313,7 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
             const double eps = c->mala_step;
             if (info) HIP_OK(c, hipEventRecord(c->ev_grad[4 * J], st));
             HIP_OK(c, launch_rollout_grad(c->prec, rp, u, c->d_W, d_states, d_kact, c->d_acpar,
-                                          c->d_targets, c->d_kind, c->d_gpart, c->d_g, st));
+                                          c->d_targets, c->d_kind, c->d_Wt, c->d_gpart, c->d_g, st));
             if (info) HIP_OK(c, hipEventRecord(c->ev_grad[4 * J + 1], st));
             HIP_OK(c, launch_mala_propose(c->prec, count, u, c->d_g, coef, eps,
                                           make_stream(c->seed, mpc_step, J, P_MALA, c->scen_id),
@@ -329,7 +329,7 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
                                     c->d_feaspn2, c->d_logw2, st));
             if (info) HIP_OK(c, hipEventRecord(c->ev_grad[4 * J + 2], st));
             HIP_OK(c, launch_rollout_grad(c->prec, rp, c->d_up, c->d_W, d_states, d_kact, c->d_acpar,
-                                          c->d_targets, c->d_kind, c->d_gpart, c->d_g2, st));
+                                          c->d_targets, c->d_kind, c->d_Wt, c->d_gpart, c->d_g2, st));
             if (info) HIP_OK(c, hipEventRecord(c->ev_grad[4 * J + 3], st));
             HIP_OK(c, launch_mala_decide(c->prec, L, N, D, u, c->d_up, c->d_g, c->d_g2, coef, eps,
                                          c->d_logw, c->d_logw2,
@@ -641,7 +641,7 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     if ((st = dalloc_t(c, &c->d_acpar, N * SMC_AC_NPAR)) || (st = dalloc_t(c, &c->d_targets, N * 4)) ||
         (st = dalloc_t(c, &c->d_kind, N)) ||
         (st = dalloc(c, &c->d_Lfac, G * G * c->rsz)) || (st = dalloc(c, &c->d_Z, G * 2 * M * c->rsz)) ||
-        (st = dalloc(c, &c->d_W, M * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_u, L * N * D * c->rsz)) ||
+        (st = dalloc(c, &c->d_W, M * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_Wt, M * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_u, L * N * D * c->rsz)) ||
         (st = dalloc(c, &c->d_u2, L * N * D * c->rsz)) ||
         (st = dalloc(c, &c->d_up, (c->move != SMC_MOVE_JITTER ? L : 1) * N * D * c->rsz)) ||
         (st = dalloc_t(c, &c->d_cost, M * L * N)) || (st = dalloc_t(c, &c->d_feas, M * L * N)) ||
@@ -917,7 +917,7 @@ smc_status smc_k_rollout_grad(smc_ctx* c, const void* u, int32_t P, const void* 
     rp.H = horizon;
     rp.P = P;
     HIP_OK(c, launch_rollout_grad(c->prec, rp, u, W, states, k_active, c->d_acpar, c->d_targets,
-                                  c->d_kind, c->d_gpart, grad, pick(c, stream)));
+                                  c->d_kind, c->d_Wt, c->d_gpart, grad, pick(c, stream)));
     return SMC_OK;
 }
 
