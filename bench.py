@@ -194,6 +194,85 @@ def bench_batch(args, desc):
     print(json.dumps(out), flush=True)
 
 
+def compare_moves(args):
+    """Wall time per MPC update for each move (Langevin with the adjoint's
+    gradient, random-walk Metropolis, and the paper's jitter) to reach the
+    converged expected cost of plain random-walk SMC on the differentiable
+    workload (C4).  Every returned control sequence is re-scored by the
+    library on one fixed set of wind fields drawn from an iteration word that
+    no run uses, so costs are comparable across runs; a run reaches the target
+    if its controls are feasible under those fields and score within 1e-3 of
+    random-walk SMC at the largest iteration count.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1506_02869_amd as smc
+    import synth
+
+    iters = [int(k) for k in args.compare_iters.split(",")]
+    j_eval = 1 << 20
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda")
+    runs = {}
+    for move in ("rwmh", "mala", "jitter"):
+        runs[move] = []
+        for K in iters:
+            scen = synth.c4(move=move, K=K)
+            ctx = smc.smc_mpc_init(scen)
+            states = torch.as_tensor(scen["states"], dtype=torch.float64, device=dev)
+            kact = torch.as_tensor(scen["k_active"], dtype=torch.int32, device=dev)
+            ctrl = torch.empty((scen["N"], scen["S"], 3), dtype=torch.float64, device=dev)
+            cost = torch.empty(1 + scen["N"], dtype=torch.float64, device=dev)
+            status = torch.zeros(1, dtype=torch.int32, device=dev)
+
+            def one():
+                smc.smc_mpc_step_dev(ctx, int(scen["mpc_step"]), states, kact,
+                                     scen["wind_mean"], scen["H"], ctrl, cost, status)
+
+            one()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            one()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            _, info = smc.smc_mpc_step_dev(ctx, int(scen["mpc_step"]), states, kact,
+                                           scen["wind_mean"], scen["H"], ctrl, cost, status,
+                                           want_info=True)
+            u = (ctrl.cpu().numpy() - scen["ctrl_lo"]) / (scen["ctrl_hi"] - scen["ctrl_lo"])
+            ec, ef = smc.smc_eval_cost(ctx, u[None], j_eval)
+            score = float(ec.sum())
+            feas = bool(np.all(ef))
+            runs[move].append({"K": K, "ms_per_update": round(ms, 1), "score": score,
+                               "feasible": feas, "returned_cost": float(cost[0].item()),
+                               "accept_rate": round(info["accept_rate"], 6),
+                               "feasible_frac": round(info["feasible_frac"], 4)})
+            print(f"compare-moves {move} K={K}: {ms:.1f} ms, score {score:.6f} "
+                  f"(feasible {feas})", file=sys.stderr, flush=True)
+            ctx.close()
+    ref = runs["rwmh"][-1]["score"]
+    target = ref * (1.0 + 1e-3)
+
+    def reach(move):
+        for r in runs[move]:
+            if r["feasible"] and r["score"] <= target:
+                return r
+        return None
+
+    out = {"metric": "wall time per MPC update to reach plain SMC's converged expected cost "
+                     "within 1e-3 relative", "workload": WORKLOADS["c4"][0],
+           "converged_cost": ref, "converged_from": f"rwmh, K={runs['rwmh'][-1]['K']}",
+           "scoring": f"smc_eval_cost on the wind fields of iteration word {j_eval}",
+           "runs": runs}
+    rr = reach("rwmh")
+    for move in ("mala", "jitter"):
+        rm = reach(move)
+        out[f"{move}_reaches"] = rm
+        out[f"{move}_speedup_vs_rwmh"] = (None if rm is None or rr is None
+                                          else round(rr["ms_per_update"] / rm["ms_per_update"], 3))
+    out["rwmh_reaches"] = rr
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +284,9 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="batched workload: autotune the persistent rollout's launch shape first")
+    ap.add_argument("--compare-moves", action="store_true",
+                    help="C4: time each move to reach plain SMC's converged cost")
+    ap.add_argument("--compare-iters", default="5,10,20,40,80,160")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -226,6 +308,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.compare_moves:
+        return compare_moves(args)
     desc, key = WORKLOADS[args.workload]
     if key == "c3":
         return bench_batch(args, desc)
