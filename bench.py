@@ -57,6 +57,10 @@ WORKLOADS = {
            "FP32 rollout and adjoint with FP64 weights, scan and gradient sums, MALA moves "
            "(step 1e-2) driven by the adjoint of the fuel + time cost, checkpoint every "
            "25 steps", "c4"),
+    "c5": ("large form: 40 aircraft (24 arrivals, 16 departures, 780 pairs), 150x150x10 km, "
+           "H=180 dt=5 s, S=12, fuel + time + noise (256x256 lognormal population below "
+           "2 km), wind 64x64x8 (G=32768) M=128, L=65536, K=60, FP32 rollout "
+           "(aircraft-per-lane) with FP64 weights and scan, jitter moves", "c5"),
 }
 
 
@@ -329,8 +333,12 @@ def main():
         return smc.smc_mpc_step_dev(ctx, step_id, states, kact, wm, scen["H"], ctrl, cost,
                                     status, want_info=info)
 
+    def note(msg):
+        print(f"bench {args.workload}: {msg}", file=sys.stderr, flush=True)
+
     # one instrumented update: work count and per-kernel event timings
     _, info0 = one(info=True)
+    note(f"instrumented update {info0['ms_total']:.1f} ms")
     for _ in range(args.warmup):
         one()
     torch.cuda.synchronize()
@@ -340,8 +348,9 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
+    note(f"{args.steps} timed updates, {ms_step:.1f} ms each")
     # per-kernel timings over instrumented updates (event pairs on the stream
-    # the kernels run on)
+    # the kernels run on); the last one's outputs are also the cost check's
     infos = [one(info=True)[1] for _ in range(max(1, min(args.steps, 3)))]
     torch.cuda.synchronize()
     aircraft_steps = info0["aircraft_steps"]
@@ -397,8 +406,6 @@ def main():
         # re-score the returned controls with the FP64 oracle on the last
         # iteration's wind fields
         from oracle import smc as osmc
-        one()
-        torch.cuda.synchronize()
         c_ctrl = ctrl.cpu().numpy()
         c_cost = cost.cpu().numpy()
         u = (c_ctrl - scen["ctrl_lo"]) / (scen["ctrl_hi"] - scen["ctrl_lo"])

@@ -6,6 +6,13 @@ include/smc_kernels.h and include/smc_batch.h.  Function names follow the C ABI.
 torch tensors on a HIP device (PyTorch provides device memory and streams);
 host arrays are NumPy arrays.
 
+Streams: device-form calls take ``stream`` (a torch stream; default: torch's
+current stream).  Torch's default stream has the handle 0, which the library
+reads as "the context's own stream": work is then queued there and is not
+ordered with torch's default stream, so call ``torch.cuda.synchronize()``
+before torch reads the outputs (or pass a non-default torch stream, on which
+library and torch work are ordered).
+
 The library must be built first (``python -m paper_1506_02869_amd.build``);
 importing this package without it raises at the first call.
 """

@@ -53,6 +53,10 @@ def separable_field(scen, seed, M=None):
     M = scen["M"] if M is None else M
     nx, ny, nz = (int(n) for n in scen["grid"])
     Z = np.random.default_rng(seed).standard_normal((nx, ny, nz, M, 2))
-    W = np.einsum("ai,bj,ck,ijkmq->abcmq", Lx, Ly, Lz, Z) * scen["wind_sigma"]
+    # one axis at a time: (Lx kron Ly kron Lz) Z without the G x G matrix
+    W = np.tensordot(Lx, Z, axes=(1, 0))                            # a j k m q
+    W = np.moveaxis(np.tensordot(Ly, W, axes=(1, 1)), 0, 1)         # a b k m q
+    W = np.moveaxis(np.tensordot(Lz, W, axes=(1, 2)), 0, 2)         # a b c m q
+    W = W * scen["wind_sigma"]
     W = W.reshape(nx * ny * nz, M, 2).transpose(1, 0, 2).copy()
     return W + np.asarray(scen["wind_mean"])[None, None, :]

@@ -61,6 +61,25 @@ def test_eval_cost_matches_oracle(lib, prec):
     assert np.all(rel_err(cost, rc)[ok] < (1e-6 if prec == "fp64" else 2e-5))
 
 
+def _check_sampled_worlds(s, u, W, cost_at, feas_at, picks):
+    """Compare the (particle, sample) worlds in picks with the oracle one by
+    one: feasibility exactly, per-aircraft cost within 2e-5 relative (FP32),
+    skipping worlds with a discrete decision within 1e-4 of its threshold.
+    Returns the number of worlds compared."""
+    bad = compared = 0
+    for (p, m) in picks:
+        r = oro.rollout(s, u[p:p + 1].astype(np.float64), W[m:m + 1].astype(np.float64),
+                        with_margins=True)
+        if (r["margin"] < 1e-4).any():
+            continue
+        compared += 1
+        assert np.array_equal(feas_at(p, m), r["feas"][0, 0]), (p, m)
+        e = rel_err(cost_at(p, m), r["cost"][0, 0])
+        bad += int((e > 2e-5).sum())
+    assert bad == 0
+    return compared
+
+
 @pytest.mark.parametrize("layout", [0, 1])
 def test_full_size_c2_rollout_sampled(lib, layout):
     """C2 at full size (8192 particles x 64 wind samples x 10 aircraft x 120
@@ -81,16 +100,81 @@ def test_full_size_c2_rollout_sampled(lib, layout):
     gc, gf = host(cost), host(feas).astype(bool)
     picks = [(int(rng.integers(P)), int(rng.integers(M))) for _ in range(48)]
     picks += [(0, 0), (P - 1, M - 1)]
-    bad = 0
-    for (p, m) in picks:
-        r = oro.rollout(s, u[p:p + 1].astype(np.float64), W[m:m + 1].astype(np.float64),
-                        with_margins=True)
-        if (r["margin"] < 1e-4).any():
-            continue
-        assert np.array_equal(gf[m, p], r["feas"][0, 0])
-        e = rel_err(gc[m, p], r["cost"][0, 0])
-        bad += int((e > 2e-5).sum())
-    assert bad == 0
+    n = _check_sampled_worlds(s, u, W, lambda p, m: gc[m, p], lambda p, m: gf[m, p], picks)
+    assert n >= 40
+
+
+def test_full_size_c4_rollout_and_adjoint_sampled(lib):
+    """C4 at full size (16384 particles x 64 wind samples x 20 aircraft x 150
+    steps: the 20-aircraft world-per-lane rollout and the adjoint, the
+    launches the benchmark times).  24 random worlds against the oracle's
+    rollout; the summed fuel + time gradient of 4 random particles (all
+    aircraft, all 64 samples) against the FP64 autograd reference, excluding
+    aircraft with a landing decision within 1e-4 of its threshold."""
+    import torch
+    from oracle import grad as og
+    s = synth.c4()
+    ctx = lib.smc_mpc_init(s)
+    P, M, N, S = s["L"], s["M"], s["N"], s["S"]
+    rng = np.random.default_rng(12)
+    u = rng.uniform(0, 1, (P, N, S, 3)).astype(np.float32)
+    W = separable_field(s, 6).astype(np.float32)
+    du, dW = dev(u), dev(W)
+    cost = empty((M, P, N), torch.float64)
+    feas = empty((M, P, N), torch.uint8)
+    lib.smc_k_rollout(ctx, du, P, dW, dev(s["states"]), dev(s["k_active"]), s["H"], cost, feas)
+    g = empty((P, N, S, 3), torch.float64)
+    lib.smc_k_rollout_grad(ctx, du, P, dW, dev(s["states"]), dev(s["k_active"]), s["H"], g)
+    gc, gf, gg = host(cost), host(feas).astype(bool), host(g)
+    picks = [(int(rng.integers(P)), int(rng.integers(M))) for _ in range(22)]
+    picks += [(0, 0), (P - 1, M - 1)]
+    n = _check_sampled_worlds(s, u, W, lambda p, m: gc[m, p], lambda p, m: gf[m, p], picks)
+    assert n >= 16
+    W64 = W.astype(np.float64)
+    checked = 0
+    for p in [int(x) for x in rng.integers(P, size=4)]:
+        u64 = u[p:p + 1].astype(np.float64)
+        r = oro.rollout(s, u64, W64, with_margins=True)
+        keep = (r["margin"][0] >= 1e-4).all(axis=0)          # per aircraft, over samples
+        _, ref = og.grad_fuel_time(s, u64, W64)
+        ref = ref[0] * M                                     # sum over the samples
+        got = gg[p]
+        scale = np.abs(ref[keep]).max()
+        err = np.abs(got[keep] - ref[keep])
+        assert err.max() <= 2e-3 * scale, (p, err.max() / scale)
+        assert np.median(err / np.maximum(np.abs(ref[keep]), 1e-3 * scale)) < 1e-4
+        checked += int(keep.sum())
+    assert checked >= 60
+
+
+def test_full_size_c5_rollout_sampled(lib):
+    """C5 at full size (65536 particles x 128 wind samples x 40 aircraft x
+    180 steps, 780 pairs, noise term over a 256 x 256 population grid: the
+    aircraft-per-lane rollout the benchmark times); 24 random worlds against
+    the oracle one by one (sampled on the device, only they are copied)."""
+    import torch
+    s = synth.c5()
+    ctx = lib.smc_mpc_init(s)
+    P, M, N, S = s["L"], s["M"], s["N"], s["S"]
+    rng = np.random.default_rng(13)
+    u = rng.uniform(0, 1, (P, N, S, 3)).astype(np.float32)
+    W = separable_field(s, 7).astype(np.float32)
+    cost = empty((M, P, N), torch.float64)
+    feas = empty((M, P, N), torch.uint8)
+    lib.smc_k_rollout(ctx, dev(u), P, dev(W), dev(s["states"]), dev(s["k_active"]), s["H"],
+                      cost, feas)
+    picks = [(int(rng.integers(P)), int(rng.integers(M))) for _ in range(22)]
+    picks += [(0, 0), (P - 1, M - 1)]
+    # the rollout ran on the context's own stream: wait for it before torch
+    # gathers the sampled worlds on its stream
+    torch.cuda.synchronize()
+    pi = torch.as_tensor([p for p, _ in picks], device=cost.device)
+    mi = torch.as_tensor([m for _, m in picks], device=cost.device)
+    sc, sf = host(cost[mi, pi]), host(feas[mi, pi]).astype(bool)
+    at = {pm: k for k, pm in enumerate(picks)}
+    n = _check_sampled_worlds(s, u, W, lambda p, m: sc[at[(p, m)]],
+                              lambda p, m: sf[at[(p, m)]], picks)
+    assert n >= 12
 
 
 def test_all_infeasible_returns_warning(lib):
