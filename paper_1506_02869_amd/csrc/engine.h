@@ -11,6 +11,9 @@ namespace smc {
 constexpr int kMaxAircraft = 64;
 constexpr int kStepSlots = 64;   // striped counters of simulated aircraft-steps
 constexpr int kWorldLaneMaxN = 20;  // largest N of the world-per-lane rollout
+// Largest workgroup of the aircraft-per-lane rollout (FP32 / FP64 lanes).
+constexpr int kRolloutMaxBlock32 = 1024;
+constexpr int kRolloutMaxBlock64 = 256;
 constexpr int kAcR = 16;            // per-aircraft parameters in the rollout's precision
 
 // Constants of the world-per-lane rollout in its own precision, derived on

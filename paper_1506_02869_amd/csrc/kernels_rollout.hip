@@ -11,35 +11,60 @@
 //   unary checks (Sec. "Constraint Handling") -> landing sector test
 //   (eq. TO_init) -> per-step cost elements (Sec. "Particle Costing",
 //   "Noise Pollution Reduction") -> pairwise separation (eq. avoidance)
-//   through an LDS exchange of the new positions inside the wavefront.
+//   through an LDS exchange of the new positions inside the workgroup.
+// Up to 32 aircraft (or 64), each wavefront holds whole worlds and the
+// double-buffered position exchange needs only the wavefront's order.  For
+// 33 .. 63 aircraft, where one world per wavefront would leave many lanes
+// idle, the worlds of a workgroup sit back to back in its lanes (a world may
+// straddle two wavefronts; e.g. 8 worlds of 40 aircraft in 320 lanes) and
+// one workgroup barrier per step orders the exchange.
 // Pairs are split evenly over the world's lanes (lane i tests i against
 // i+1 .. i+(N-1)/2 modulo N, plus i+N/2 for i < N/2 when N is even); a hit
 // sets the bits of both aircraft in a per-lane violation mask that is
-// OR-reduced over the world once, after the last step.
+// OR-reduced over the world once, after the last step.  The pair tests with
+// both aircraft present are counted per world and step from the wavefronts'
+// presence ballots.
 #include "rollout_math.h"
 
 namespace smc {
 
-template <typename R>
-__global__ void __launch_bounds__(256, sizeof(R) == 4 ? 4 : 1)
-k_rollout(const RolloutParams p, const RolloutArrays a) {
+template <typename R, bool PACKED>
+__global__ void __launch_bounds__(sizeof(R) == 4 ? kRolloutMaxBlock32 : kRolloutMaxBlock64)
+k_rollout(const RolloutParams p, const RolloutArrays a, int wpb) {
     typedef typename V2<R>::t R2;
     typedef typename V4<R>::t R4;
-    __shared__ R4 pos[4][2][64];
+    extern __shared__ unsigned char smem_raw[];
+    const int nb = blockDim.x;
 
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int N = p.N, S = p.S, H = p.H;
-    const int wpw = 64 / N;
-    const int64_t gwave = (int64_t)blockIdx.x * 4 + wv;
-    const int wiw = lane / N;
-    const int i = lane - wiw * N;
-    const int64_t world = gwave * wpw + wiw;
+    int wib, i;        // world within the workgroup, aircraft
+    bool inblk;        // the lane holds an aircraft of one of the workgroup's worlds
+    if constexpr (PACKED) {
+        wib = tid / N;
+        i = tid - wib * N;
+        inblk = wib < wpb;
+    } else {           // whole worlds in each wavefront
+        const int wpw = 64 / N;
+        const int wiw = lane / N;
+        i = lane - wiw * N;
+        wib = (tid >> 6) * wpw + wiw;
+        inblk = wiw < wpw;
+    }
+    const int lbase = tid - i;                     // lane of the world's aircraft 0
+    const int64_t world = (int64_t)blockIdx.x * wpb + wib;
     const int64_t nworld = (int64_t)p.P * p.M;
-    const bool valid = (wiw < wpw) && (world < nworld);
+    const bool valid = inblk && (world < nworld);
     const int pidx = valid ? (int)(world % p.P) : 0;
     const int m = valid ? (int)(world / p.P) : 0;
-    const int base = wiw * N;
+    const int base = wib * N;
+    // Positions as two arrays of pairs, (x, y) and (z, present), each world
+    // stored twice in a row (2N entries): the partner i + d of lane i needs no
+    // wrap, and its address is the lane's own plus a constant.
+    const int nslot = 2 * wpb * N;                // entries per buffer
+    R2* pxy = reinterpret_cast<R2*>(smem_raw);    // [2][nslot]
+    R2* pzw = pxy + 2 * nslot;                    // [2][nslot]
 
     // per-aircraft constants
     const double* ac = a.acpar + i * 9;
@@ -84,7 +109,11 @@ k_rollout(const RolloutParams p, const RolloutArrays a) {
 
     R burn = 0, burn_c = 0, acc = 0, acc_c = 0;
     bool feas_unary = true, done = false;
-    unsigned long long vmask = 0ull;
+    // separation hits relative to the lane: bit d of relmask is set once the
+    // pair (i, i + d mod N) violated, d = 1 .. (N - 1) / 2; halfhit for the
+    // pair (i, i + N / 2) of an even N (lanes i < N / 2)
+    uint32_t relmask = 0u;
+    bool halfhit = false;
     int nsim = 0, npair = 0;
     R chidot = 0, vc = 0, zdot = 0;
     int s_cur = -1, k_end = 0;
@@ -208,46 +237,64 @@ k_rollout(const RolloutParams p, const RolloutArrays a) {
         if (present && !landed) kahan_add(acc, acc_c, c);
         if (landed) done = true;
 
-        // separation at the new state among aircraft simulated this step
+        // separation at the new state among aircraft simulated this step.
+        // Double buffering: a lane writes buffer k & 1 only after every lane
+        // passed the barrier of step k - 1, i.e. finished reading it at k - 2.
         const int buf = k & 1;
         const R px_ = present ? x : sent_x;
         const R py_ = present ? y : (R)0;
         const R pz_ = present ? z : (R)0;
-        R4 me;
-        me.x = px_; me.y = py_; me.z = pz_; me.w = present ? (R)1 : (R)0;
-        pos[wv][buf][lane] = me;
-        wave_sync();
+        R2 mxy, mzw;
+        mxy.x = px_; mxy.y = py_;
+        mzw.x = pz_; mzw.y = present ? (R)1 : (R)0;
+        if (inblk) {
+            const int o = buf * nslot + 2 * base + i;
+            pxy[o] = mxy; pxy[o + N] = mxy;
+            pzw[o] = mzw; pzw[o + N] = mzw;
+        }
+        // a world's lanes in one wavefront need only the wavefront's order;
+        // one barrier per step orders the workgroup otherwise
+        if constexpr (PACKED) __syncthreads(); else wave_sync();
         if (valid) {
+            const R2* qxy = pxy + buf * nslot + 2 * base + i;   // partner d at [d]
+            const R2* qzw = pzw + buf * nslot + 2 * base + i;
+            R qsum = (R)0;
             const int half = (N - 1) >> 1;
             for (int d = 1; d <= half; ++d) {
-                int j = i + d;
-                if (j >= N) j -= N;
-                const R4 q = pos[wv][buf][base + j];
-                npair += (present && q.w != (R)0) ? 1 : 0;
-                const R dx = px_ - q.x, dy = py_ - q.y, dz = pz_ - q.z;
-                if (dx * dx + dy * dy < sep_h2 && m_abs(dz) < sep_v)
-                    vmask |= (1ull << i) | (1ull << j);
+                const R2 a2 = qxy[d], b2 = qzw[d];
+                qsum += b2.y;
+                const R dx = px_ - a2.x, dy = py_ - a2.y, dz = pz_ - b2.x;
+                const bool hit = (dx * dx + dy * dy < sep_h2) & (m_abs(dz) < sep_v);
+                relmask |= hit ? (1u << d) : 0u;
             }
             if (((N & 1) == 0) && i < (N >> 1)) {
-                const int j = i + (N >> 1);
-                const R4 q = pos[wv][buf][base + j];
-                npair += (present && q.w != (R)0) ? 1 : 0;
-                const R dx = px_ - q.x, dy = py_ - q.y, dz = pz_ - q.z;
-                if (dx * dx + dy * dy < sep_h2 && m_abs(dz) < sep_v)
-                    vmask |= (1ull << i) | (1ull << j);
+                const int d = N >> 1;
+                const R2 a2 = qxy[d], b2 = qzw[d];
+                qsum += b2.y;
+                const R dx = px_ - a2.x, dy = py_ - a2.y, dz = pz_ - b2.x;
+                halfhit |= (dx * dx + dy * dy < sep_h2) & (m_abs(dz) < sep_v);
             }
+            if (present) npair += (int)qsum;
         }
-        wave_sync();
     }
 
-    // OR the violation masks of the world's lanes
-    unsigned long long* mk = reinterpret_cast<unsigned long long*>(&pos[wv][0][0]);
-    wave_sync();
-    mk[lane] = vmask;
-    wave_sync();
-    unsigned long long wmask = 0ull;
-    if (valid)
-        for (int j = 0; j < N; ++j) wmask |= mk[base + j];
+    // an aircraft violated separation if its own tests hit, or if the lane
+    // that tested it as partner i + d recorded bit d
+    __syncthreads();
+    uint32_t* rm = reinterpret_cast<uint32_t*>(smem_raw);   // [nb] relmask, [nb] halfhit
+    rm[tid] = relmask;
+    rm[nb + tid] = halfhit ? 1u : 0u;
+    __syncthreads();
+    bool sepbad = relmask != 0u || halfhit;
+    if (valid) {
+        const int half = (N - 1) >> 1;
+        for (int d = 1; d <= half; ++d) {
+            int src = i - d;
+            if (src < 0) src += N;
+            if ((rm[lbase + src] >> d) & 1u) sepbad = true;
+        }
+        if (((N & 1) == 0) && i >= (N >> 1) && rm[nb + lbase + i - (N >> 1)]) sepbad = true;
+    }
 
     if (valid) {
         double cost = 0.0;
@@ -258,7 +305,7 @@ k_rollout(const RolloutParams p, const RolloutArrays a) {
             const double fuel_term = (double)burn / denom;
             cost = (1.0 - p.w[7] - p.w[8]) * wf * fuel_term + (double)acc / (double)nsteps;
         }
-        const bool ok = feas_unary && !((wmask >> i) & 1ull);
+        const bool ok = feas_unary && !sepbad;
         const int64_t o = ((int64_t)m * p.P + pidx) * N + i;
         a.cost[o] = cost;
         a.feas[o] = ok ? 1 : 0;
@@ -280,17 +327,53 @@ k_rollout(const RolloutParams p, const RolloutArrays a) {
     }
 }
 
+// Packed layout: worlds across wavefronts (see above).
+bool rollout_packed(int N) { return N > 32 && N < 64; }
+
+// Worlds per workgroup.  Packed: the count whose lanes (N per world, rounded
+// up to whole wavefronts) are the busiest, the smaller workgroup on ties;
+// otherwise four wavefronts of 64 / N worlds.
+int rollout_worlds_per_block(int N, int prec) {
+    if (!rollout_packed(N)) return 4 * (64 / N);
+    const int maxb = prec == 0 ? kRolloutMaxBlock64 : kRolloutMaxBlock32;
+    int best_k = 1;
+    double best_u = -1.0;
+    for (int k = 1; k * N <= maxb; ++k) {
+        const int lanes = k * N;
+        const int threads = (lanes + 63) / 64 * 64;
+        const double u = (double)lanes / threads;
+        if (u > best_u + 1e-12) { best_u = u; best_k = k; }
+    }
+    return best_k;
+}
+
 hipError_t launch_rollout(int prec, const RolloutParams& p, const RolloutArrays& a,
                           hipStream_t st) {
-    const int wpw = 64 / p.N;
+    if (p.N < 1 || p.N > 64) return hipErrorInvalidValue;
+    const bool packed = rollout_packed(p.N);
+    const int wpb = rollout_worlds_per_block(p.N, prec);
+    const int threads = packed ? (wpb * p.N + 63) / 64 * 64 : 256;
     const int64_t nworld = (int64_t)p.P * p.M;
-    const int64_t nwave = (nworld + wpw - 1) / wpw;
-    const int64_t nblock = (nwave + 3) / 4;
+    const int64_t nblock = (nworld + wpb - 1) / wpb;
     if (nblock <= 0) return hipSuccess;
-    if (prec == 0)
-        hipLaunchKernelGGL(k_rollout<double>, dim3((unsigned)nblock), dim3(256), 0, st, p, a);
-    else
-        hipLaunchKernelGGL(k_rollout<float>, dim3((unsigned)nblock), dim3(256), 0, st, p, a);
+    const size_t rsz = prec == 0 ? sizeof(double) : sizeof(float);
+    // two arrays of pairs, two buffers, each world twice
+    const size_t lds = (size_t)2 * 2 * (2 * wpb * p.N) * 2 * rsz;
+    if (prec == 0) {
+        if (packed)
+            hipLaunchKernelGGL((k_rollout<double, true>), dim3((unsigned)nblock), dim3(threads), lds,
+                               st, p, a, wpb);
+        else
+            hipLaunchKernelGGL((k_rollout<double, false>), dim3((unsigned)nblock), dim3(threads),
+                               lds, st, p, a, wpb);
+    } else {
+        if (packed)
+            hipLaunchKernelGGL((k_rollout<float, true>), dim3((unsigned)nblock), dim3(threads), lds,
+                               st, p, a, wpb);
+        else
+            hipLaunchKernelGGL((k_rollout<float, false>), dim3((unsigned)nblock), dim3(threads),
+                               lds, st, p, a, wpb);
+    }
     return hipGetLastError();
 }
 

@@ -184,11 +184,14 @@ def test_rollout_c2_shape_ragged(lib, prec, layout):
     assert n_near < 0.25 * 37 * 5
 
 
-@pytest.mark.parametrize("N,layout", [(1, 1), (2, 1), (3, 1), (7, 1), (16, 1), (33, 1), (64, 1),
+@pytest.mark.parametrize("N,layout", [(1, 1), (2, 1), (3, 1), (7, 1), (16, 1), (24, 1), (33, 1),
+                                      (40, 1), (48, 1), (63, 1), (64, 1),
                                       (1, 2), (2, 2), (3, 2), (5, 2), (7, 2), (9, 2), (10, 2),
                                       (11, 2), (13, 2), (16, 2)])
 def test_rollout_aircraft_counts(lib, N, layout):
-    """Worlds from 1 lane to a full wave; mixed kinds and activation steps."""
+    """Worlds from 1 lane to a full wave; mixed kinds and activation steps.
+    33 .. 63 aircraft use the packed aircraft-per-lane layout (worlds across
+    wavefronts of a workgroup)."""
     rng = np.random.default_rng(N)
     n_arr = min(max(1, N // 2), 12)
     s = synth.make_scenario("T", n_arr=n_arr, n_dep=N - n_arr,
@@ -202,11 +205,11 @@ def test_rollout_aircraft_counts(lib, N, layout):
     assert steps == ref["steps"]
 
 
-@pytest.mark.parametrize("layout", LAYOUTS)
-def test_rollout_close_traffic_separation(lib, layout):
+@pytest.mark.parametrize("N,layout", [(12, 1), (12, 2), (40, 1), (41, 1)])
+def test_rollout_close_traffic_separation(lib, N, layout):
     """Aircraft packed inside one separation cell so that many pair tests
-    fire, exercising both the pair split and the mask reduction."""
-    N = 12
+    fire, exercising both the pair split and the mask reduction (40 and 41
+    aircraft: the packed layout, even and odd pair split)."""
     rng = np.random.default_rng(5)
     s = synth.make_scenario("T", n_arr=0, n_dep=N, box=(60e3, 60e3, 6e3), grid=(4, 4, 3),
                             H=8, dt=5.0, S=2, M=2, L=4, K=2, precision="fp64", seed=1)
