@@ -72,11 +72,11 @@ def _src_hash(*names):
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel_src: tuple, workload: str):
+def traffic_for(kernel_src: tuple, workload: str, kind: str = "rollout"):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, or
     None when absent, taken on another workload or on a different kernel
     source."""
-    path = os.path.join(ROOT, "profiles", f"rollout_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kind}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -397,6 +397,8 @@ def main():
         gach = gflops / (ms_grad * 1e-3) / 1e12
         grad_roof = {"kernel": "k_rollout_grad", "bound": "alu", "achieved": round(gach, 3),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(gach / peak, 4),
+                     "traffic": traffic_for(("kernels_grad.hip", "rollout_math.h"), args.workload,
+                                            "adjoint"),
                      "ms_per_launch": round(ms_grad, 4), "lane_steps_per_launch": int(ls_launch),
                      "flops_per_launch": gflops,
                      "ms_per_mpc_step_in_adjoint": round(ms_grad * info0["grad_launches"], 2)}
