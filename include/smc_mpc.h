@@ -183,6 +183,32 @@ smc_status smc_eval_cost(smc_ctx* ctx, int64_t mpc_step, int32_t iter,
                          const double* particles, int32_t P,
                          double* cost_out, uint8_t* feasible_out);
 
+/* The plant of the receding-horizon loop (Sec. "Model Predictive Control":
+ * only the first part of the returned control sequence is applied, and the
+ * plant's disturbance differs from the optimiser's predictions; Sec.
+ * "Rolling Window": aircraft join at a pre-determined step and leave the
+ * problem when they finish).  Every aircraft that has joined flies the first
+ * n_steps steps of the plan `controls` [N x S x 3] (physical units, as
+ * returned by smc_mpc_step for `horizon`; segment s(k) = floor(k S /
+ * horizon)) from `states` with the rollout's arithmetic (the context's
+ * precision), through one wind field: sample 0 of the fields of iteration
+ * word `plant_iter` of update `mpc_step` (an iteration word >= n_iters is
+ * never drawn by the optimiser), with mean wind_mean.  An arrival stops when
+ * it meets the landing sector.
+ *  states_out[N x 6]: states after the steps (an aircraft that has not
+ *     joined keeps its state; a landed one its landing state).
+ *  k_active_out[N]: activation steps for the next update: k_active -
+ *     n_steps, at least 0, or -1 for an aircraft that was inactive, landed,
+ *     or is a departure outside its exit radius D_TMA after the steps.
+ *  event_out[N]: 1 landed, 2 left through the exit radius, 0 otherwise.
+ * n_steps in [1, horizon], plant_iter >= 0.  Host pointers, synchronous.
+ * Errors: SMC_EINVAL (nothing written), SMC_EDEVICE. */
+smc_status smc_plant_step(smc_ctx* ctx, int64_t mpc_step, int32_t plant_iter,
+                          const double* states, const int32_t* k_active,
+                          const double* wind_mean, const double* controls,
+                          int32_t horizon, int32_t n_steps, double* states_out,
+                          int32_t* k_active_out, int32_t* event_out);
+
 /* Message of the last failing call on ctx (or of the last failing init when
  * ctx is NULL).  Owned by the library, valid until the next call. */
 const char* smc_last_error(const smc_ctx* ctx);

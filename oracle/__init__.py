@@ -10,8 +10,10 @@ Modules:
   wind     -- grid, Kronecker Cholesky factor, field samples, trilinear lookup
   rollout  -- dynamics, constraints, landing, cost terms, pairwise separation
   smc      -- Alg. 1: initialisation, weights, resampling, moves, selection
+  grad     -- FP64 autograd transcription of the fuel + time cost (Langevin move)
+  mpc      -- receding-horizon loop: plant step, rolling window
 
 Each function cites the passage of the paper it follows.  Functions without an
 independent pin say "parity unpinned" in their docstring.
 """
-from . import philox, wind, rollout, smc  # noqa: F401
+from . import philox, wind, rollout, smc, mpc  # noqa: F401

@@ -124,6 +124,8 @@ _SIGS = {
                                    C.POINTER(StepInfo), _VP]),
     "smc_eval_cost": (C.c_int, [_VP, C.c_int64, C.c_int32, _VP, _VP, _VP, C.c_int32, _VP,
                                 C.c_int32, _VP, _VP]),
+    "smc_plant_step": (C.c_int, [_VP, C.c_int64, C.c_int32, _VP, _VP, _VP, _VP, C.c_int32,
+                                 C.c_int32, _VP, _VP, _VP]),
     "smc_k_philox": (C.c_int, [C.c_uint64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                C.c_int64, C.c_int64, _VP, _VP]),
     "smc_k_init_particles": (C.c_int, [_VP, C.c_int64, C.c_int32, _VP, _VP]),
@@ -357,6 +359,57 @@ def smc_eval_cost(ctx: Context, particles, iter_, mpc_step=None, states=None, k_
                             feas.ctypes.data_as(C.c_void_p))
     _check(r, ctx)
     return cost, feas.astype(bool)
+
+
+def smc_plant_step(ctx: Context, controls, plant_iter, n_steps=None, mpc_step=None, states=None,
+                   k_active=None, wind_mean=None, horizon=None):
+    """Host form: returns (states [N,6], k_active [N], event [N]) after the
+    plant flew n_steps (default: the first control segment) of the plan."""
+    s = ctx.scen
+    mpc_step = s["mpc_step"] if mpc_step is None else mpc_step
+    states = s["states"] if states is None else states
+    k_active = s["k_active"] if k_active is None else k_active
+    wind_mean = s["wind_mean"] if wind_mean is None else wind_mean
+    horizon = ctx.H if horizon is None else horizon
+    n_steps = -(-int(horizon) // ctx.S) if n_steps is None else n_steps
+    st_a, p_st = _hp(states, np.float64)
+    ka_a, p_ka = _hp(k_active, np.int32)
+    wm_a, p_wm = _hp(wind_mean, np.float64)
+    c_a, p_c = _hp(controls, np.float64)
+    st_out = np.zeros((ctx.N, 6))
+    ka_out = np.zeros(ctx.N, dtype=np.int32)
+    ev = np.zeros(ctx.N, dtype=np.int32)
+    r = lib().smc_plant_step(ctx.handle, int(mpc_step), int(plant_iter), p_st, p_ka, p_wm, p_c,
+                             int(horizon), int(n_steps), st_out.ctypes.data_as(C.c_void_p),
+                             ka_out.ctypes.data_as(C.c_void_p), ev.ctypes.data_as(C.c_void_p))
+    _check(r, ctx)
+    return st_out, ka_out, ev
+
+
+def rolling_window(ctx: Context, n_updates, plant_iter=None, states=None, k_active=None,
+                   mpc_step0=None, wind_mean=None):
+    """Receding-horizon loop (Sec. "Model Predictive Control", "Rolling
+    Window"): n_updates times solve one MPC update from the current states,
+    let the plant fly the first control segment (smc_plant_step, disturbance
+    from iteration word plant_iter, default n_iters + 1), move the window.
+    Returns one dict per update (controls, cost, states and k_active after the
+    plant step, events, info)."""
+    s = ctx.scen
+    plant_iter = int(s["K"]) + 1 if plant_iter is None else plant_iter
+    states = np.array(s["states"] if states is None else states, dtype=np.float64)
+    k_active = np.array(s["k_active"] if k_active is None else k_active, dtype=np.int32)
+    step0 = int(s["mpc_step"]) if mpc_step0 is None else int(mpc_step0)
+    out = []
+    for t in range(n_updates):
+        step = step0 + t
+        ctrl, cost, status, info = smc_mpc_step(ctx, mpc_step=step, states=states,
+                                                k_active=k_active, wind_mean=wind_mean)
+        states, k_active, ev = smc_plant_step(ctx, ctrl, plant_iter, mpc_step=step,
+                                              states=states, k_active=k_active,
+                                              wind_mean=wind_mean)
+        out.append(dict(controls=ctrl, cost=cost, status=status, states=states.copy(),
+                        k_active=k_active.copy(), event=ev, info=info))
+    return out
 
 
 # ---- kernel-level entry points (device tensors) -----------------------------

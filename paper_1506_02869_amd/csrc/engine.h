@@ -144,6 +144,12 @@ hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u,
                                const double* states, const int32_t* k_active, const double* acpar,
                                const double* targets, const int8_t* kind, void* Wt, double* partial,
                                double* grad_out, hipStream_t st);
+// The receding-horizon plant: one lane per aircraft (N <= 64), one wind field.
+hipError_t launch_plant(int prec, const RolloutParams& p, const double* ctrl, const void* W,
+                        const double* states, const int32_t* k_active, const double* acpar,
+                        const double* targets, const int8_t* kind, int n_steps,
+                        double* states_out, int32_t* k_active_out, int32_t* event_out,
+                        hipStream_t st);
 hipError_t launch_mala_propose(int prec, int64_t count, const void* u, const double* gsum,
                                double coef, double eps, Stream s, void* up, hipStream_t st);
 hipError_t launch_mala_decide(int prec, int P, int N, int D, const void* u, const void* up,

@@ -32,7 +32,6 @@ template <typename R, bool PACKED>
 __global__ void __launch_bounds__(sizeof(R) == 4 ? kRolloutMaxBlock32 : kRolloutMaxBlock64)
 k_rollout(const RolloutParams p, const RolloutArrays a, int wpb) {
     typedef typename V2<R>::t R2;
-    typedef typename V4<R>::t R4;
     extern __shared__ unsigned char smem_raw[];
     const int nb = blockDim.x;
 

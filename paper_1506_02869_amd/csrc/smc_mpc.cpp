@@ -71,6 +71,8 @@ struct smc_ctx {
     int32_t* d_status = nullptr;
     unsigned long long* d_steps = nullptr;
     double *d_states = nullptr, *d_ctrl_out = nullptr, *d_cost_out = nullptr;
+    double* d_plant_states = nullptr;   // plant step: states after the steps
+    int32_t* d_plant_i32 = nullptr;     // plant step: activation steps, events
     int32_t* d_kact = nullptr;
     int64_t eval_cap = 0;  // particles the eval buffers hold
     void* d_ueval = nullptr;
@@ -654,6 +656,7 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         (st = dalloc_t(c, &c->d_status, 1)) || (st = dalloc_t(c, &c->d_steps, 2 * kStepSlots)) ||
         (st = dalloc_t(c, &c->d_states, N * 6)) || (st = dalloc_t(c, &c->d_kact, N)) ||
         (st = dalloc_t(c, &c->d_ctrl_out, N * D)) || (st = dalloc_t(c, &c->d_cost_out, 1 + N)) ||
+        (st = dalloc_t(c, &c->d_plant_states, N * 6)) || (st = dalloc_t(c, &c->d_plant_i32, 2 * N)) ||
         (st = dalloc_t(c, &d_Lx, (size_t)c->nx * c->nx)) || (st = dalloc_t(c, &d_Ly, (size_t)c->ny * c->ny)) ||
         (st = dalloc_t(c, &d_Lz, (size_t)c->nz * c->nz)))
         return bail(st);
@@ -734,6 +737,40 @@ smc_status smc_mpc_step(smc_ctx* c, int64_t mpc_step, const double* states,
                              hipMemcpyDeviceToHost, st));
     HIP_OK(c, hipStreamSynchronize(st));
     return r;
+}
+
+smc_status smc_plant_step(smc_ctx* c, int64_t mpc_step, int32_t plant_iter, const double* states,
+                          const int32_t* k_active, const double* wind_mean, const double* controls,
+                          int32_t horizon, int32_t n_steps, double* states_out,
+                          int32_t* k_active_out, int32_t* event_out) {
+    if (!c) return fail(nullptr, SMC_EINVAL, "ctx is NULL");
+    if (!states || !k_active || !wind_mean || !controls || !states_out || !k_active_out || !event_out)
+        return fail(c, SMC_EINVAL, "NULL argument");
+    smc_status vs = check_horizon(c, horizon);
+    if (vs) return vs;
+    if (n_steps < 1 || n_steps > horizon) return fail(c, SMC_EINVAL, "n_steps must be in [1, horizon]");
+    if (plant_iter < 0) return fail(c, SMC_EINVAL, "plant_iter must be >= 0");
+    hipStream_t st = c->stream;
+    const int N = c->N;
+    HIP_OK(c, hipMemcpyAsync(c->d_states, states, sizeof(double) * N * 6, hipMemcpyHostToDevice, st));
+    HIP_OK(c, hipMemcpyAsync(c->d_kact, k_active, sizeof(int32_t) * N, hipMemcpyHostToDevice, st));
+    HIP_OK(c, hipMemcpyAsync(c->d_ctrl_out, controls, sizeof(double) * N * c->S * 3,
+                             hipMemcpyHostToDevice, st));
+    HIP_OK(c, launch_wind_normals(c->prec, make_stream(c->seed, mpc_step, plant_iter, P_WIND, c->scen_id),
+                                  c->G, c->M, c->d_Z, st));
+    HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G, c->M,
+                               c->d_W, st));
+    RolloutParams rp = c->rp;
+    rp.H = horizon;
+    HIP_OK(c, launch_plant(c->prec, rp, c->d_ctrl_out, c->d_W, c->d_states, c->d_kact, c->d_acpar,
+                           c->d_targets, c->d_kind, n_steps, c->d_plant_states, c->d_plant_i32,
+                           c->d_plant_i32 + N, st));
+    HIP_OK(c, hipMemcpyAsync(states_out, c->d_plant_states, sizeof(double) * N * 6,
+                             hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipMemcpyAsync(k_active_out, c->d_plant_i32, sizeof(int32_t) * N, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipMemcpyAsync(event_out, c->d_plant_i32 + N, sizeof(int32_t) * N, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipStreamSynchronize(st));
+    return SMC_OK;
 }
 
 smc_status smc_eval_cost(smc_ctx* c, int64_t mpc_step, int32_t iter, const double* states,
