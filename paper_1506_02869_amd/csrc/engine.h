@@ -122,8 +122,14 @@ hipError_t launch_wind_normals(int prec, Stream s, int G, int M, void* Z,
 hipError_t launch_kron_expand(int prec, const double* Lx, const double* Ly,
                               const double* Lz, int nx, int ny, int nz,
                               double sigma, void* Lfac, hipStream_t st);
+// Wind GEMM.  When few output tiles would leave the chip idle (fewer than
+// kWindGemmSplitBelow workgroups of whole row blocks), each K chunk runs in
+// its own workgroup and `part` (wind_gemm_part_elems(G, M) reals, else
+// unused) holds the chunk products.
+constexpr int kWindGemmSplitBelow = 1024;
+size_t wind_gemm_part_elems(int G, int M);
 hipError_t launch_wind_gemm(int prec, const void* Lfac, const void* Z,
-                            double wm0, double wm1, int G, int M, void* W,
+                            double wm0, double wm1, int G, int M, void* W, void* part,
                             hipStream_t st);
 hipError_t launch_rollout(int prec, const RolloutParams& p,
                           const RolloutArrays& a, hipStream_t st);
@@ -182,7 +188,7 @@ hipError_t launch_select(int P, int N, const double* logw, const double* chat,
                          double beta, int32_t* best, hipStream_t st);
 hipError_t launch_wind_gemm_grouped(int prec, const void* Lfac, const void* Z,
                                     const double* wmean, int mper, int G, int M, void* W,
-                                    hipStream_t st);
+                                    void* part, hipStream_t st);
 
 // batched launches: grids span every scenario of the table (ns entries)
 hipError_t launch_b_fill(uint32_t* p, int64_t n, hipStream_t st);

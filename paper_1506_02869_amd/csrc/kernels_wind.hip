@@ -43,8 +43,7 @@ template <> struct Mfma<double> {
 
 // Block tile 32 (grid points) x 64 (columns), K stage 32; 4 waves as 2 x 2,
 // each wave 16 x 32 = two 16x16 MFMA tiles.  The factor is lower triangular,
-// so row block rb only needs k < (rb + 1) * 32; each workgroup takes row
-// blocks R - 1 - rb and rb so that all workgroups do the same work.
+// so row block rb only needs k < (rb + 1) * 32.
 // Stages are double-buffered in LDS with the next stage's global loads in
 // flight in registers while the current one feeds the MFMAs (one barrier per
 // stage).  LDS tiles are k-major: As[k][row], Bs[k][col], so the fragment
@@ -119,32 +118,29 @@ __device__ __forceinline__ void gemm_store(const GemmStage<T>& st, T* As, T* Bs)
     }
 }
 
+// Product of the tile's rows with the K range [kbeg, kend) (whole stages),
+// accumulated from zero: acc0 / acc1 hold the wave's two 16 x 16 tiles.
 template <typename T>
-__device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* __restrict__ Z,
-                                              int G, int NC, int rb, int cb, double wm0,
-                                              double wm1, const double* __restrict__ wmean,
-                                              int mper, T* __restrict__ W, T* As, T* Bs) {
-    typedef typename Mfma<T>::acc_t acc_t;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
+__device__ __forceinline__ void gemm_range(const T* __restrict__ A, const T* __restrict__ Z,
+                                           int G, int NC, int row0, int col0, int kbeg, int kend,
+                                           T* As, T* Bs, typename Mfma<T>::acc_t& acc0,
+                                           typename Mfma<T>::acc_t& acc1) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * 16;         // wave row offset in tile
     const int wc = (wave & 1) * 32;          // wave col offset in tile
-    const int row0 = rb * GB_M;
-    const int col0 = cb * GB_N;
-    const int kmax = min(G, row0 + GB_M);
-    const int nst = (kmax + GB_K - 1) / GB_K;
-    acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-
+    const int nst = (kend - kbeg + GB_K - 1) / GB_K;
+    acc0 = {0, 0, 0, 0};
+    acc1 = {0, 0, 0, 0};
     GemmStage<T> st;
-    gemm_fetch<T>(A, Z, G, NC, row0, col0, 0, st);
+    gemm_fetch<T>(A, Z, G, NC, row0, col0, kbeg, st);
     gemm_store<T>(st, As, Bs);
     __syncthreads();
     for (int s = 0; s < nst; ++s) {
         const int cur = s & 1;
         const T* Ac = As + cur * (GB_K * GA_LD);
         const T* Bc = Bs + cur * (GB_K * GBB_LD);
-        if (s + 1 < nst) gemm_fetch<T>(A, Z, G, NC, row0, col0, (s + 1) * GB_K, st);
+        if (s + 1 < nst) gemm_fetch<T>(A, Z, G, NC, row0, col0, kbeg + (s + 1) * GB_K, st);
 #pragma unroll
         for (int kk = 0; kk < GB_K; kk += 4) {
             const int kr = kk + (lane >> 4);
@@ -158,27 +154,63 @@ __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* 
                                        Bs + (cur ^ 1) * (GB_K * GBB_LD));
         __syncthreads();
     }
-    // epilogue: element (g, col) -> W[m][g][c] with col = 2 m + c; the mean
-    // is (wm0, wm1), or wmean[2 (m / mper) + c] per group of mper samples
+}
+
+// W element (g, col) with col = 2 m + c: the mean (wm0, wm1), or
+// wmean[2 (m / mper) + c] per group of mper samples, plus the product.
+template <typename T>
+__device__ __forceinline__ void gemm_put(int G, int g, int col, double wm0, double wm1,
+                                         const double* __restrict__ wmean, int mper, T v,
+                                         T* __restrict__ W) {
+    const int m = col >> 1, c = col & 1;
+    const double base = wmean ? wmean[2 * (m / mper) + c] : (c ? wm1 : wm0);
+    W[((int64_t)m * G + g) * 2 + c] = (T)(base + (double)v);
+}
+
+// The K extent of row block rb is split into chunks of GK_CHUNK (the factor
+// is lower triangular: k < (rb + 1) 32), each accumulated from zero; the
+// chunk products are summed in chunk order.  Both launch forms below do
+// exactly these additions, so a field does not depend on how many columns
+// share the launch.
+constexpr int GK_CHUNK = 1024;
+
+__host__ __device__ inline int gemm_kmax(int G, int rb) { return min(G, (rb + 1) * GB_M); }
+__host__ __device__ inline int gemm_nchunks(int G, int rb) {
+    return (gemm_kmax(G, rb) + GK_CHUNK - 1) / GK_CHUNK;
+}
+
+// One row block: all its chunks in turn, the sum and the epilogue.
+template <typename T>
+__device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* __restrict__ Z,
+                                              int G, int NC, int rb, int cb, double wm0,
+                                              double wm1, const double* __restrict__ wmean,
+                                              int mper, T* __restrict__ W, T* As, T* Bs) {
+    typedef typename Mfma<T>::acc_t acc_t;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 16, wc = (wave & 1) * 32;
+    const int row0 = rb * GB_M, col0 = cb * GB_N;
+    const int kmax = gemm_kmax(G, rb);
+    acc_t tot0 = {0, 0, 0, 0}, tot1 = {0, 0, 0, 0};
+    for (int j = 0; j * GK_CHUNK < kmax; ++j) {
+        acc_t a0, a1;
+        gemm_range<T>(A, Z, G, NC, row0, col0, j * GK_CHUNK, min(kmax, (j + 1) * GK_CHUNK), As,
+                      Bs, a0, a1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { tot0[r] += a0[r]; tot1[r] += a1[r]; }
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int g = row0 + wr + Mfma<T>::row(lane, r);
         if (g >= G) continue;
-        const int c0 = col0 + wc + (lane & 15);
-        const int c1 = c0 + 16;
-        if (c0 < NC) {
-            const int m = c0 >> 1, c = c0 & 1;
-            const double base = wmean ? wmean[2 * (m / mper) + c] : (c ? wm1 : wm0);
-            W[((int64_t)m * G + g) * 2 + c] = (T)(base + (double)acc0[r]);
-        }
-        if (c1 < NC) {
-            const int m = c1 >> 1, c = c1 & 1;
-            const double base = wmean ? wmean[2 * (m / mper) + c] : (c ? wm1 : wm0);
-            W[((int64_t)m * G + g) * 2 + c] = (T)(base + (double)acc1[r]);
-        }
+        const int c0 = col0 + wc + (lane & 15), c1 = c0 + 16;
+        if (c0 < NC) gemm_put<T>(G, g, c0, wm0, wm1, wmean, mper, tot0[r], W);
+        if (c1 < NC) gemm_put<T>(G, g, c1, wm0, wm1, wmean, mper, tot1[r], W);
     }
 }
 
+// Whole row blocks per workgroup (enough tiles to fill the chip): row blocks
+// R - 1 - rb and rb, so that all workgroups do the same work.
 template <typename T>
 __global__ void __launch_bounds__(256) k_wind_gemm(const T* __restrict__ A,
                                                    const T* __restrict__ Z, int G, int NC,
@@ -198,6 +230,52 @@ __global__ void __launch_bounds__(256) k_wind_gemm(const T* __restrict__ A,
     }
 }
 
+// One (row block, column block, chunk) per workgroup (few tiles: the chunks
+// give the chip enough workgroups); the chunk product goes to
+// part[chunk][g][col].  Workgroups past a row block's last chunk exit.
+template <typename T>
+__global__ void __launch_bounds__(256) k_wind_gemm_part(const T* __restrict__ A,
+                                                        const T* __restrict__ Z, int G, int NC,
+                                                        T* __restrict__ part) {
+    __shared__ T As[2 * GB_K * GA_LD];
+    __shared__ T Bs[2 * GB_K * GBB_LD];
+    typedef typename Mfma<T>::acc_t acc_t;
+    const int rb = blockIdx.x, cb = blockIdx.y, j = blockIdx.z;
+    if (j >= gemm_nchunks(G, rb)) return;       // uniform over the workgroup
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 16, wc = (wave & 1) * 32;
+    const int row0 = rb * GB_M, col0 = cb * GB_N;
+    const int kmax = gemm_kmax(G, rb);
+    acc_t a0, a1;
+    gemm_range<T>(A, Z, G, NC, row0, col0, j * GK_CHUNK, min(kmax, (j + 1) * GK_CHUNK), As, Bs,
+                  a0, a1);
+    T* pj = part + (int64_t)j * G * NC;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int g = row0 + wr + Mfma<T>::row(lane, r);
+        if (g >= G) continue;
+        const int c0 = col0 + wc + (lane & 15), c1 = c0 + 16;
+        if (c0 < NC) pj[(int64_t)g * NC + c0] = a0[r];
+        if (c1 < NC) pj[(int64_t)g * NC + c1] = a1[r];
+    }
+}
+
+// Sum of a row's chunk products in chunk order, then the epilogue.
+template <typename T>
+__global__ void __launch_bounds__(256) k_wind_gemm_sum(const T* __restrict__ part, int G, int NC,
+                                                       double wm0, double wm1,
+                                                       const double* __restrict__ wmean,
+                                                       int mper, T* __restrict__ W) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)G * NC) return;
+    const int g = (int)(e / NC), col = (int)(e % NC);
+    const int nch = gemm_nchunks(G, g / GB_M);
+    T tot = 0;
+    for (int j = 0; j < nch; ++j) tot += part[(int64_t)j * G * NC + e];
+    gemm_put<T>(G, g, col, wm0, wm1, wmean, mper, tot, W);
+}
+
 hipError_t launch_kron_expand(int prec, const double* Lx, const double* Ly,
                               const double* Lz, int nx, int ny, int nz,
                               double sigma, void* Lfac, hipStream_t st) {
@@ -213,12 +291,39 @@ hipError_t launch_kron_expand(int prec, const double* Lx, const double* Ly,
     return hipGetLastError();
 }
 
+size_t wind_gemm_part_elems(int G, int M) {
+    const int NC = 2 * M;
+    const int R = (G + GB_M - 1) / GB_M;
+    const int ncb = (NC + GB_N - 1) / GB_N;
+    if ((int64_t)((R + 1) / 2) * ncb >= kWindGemmSplitBelow) return 0;   // whole row blocks
+    return (size_t)gemm_nchunks(G, R - 1) * G * NC;
+}
+
 static hipError_t wind_gemm(int prec, const void* Lfac, const void* Z, double wm0, double wm1,
-                            const double* wmean, int mper, int G, int M, void* W,
+                            const double* wmean, int mper, int G, int M, void* W, void* part,
                             hipStream_t st) {
     const int NC = 2 * M;
     const int R = (G + GB_M - 1) / GB_M;
-    dim3 grid((unsigned)((R + 1) / 2), (unsigned)((NC + GB_N - 1) / GB_N));
+    const int ncb = (NC + GB_N - 1) / GB_N;
+    if (wind_gemm_part_elems(G, M) > 0) {   // few tiles: one workgroup per chunk
+        if (!part) return hipErrorInvalidValue;
+        const dim3 grid((unsigned)R, (unsigned)ncb, (unsigned)gemm_nchunks(G, R - 1));
+        const int64_t n = (int64_t)G * NC;
+        const unsigned sblocks = (unsigned)((n + 255) / 256);
+        if (prec == 0) {
+            hipLaunchKernelGGL(k_wind_gemm_part<double>, grid, dim3(256), 0, st,
+                               (const double*)Lfac, (const double*)Z, G, NC, (double*)part);
+            hipLaunchKernelGGL(k_wind_gemm_sum<double>, dim3(sblocks), dim3(256), 0, st,
+                               (const double*)part, G, NC, wm0, wm1, wmean, mper, (double*)W);
+        } else {
+            hipLaunchKernelGGL(k_wind_gemm_part<float>, grid, dim3(256), 0, st,
+                               (const float*)Lfac, (const float*)Z, G, NC, (float*)part);
+            hipLaunchKernelGGL(k_wind_gemm_sum<float>, dim3(sblocks), dim3(256), 0, st,
+                               (const float*)part, G, NC, wm0, wm1, wmean, mper, (float*)W);
+        }
+        return hipGetLastError();
+    }
+    dim3 grid((unsigned)((R + 1) / 2), (unsigned)ncb);
     if (prec == 0)
         hipLaunchKernelGGL(k_wind_gemm<double>, grid, dim3(256), 0, st,
                            (const double*)Lfac, (const double*)Z, G, NC, wm0, wm1, wmean,
@@ -230,15 +335,15 @@ static hipError_t wind_gemm(int prec, const void* Lfac, const void* Z, double wm
 }
 
 hipError_t launch_wind_gemm(int prec, const void* Lfac, const void* Z, double wm0,
-                            double wm1, int G, int M, void* W, hipStream_t st) {
-    return wind_gemm(prec, Lfac, Z, wm0, wm1, nullptr, 1, G, M, W, st);
+                            double wm1, int G, int M, void* W, void* part, hipStream_t st) {
+    return wind_gemm(prec, Lfac, Z, wm0, wm1, nullptr, 1, G, M, W, part, st);
 }
 
 hipError_t launch_wind_gemm_grouped(int prec, const void* Lfac, const void* Z,
                                     const double* wmean, int mper, int G, int M, void* W,
-                                    hipStream_t st) {
+                                    void* part, hipStream_t st) {
     if (!wmean || mper < 1) return hipErrorInvalidValue;
-    return wind_gemm(prec, Lfac, Z, 0.0, 0.0, wmean, mper, G, M, W, st);
+    return wind_gemm(prec, Lfac, Z, 0.0, 0.0, wmean, mper, G, M, W, part, st);
 }
 
 }  // namespace smc

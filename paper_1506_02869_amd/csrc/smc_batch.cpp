@@ -58,6 +58,7 @@ struct smc_batch {
     double *d_acpar = nullptr, *d_targets = nullptr;
     int8_t* d_kind = nullptr;
     void *d_Lfac = nullptr, *d_Z = nullptr, *d_W = nullptr;
+    void* d_wpart = nullptr;   // wind GEMM chunk products (few-tile shapes)
     void *d_u = nullptr, *d_u2 = nullptr, *d_up = nullptr;
     double* d_cost = nullptr;
     uint8_t* d_feas = nullptr;
@@ -270,7 +271,7 @@ hipError_t enqueue_update(smc_batch* b, hipStream_t st, int* launches, bool time
     for (int J = 0; J < K; ++J) {
         Q(launch_b_normals(b->prec, b->d_tab, b->d_hdr, ns, J, b->G, M, b->d_Z, st));
         Q(launch_wind_gemm_grouped(b->prec, b->d_Lfac, b->d_Z, b->d_wmean, M, b->G, ns * M,
-                                   b->d_W, st));
+                                   b->d_W, b->d_wpart, st));
         Q(mark(2 * pass));
         Q(rollout_pass(b, pass, u, launches, st));
         Q(mark(2 * pass + 1));
@@ -563,6 +564,8 @@ smc_status smc_batch_init(const smc_scenario* sc, int32_t ns, smc_batch** out) {
         (st = balloc<char>(b, (char**)&b->d_Lfac, G * G, b->rsz)) ||
         (st = balloc<char>(b, (char**)&b->d_Z, G * 2 * M * nsz, b->rsz)) ||
         (st = balloc<char>(b, (char**)&b->d_W, G * 2 * M * nsz, b->rsz)) ||
+        (st = balloc<char>(b, (char**)&b->d_wpart,
+                           std::max<size_t>(wind_gemm_part_elems((int)G, (int)(M * nsz)), 1), b->rsz)) ||
         (st = balloc<char>(b, (char**)&b->d_u, nu, b->rsz)) ||
         (st = balloc<char>(b, (char**)&b->d_u2, nu, b->rsz)) ||
         (st = balloc<char>(b, (char**)&b->d_up, b->move == SMC_MOVE_RWMH ? nu : 1, b->rsz)) ||
@@ -773,7 +776,7 @@ smc_status smc_batch_autotune(smc_batch* b, int64_t mpc_step, const double* stat
     BHIP(b, launch_b_init(b->prec, b->d_tab, b->d_hdr, b->ns, b->max_count, b->d_u, st));
     BHIP(b, launch_b_normals(b->prec, b->d_tab, b->d_hdr, b->ns, 0, b->G, b->M, b->d_Z, st));
     BHIP(b, launch_wind_gemm_grouped(b->prec, b->d_Lfac, b->d_Z, b->d_wmean, b->M, b->G,
-                                     b->ns * b->M, b->d_W, st));
+                                     b->ns * b->M, b->d_W, b->d_wpart, st));
     unsigned long long* steps = reinterpret_cast<unsigned long long*>(b->d_cnt + b->cnt_steps);
     smc_batch_tuning best = b->tune;
     const int blocks[3] = {64, 128, 256};

@@ -56,6 +56,7 @@ struct smc_ctx {
     float* d_pop = nullptr;
     void* d_Lfac = nullptr;
     void *d_Z = nullptr, *d_W = nullptr, *d_Wt = nullptr;
+    void* d_wpart = nullptr;   // wind GEMM chunk products (few-tile shapes)
     void *d_u = nullptr, *d_u2 = nullptr, *d_up = nullptr;
     double* d_cost = nullptr;
     uint8_t* d_feas = nullptr;
@@ -270,7 +271,7 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
                                       c->G, c->M, c->d_Z, st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_wind[2 * J], st));
         HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G,
-                                   c->M, c->d_W, st));
+                                   c->M, c->d_W, c->d_wpart, st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_wind[2 * J + 1], st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J], st));
         HIP_OK(c, do_rollout(c, rp,
@@ -643,7 +644,8 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     if ((st = dalloc_t(c, &c->d_acpar, N * SMC_AC_NPAR)) || (st = dalloc_t(c, &c->d_targets, N * 4)) ||
         (st = dalloc_t(c, &c->d_kind, N)) ||
         (st = dalloc(c, &c->d_Lfac, G * G * c->rsz)) || (st = dalloc(c, &c->d_Z, G * 2 * M * c->rsz)) ||
-        (st = dalloc(c, &c->d_W, M * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_Wt, M * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_u, L * N * D * c->rsz)) ||
+        (st = dalloc(c, &c->d_W, M * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_Wt, M * G * 2 * c->rsz)) ||
+        (st = dalloc(c, &c->d_wpart, std::max<size_t>(wind_gemm_part_elems((int)G, (int)M), 1) * c->rsz)) || (st = dalloc(c, &c->d_u, L * N * D * c->rsz)) ||
         (st = dalloc(c, &c->d_u2, L * N * D * c->rsz)) ||
         (st = dalloc(c, &c->d_up, (c->move != SMC_MOVE_JITTER ? L : 1) * N * D * c->rsz)) ||
         (st = dalloc_t(c, &c->d_cost, M * L * N)) || (st = dalloc_t(c, &c->d_feas, M * L * N)) ||
@@ -759,7 +761,7 @@ smc_status smc_plant_step(smc_ctx* c, int64_t mpc_step, int32_t plant_iter, cons
     HIP_OK(c, launch_wind_normals(c->prec, make_stream(c->seed, mpc_step, plant_iter, P_WIND, c->scen_id),
                                   c->G, c->M, c->d_Z, st));
     HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G, c->M,
-                               c->d_W, st));
+                               c->d_W, c->d_wpart, st));
     RolloutParams rp = c->rp;
     rp.H = horizon;
     HIP_OK(c, launch_plant(c->prec, rp, c->d_ctrl_out, c->d_W, c->d_states, c->d_kact, c->d_acpar,
@@ -802,7 +804,7 @@ smc_status smc_eval_cost(smc_ctx* c, int64_t mpc_step, int32_t iter, const doubl
     HIP_OK(c, launch_wind_normals(c->prec, make_stream(c->seed, mpc_step, iter, P_WIND, c->scen_id),
                                   c->G, c->M, c->d_Z, st));
     HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G, c->M,
-                               c->d_W, st));
+                               c->d_W, c->d_wpart, st));
     RolloutParams rp = c->rp;
     rp.H = horizon;
     rp.P = P;
@@ -849,7 +851,7 @@ smc_status smc_k_wind_normals(smc_ctx* c, int64_t mpc_step, int32_t iter, void* 
 smc_status smc_k_wind_gemm(smc_ctx* c, const void* Z, const double* wind_mean, void* W, void* stream) {
     if (!c || !Z || !W || !wind_mean) return fail(c, SMC_EINVAL, "smc_k_wind_gemm: bad arguments");
     HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, Z, wind_mean[0], wind_mean[1], c->G, c->M, W,
-                               pick(c, stream)));
+                               c->d_wpart, pick(c, stream)));
     return SMC_OK;
 }
 
