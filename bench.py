@@ -277,6 +277,35 @@ def compare_moves(args):
     print(json.dumps(out), flush=True)
 
 
+def rolling(args):
+    """The receding-horizon loop (solve, apply the first control segment to
+    the plant, move the window) for --rolling updates of the chosen workload,
+    host form: wall time per update including the plant step and the host
+    copies.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1506_02869_amd as smc
+    import synth
+
+    scen = getattr(synth, WORKLOADS[args.workload][1])()
+    torch.cuda.set_device(0)
+    ctx = smc.smc_mpc_init(scen)
+    smc.rolling_window(ctx, 1)                     # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = smc.rolling_window(ctx, args.rolling)
+    ms = (time.perf_counter() - t0) * 1e3 / args.rolling
+    steps = sum(h["info"]["aircraft_steps"] for h in hist)
+    out = {"metric": "wall time per receding-horizon update (MPC update + plant step, host form)",
+           "workload": WORKLOADS[args.workload][0], "updates": args.rolling,
+           "ms_per_update": round(ms, 2), "aircraft_steps_per_s": steps / (ms * 1e-3 * args.rolling),
+           "events": [h["event"].tolist() for h in hist],
+           "active": [int((h["k_active"] >= 0).sum()) for h in hist],
+           "cost": [float(h["cost"][0]) for h in hist]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,6 +320,8 @@ def main():
     ap.add_argument("--compare-moves", action="store_true",
                     help="C4: time each move to reach plain SMC's converged cost")
     ap.add_argument("--compare-iters", default="5,10,20,40,80,160")
+    ap.add_argument("--rolling", type=int, default=0,
+                    help="run this many receding-horizon updates (solve + plant) instead")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -314,6 +345,8 @@ def main():
         del src, dst
     if args.compare_moves:
         return compare_moves(args)
+    if args.rolling > 0:
+        return rolling(args)
     desc, key = WORKLOADS[args.workload]
     if key == "c3":
         return bench_batch(args, desc)

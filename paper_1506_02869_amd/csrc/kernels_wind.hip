@@ -179,7 +179,9 @@ __host__ __device__ inline int gemm_nchunks(int G, int rb) {
     return (gemm_kmax(G, rb) + GK_CHUNK - 1) / GK_CHUNK;
 }
 
-// One row block: all its chunks in turn, the sum and the epilogue.
+// One row block: one pipelined pass over its K extent, the accumulators
+// folded into the running sum at every chunk boundary (the same additions as
+// the per-chunk form), then the epilogue.
 template <typename T>
 __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* __restrict__ Z,
                                               int G, int NC, int rb, int cb, double wm0,
@@ -191,13 +193,37 @@ __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* 
     const int wr = (wave >> 1) * 16, wc = (wave & 1) * 32;
     const int row0 = rb * GB_M, col0 = cb * GB_N;
     const int kmax = gemm_kmax(G, rb);
+    const int nst = (kmax + GB_K - 1) / GB_K;
+    constexpr int kChunkStages = GK_CHUNK / GB_K;
     acc_t tot0 = {0, 0, 0, 0}, tot1 = {0, 0, 0, 0};
-    for (int j = 0; j * GK_CHUNK < kmax; ++j) {
-        acc_t a0, a1;
-        gemm_range<T>(A, Z, G, NC, row0, col0, j * GK_CHUNK, min(kmax, (j + 1) * GK_CHUNK), As,
-                      Bs, a0, a1);
+    acc_t acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    GemmStage<T> st;
+    gemm_fetch<T>(A, Z, G, NC, row0, col0, 0, st);
+    gemm_store<T>(st, As, Bs);
+    __syncthreads();
+    for (int s = 0; s < nst; ++s) {
+        const int cur = s & 1;
+        const T* Ac = As + cur * (GB_K * GA_LD);
+        const T* Bc = Bs + cur * (GB_K * GBB_LD);
+        if (s + 1 < nst) gemm_fetch<T>(A, Z, G, NC, row0, col0, (s + 1) * GB_K, st);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) { tot0[r] += a0[r]; tot1[r] += a1[r]; }
+        for (int kk = 0; kk < GB_K; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            const T a = Ac[kr * GA_LD + wr + (lane & 15)];
+            const T b0 = Bc[kr * GBB_LD + wc + (lane & 15)];
+            const T b1 = Bc[kr * GBB_LD + wc + 16 + (lane & 15)];
+            acc0 = Mfma<T>::op(a, b0, acc0);
+            acc1 = Mfma<T>::op(a, b1, acc1);
+        }
+        if (s + 1 == nst || (s + 1) % kChunkStages == 0) {   // end of a chunk
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { tot0[r] += acc0[r]; tot1[r] += acc1[r]; }
+            acc0 = {0, 0, 0, 0};
+            acc1 = {0, 0, 0, 0};
+        }
+        if (s + 1 < nst) gemm_store<T>(st, As + (cur ^ 1) * (GB_K * GA_LD),
+                                       Bs + (cur ^ 1) * (GB_K * GBB_LD));
+        __syncthreads();
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
