@@ -75,12 +75,15 @@ typedef struct {
 
 /* Create a batch of n_scen (1..SMC_BATCH_MAX_SCENARIOS) scenarios.  Each
  * scenario is validated as by smc_mpc_init(); across the batch they must
- * share n_particles, n_wind, n_iters, precision, move (SMC_MOVE_JITTER or
- * SMC_MOVE_RWMH), grid_n, box, wind_sigma, wind_ell and wind_nugget, and have
- * at most SMC_BATCH_MAX_AIRCRAFT aircraft.  Everything else (aircraft, N, S,
- * horizon_max, costs, limits, kappa, sigma_move, seed, scenario_id) may
- * differ.  Errors: SMC_EINVAL (message names the scenario), SMC_ENOTSPD,
- * SMC_ENOMEM, SMC_EDEVICE; *out is NULL on error. */
+ * share n_particles, n_wind, n_iters, precision, move (any of SMC_MOVE_*),
+ * grid_n, box, wind_sigma, wind_ell and wind_nugget, and have at most
+ * SMC_BATCH_MAX_AIRCRAFT aircraft.  Everything else (aircraft, N, S,
+ * horizon_max, costs, limits, kappa, sigma_move, mala_step, seed,
+ * scenario_id) may differ.  With SMC_MOVE_MALA every iteration adds two
+ * adjoint launches per scenario (gradients of the particles and of the
+ * proposals), and a captured graph is re-captured when the horizons change.
+ * Errors: SMC_EINVAL (message names the scenario), SMC_ENOTSPD, SMC_ENOMEM,
+ * SMC_EDEVICE; *out is NULL on error. */
 smc_status smc_batch_init(const smc_scenario* scenarios, int32_t n_scen, smc_batch** out);
 
 /* One MPC update of every scenario (host arrays, synchronous).  horizons[s]

@@ -100,6 +100,7 @@ struct BatchScen {
     int64_t off_ctrl;      // returned controls [N][D]
     int64_t off_cost;      // returned expected costs [1 + N]
     double sigma_move;
+    double mala_step;      // Langevin step (MALA moves)
     Ctrl3 box;
 };
 
@@ -219,6 +220,15 @@ hipError_t launch_b_accept(int prec, const BatchScen* tab, const BatchStep* hdr,
                            const double* chat_prop, uint8_t* feas_pn, const uint8_t* feas_prop,
                            double* logw, const double* logw_prop, int32_t* flags,
                            uint32_t* accepted, hipStream_t st);
+hipError_t launch_b_mala_propose(int prec, const BatchScen* tab, const BatchStep* hdr, int ns,
+                                int J, int64_t max_count, const void* u, const double* g,
+                                void* u_prop, hipStream_t st);
+hipError_t launch_b_mala_accept(int prec, const BatchScen* tab, const BatchStep* hdr, int ns,
+                                int J, int P, int64_t max_count, void* u, const void* u_prop,
+                                const double* g, const double* g_prop, double* chat,
+                                const double* chat_prop, uint8_t* feas_pn,
+                                const uint8_t* feas_prop, double* logw, const double* logw_prop,
+                                int32_t* flags, uint32_t* accepted, hipStream_t st);
 hipError_t launch_b_select(const BatchScen* tab, int ns, int J, int P, const double* logw,
                            const double* chat, int32_t* best, hipStream_t st);
 hipError_t launch_b_write_result(int prec, const BatchScen* tab, int ns, const void* u,

@@ -102,6 +102,45 @@ __global__ void k_b_propose(const BatchScen* __restrict__ tab, const BatchStep* 
     propose_at<R>(e, u + sc.off_u, up + sc.off_u, s, sc.sigma_move);
 }
 
+// Langevin proposal of every scenario (the adjoint's gradient g laid out
+// like the particles).
+template <typename R>
+__global__ void k_b_mala_propose(const BatchScen* __restrict__ tab,
+                                 const BatchStep* __restrict__ hdr, int J, const R* __restrict__ u,
+                                 const double* __restrict__ g, R* __restrict__ up) {
+    const BatchScen& sc = tab[blockIdx.y];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)sc.rp.P * sc.N * sc.D) return;
+    const Stream s = make_stream(sc.seed, hdr->mpc_step, J, P_MALA, sc.scen_id);
+    const double coef = -sc.beta[J] / (double)sc.rp.M;
+    mala_propose_at<R>(e, u + sc.off_u, g + sc.off_u, coef, sc.mala_step, s, up + sc.off_u);
+}
+
+// Langevin decision per particle; accepted counts as for random-walk moves.
+template <typename R>
+__global__ void k_b_mala_decide(const BatchScen* __restrict__ tab,
+                                const BatchStep* __restrict__ hdr, int J, const R* __restrict__ u,
+                                const R* __restrict__ up, const double* __restrict__ g,
+                                const double* __restrict__ g_prop, const double* __restrict__ logw,
+                                const double* __restrict__ logw_prop, int32_t* __restrict__ flags,
+                                uint32_t* __restrict__ accepted) {
+    const int n = blockIdx.y;
+    const BatchScen& sc = tab[n];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = sc.rp.P;
+    int acc = 0;
+    if (p < P) {
+        const Stream s = make_stream(sc.seed, hdr->mpc_step, J, P_ACCEPT, sc.scen_id);
+        const double coef = -sc.beta[J] / (double)sc.rp.M;
+        acc = mala_decide_at<R>(p, sc.N, sc.D, u + sc.off_u, up + sc.off_u, g + sc.off_u,
+                                g_prop + sc.off_u, coef, sc.mala_step, logw + sc.off_pn,
+                                logw_prop + sc.off_pn, s);
+        flags[(int64_t)n * P + p] = acc;
+    }
+    const int cnt = __popcll(__ballot(acc != 0));
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(accepted + n, (uint32_t)cnt);
+}
+
 // Decision per particle; accepted counts per scenario for the step's
 // acceptance rate (one atomic per wave).
 __global__ void k_b_accept_decide(const BatchScen* __restrict__ tab,
@@ -249,6 +288,48 @@ hipError_t launch_b_accept(int prec, const BatchScen* tab, const BatchStep* hdr,
                            uint32_t* accepted, hipStream_t st) {
     hipLaunchKernelGGL(k_b_accept_decide, dim3(nblk(P, 256), (unsigned)ns), dim3(256), 0, st,
                        tab, hdr, J, logw, logw_prop, flags, accepted);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid(nblk(max_count, 256), (unsigned)ns);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_b_accept_apply<double>, grid, dim3(256), 0, st, tab, (double*)u,
+                           (const double*)u_prop, chat, chat_prop, feas_pn, feas_prop, logw,
+                           logw_prop, flags);
+    else
+        hipLaunchKernelGGL(k_b_accept_apply<float>, grid, dim3(256), 0, st, tab, (float*)u,
+                           (const float*)u_prop, chat, chat_prop, feas_pn, feas_prop, logw,
+                           logw_prop, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_mala_propose(int prec, const BatchScen* tab, const BatchStep* hdr, int ns,
+                                int J, int64_t max_count, const void* u, const double* g,
+                                void* u_prop, hipStream_t st) {
+    const dim3 grid(nblk(max_count, 256), (unsigned)ns);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_b_mala_propose<double>, grid, dim3(256), 0, st, tab, hdr, J,
+                           (const double*)u, g, (double*)u_prop);
+    else
+        hipLaunchKernelGGL(k_b_mala_propose<float>, grid, dim3(256), 0, st, tab, hdr, J,
+                           (const float*)u, g, (float*)u_prop);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_mala_accept(int prec, const BatchScen* tab, const BatchStep* hdr, int ns,
+                                int J, int P, int64_t max_count, void* u, const void* u_prop,
+                                const double* g, const double* g_prop, double* chat,
+                                const double* chat_prop, uint8_t* feas_pn,
+                                const uint8_t* feas_prop, double* logw, const double* logw_prop,
+                                int32_t* flags, uint32_t* accepted, hipStream_t st) {
+    const dim3 dgrid(nblk(P, 256), (unsigned)ns);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_b_mala_decide<double>, dgrid, dim3(256), 0, st, tab, hdr, J,
+                           (const double*)u, (const double*)u_prop, g, g_prop, logw, logw_prop,
+                           flags, accepted);
+    else
+        hipLaunchKernelGGL(k_b_mala_decide<float>, dgrid, dim3(256), 0, st, tab, hdr, J,
+                           (const float*)u, (const float*)u_prop, g, g_prop, logw, logw_prop,
+                           flags, accepted);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 grid(nblk(max_count, 256), (unsigned)ns);

@@ -13,6 +13,7 @@
 // controls.  Discrete events (landing) carry no derivative; clamps,
 // max(T, 0) and min(t, 1) take the derivative of the active branch.
 #include "rollout_math.h"
+#include "smc_steps.h"
 
 namespace smc {
 
@@ -543,15 +544,9 @@ __global__ void k_mala_propose(int64_t count, const R* __restrict__ u, const dou
                                double coef, double eps, Stream s, R* __restrict__ up) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= count) return;
-    double z0, z1;
-    normal_pair(draw(s, (uint32_t)e), z0, z1);
-    const double g = coef * gsum[e];
-    up[e] = (R)((double)u[e] + 0.5 * eps * eps * g + eps * z0);
+    mala_propose_at<R>(e, u, gsum, coef, eps, s, up);
 }
 
-// Per particle: reject a proposal outside the control box or violating;
-// accept one if the current particle violates; otherwise accept iff
-// log U < sum_i logw' - sum_i logw + log q(u | u') - log q(u' | u).
 template <typename R>
 __global__ void k_mala_decide(int P, int N, int D, const R* __restrict__ u, const R* __restrict__ up,
                               const double* __restrict__ g, const double* __restrict__ gp_,
@@ -560,35 +555,7 @@ __global__ void k_mala_decide(int P, int N, int D, const R* __restrict__ u, cons
                               int32_t* __restrict__ flags) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    const int64_t base = (int64_t)p * N * D;
-    const int64_t n = (int64_t)N * D;
-    bool inside = true;
-    double fwd = 0.0, bwd = 0.0;
-    const double h = 0.5 * eps * eps;
-    for (int64_t e = 0; e < n; ++e) {
-        const double a = (double)u[base + e], b = (double)up[base + e];
-        if (!(b >= 0.0 && b <= 1.0)) inside = false;
-        const double d1 = b - a - h * coef * g[base + e];      // u' given u
-        const double d2 = a - b - h * coef * gp_[base + e];    // u given u'
-        fwd += d1 * d1;
-        bwd += d2 * d2;
-    }
-    double s_new = 0.0, s_old = 0.0;
-    for (int i = 0; i < N; ++i) {
-        s_new += logw_prop[(int64_t)p * N + i];
-        s_old += logw[(int64_t)p * N + i];
-    }
-    int acc;
-    if (!inside || s_new == -INFINITY) {
-        acc = 0;
-    } else if (s_old == -INFINITY) {
-        acc = 1;
-    } else {
-        const double lq = (fwd - bwd) / (2.0 * eps * eps);   // log q(u|u') - log q(u'|u)
-        const Words4 w = draw(s, (uint32_t)p);
-        acc = log(uniform01(w.w0, w.w1)) < (s_new - s_old) + lq ? 1 : 0;
-    }
-    flags[p] = acc;
+    flags[p] = mala_decide_at<R>(p, N, D, u, up, g, gp_, coef, eps, logw, logw_prop, s);
 }
 
 hipError_t launch_mala_propose(int prec, int64_t count, const void* u, const double* gsum,

@@ -33,6 +33,7 @@ struct smc_batch {
     std::vector<int64_t> off_u, off_pn, off_ctrl, off_cost;  // ns + 1
     int rows = 0;                                       // sum N
     int64_t max_count = 0, max_pn = 0;                  // max L N D, max L N
+    size_t gpart_elems = 1;                             // largest adjoint chunk partials
     int64_t n_items = 0;
     int bstart[kNumBuckets] = {}, bcount[kNumBuckets] = {};
     std::vector<int> plan_h;   // horizons of the current plan
@@ -60,6 +61,12 @@ struct smc_batch {
     void *d_Lfac = nullptr, *d_Z = nullptr, *d_W = nullptr;
     void* d_wpart = nullptr;   // wind GEMM chunk products (few-tile shapes)
     void *d_u = nullptr, *d_u2 = nullptr, *d_up = nullptr;
+    // Langevin moves: the adjoint's gradients of the particles and of the
+    // proposals (laid out like the particles), its chunk partials and its
+    // sample-interleaved copy of one scenario's fields (reused scenario by
+    // scenario)
+    double *d_g = nullptr, *d_g2 = nullptr, *d_gpart = nullptr;
+    void* d_Wt = nullptr;
     double* d_cost = nullptr;
     uint8_t* d_feas = nullptr;
     double *d_chat = nullptr, *d_logw = nullptr, *d_chat2 = nullptr, *d_logw2 = nullptr;
@@ -159,8 +166,6 @@ smc_status validate_batch(const smc_scenario* sc, int ns) {
                          "scenario %d: n_particles, n_wind and n_iters must match scenario 0", s);
         if (x.precision != a.precision || x.move != a.move)
             return bfail(nullptr, SMC_EINVAL, "scenario %d: precision and move must match scenario 0", s);
-        if (x.move != SMC_MOVE_JITTER && x.move != SMC_MOVE_RWMH)
-            return bfail(nullptr, SMC_EINVAL, "batched form supports SMC_MOVE_JITTER and SMC_MOVE_RWMH");
         if (x.grid_n[0] != a.grid_n[0] || x.grid_n[1] != a.grid_n[1] || x.grid_n[2] != a.grid_n[2] ||
             !same3(x.box, a.box) || x.wind_sigma != a.wind_sigma || x.wind_ell != a.wind_ell ||
             x.wind_nugget != a.wind_nugget)
@@ -256,6 +261,21 @@ hipError_t rollout_pass(smc_batch* b, int pass, const void* u, int* launches, hi
     return hipSuccess;
 }
 
+// Gradient of the fuel + time cost of particles `u` for every scenario (one
+// adjoint launch per scenario, on its fields, states and aircraft tables;
+// the horizon is this update's).
+hipError_t batch_grad(smc_batch* b, const void* u, double* g, hipStream_t st) {
+    for (int s = 0; s < b->ns; ++s) {
+        const BatchScen& t = b->h_tab[s];
+        const hipError_t e = launch_rollout_grad(
+            b->prec, t.rp, (const char*)u + (size_t)t.off_u * b->rsz, t.ra.W, t.ra.states,
+            t.ra.k_active, t.ra.acpar, t.ra.targets, t.ra.kind, b->d_Wt, b->d_gpart, g + t.off_u,
+            st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // The device work of one update; every per-update input is already in the
 // batch's device buffers (table, header, wind means, states, items).
 hipError_t enqueue_update(smc_batch* b, hipStream_t st, int* launches, bool timed) {
@@ -277,6 +297,23 @@ hipError_t enqueue_update(smc_batch* b, hipStream_t st, int* launches, bool time
         Q(mark(2 * pass + 1));
         ++pass;
         Q(launch_b_reduce(b->d_tab, ns, J, b->max_pn, b->d_chat, b->d_feaspn, b->d_logw, st));
+        if (b->move == SMC_MOVE_MALA) {
+            // Langevin: gradients of the particles, proposals, their rollout
+            // and gradients, the decision (one adjoint launch per scenario)
+            Q(batch_grad(b, u, b->d_g, st));
+            Q(launch_b_mala_propose(b->prec, b->d_tab, b->d_hdr, ns, J, b->max_count, u, b->d_g,
+                                    b->d_up, st));
+            Q(mark(2 * pass));
+            Q(rollout_pass(b, pass, b->d_up, launches, st));
+            Q(mark(2 * pass + 1));
+            ++pass;
+            Q(launch_b_reduce(b->d_tab, ns, J, b->max_pn, b->d_chat2, b->d_feaspn2, b->d_logw2, st));
+            Q(batch_grad(b, b->d_up, b->d_g2, st));
+            Q(launch_b_mala_accept(b->prec, b->d_tab, b->d_hdr, ns, J, L, b->max_count, u, b->d_up,
+                                   b->d_g, b->d_g2, b->d_chat, b->d_chat2, b->d_feaspn,
+                                   b->d_feaspn2, b->d_logw, b->d_logw2, b->d_flags,
+                                   b->d_cnt + b->cnt_acc, st));
+        }
         if (b->move == SMC_MOVE_RWMH) {
             Q(launch_b_propose(b->prec, b->d_tab, b->d_hdr, ns, J, b->max_count, u, b->d_up, st));
             Q(mark(2 * pass));
@@ -341,6 +378,9 @@ smc_status upload(smc_batch* b, int64_t mpc_step, const double* states, const in
         for (int64_t q = 0; q < b->n_items; ++q) b->h_items[q] = BatchItem{is[q], iw[q]};
         b->plan_h.assign(horizons, horizons + ns);
         b->plan_order = b->tune.order;
+        // the adjoint's launches take the horizons as arguments: a captured
+        // graph of a Langevin batch holds the old ones
+        if (b->move == SMC_MOVE_MALA) drop_graph(b);
         BHIP(b, hipMemcpyAsync(b->d_items, b->h_items, sizeof(BatchItem) * b->n_items,
                                hipMemcpyHostToDevice, st));
     }
@@ -383,7 +423,7 @@ smc_status run_update(smc_batch* b, int64_t mpc_step, const double* states, cons
         }
         BHIP(b, hipGraphLaunch(b->gexec, st));
         for (int bk = 0; bk < kNumBuckets; ++bk)
-            if (b->bcount[bk]) launches += b->K * (b->move == SMC_MOVE_RWMH ? 2 : 1);
+            if (b->bcount[bk]) launches += b->K * (b->move != SMC_MOVE_JITTER ? 2 : 1);
     } else {
         BHIP(b, enqueue_update(b, st, &launches, info != nullptr));
     }
@@ -409,12 +449,12 @@ smc_status run_update(smc_batch* b, int64_t mpc_step, const double* states, cons
     info->aircraft_steps = (int64_t)tot;
     info->pair_tests = (int64_t)totp;
     info->ms_total = ms;
-    info->accept_rate = b->move == SMC_MOVE_RWMH
+    info->accept_rate = b->move != SMC_MOVE_JITTER
                             ? (double)acc / ((double)b->K * b->L * b->ns) : 0.0;
     info->feasible_frac = fe.empty() ? 0.0 : (double)nf / (double)fe.size();
     info->graph = b->use_graph ? 1 : 0;
     info->rollout_launches = launches;
-    info->rollout_passes = b->K * (b->move == SMC_MOVE_RWMH ? 2 : 1);
+    info->rollout_passes = b->K * (b->move != SMC_MOVE_JITTER ? 2 : 1);
     info->ms_rollout = 0.0;
     if (!b->use_graph)
         for (int q = 0; q < info->rollout_passes; ++q) {
@@ -512,6 +552,7 @@ smc_status smc_batch_init(const smc_scenario* sc, int32_t ns, smc_batch** out) {
         b->off_cost[s + 1] = b->off_cost[s] + 1 + N;
         b->max_count = std::max(b->max_count, cnt);
         b->max_pn = std::max(b->max_pn, (int64_t)b->L * N);
+        b->gpart_elems = std::max(b->gpart_elems, grad_partial_elems(b->L, N, S, b->M));
     }
     b->rows = b->off_n[ns];
     b->n_items = (int64_t)ns * (((int64_t)b->L * b->M + kItemWorlds - 1) / kItemWorlds);
@@ -568,7 +609,11 @@ smc_status smc_batch_init(const smc_scenario* sc, int32_t ns, smc_batch** out) {
                            std::max<size_t>(wind_gemm_part_elems((int)G, (int)(M * nsz)), 1), b->rsz)) ||
         (st = balloc<char>(b, (char**)&b->d_u, nu, b->rsz)) ||
         (st = balloc<char>(b, (char**)&b->d_u2, nu, b->rsz)) ||
-        (st = balloc<char>(b, (char**)&b->d_up, b->move == SMC_MOVE_RWMH ? nu : 1, b->rsz)) ||
+        (st = balloc<char>(b, (char**)&b->d_up, b->move != SMC_MOVE_JITTER ? nu : 1, b->rsz)) ||
+        (st = balloc(b, &b->d_g, b->move == SMC_MOVE_MALA ? nu : 1)) ||
+        (st = balloc(b, &b->d_g2, b->move == SMC_MOVE_MALA ? nu : 1)) ||
+        (st = balloc<char>(b, (char**)&b->d_Wt, b->move == SMC_MOVE_MALA ? G * 2 * M : 1, b->rsz)) ||
+        (st = balloc(b, &b->d_gpart, b->move == SMC_MOVE_MALA ? b->gpart_elems : 1)) ||
         (st = balloc(b, &b->d_cost, M * npn)) || (st = balloc(b, &b->d_feas, M * npn)) ||
         (st = balloc(b, &b->d_chat, npn)) || (st = balloc(b, &b->d_logw, npn)) ||
         (st = balloc(b, &b->d_chat2, npn)) || (st = balloc(b, &b->d_logw2, npn)) ||
@@ -642,6 +687,7 @@ smc_status smc_batch_init(const smc_scenario* sc, int32_t ns, smc_batch** out) {
         t.off_ctrl = b->off_ctrl[s];
         t.off_cost = b->off_cost[s];
         t.sigma_move = x.sigma_move;
+        t.mala_step = x.mala_step;
         for (int c = 0; c < 3; ++c) { t.box.lo[c] = x.ctrl_lo[c]; t.box.sp[c] = x.ctrl_hi[c] - x.ctrl_lo[c]; }
     }
 #define IHIP(expr)                                                                       \

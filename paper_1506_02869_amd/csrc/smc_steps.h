@@ -189,6 +189,55 @@ __device__ __forceinline__ void propose_at(int64_t e, const R* __restrict__ u,
     up[e] = to_real<R>(r);
 }
 
+// ---- Langevin proposal: u' = u + (eps^2 / 2) g + eps xi, g = coef * gsum --
+// (gsum: the adjoint's gradient summed over the wind samples; coef =
+// -beta_J / M makes g the drift of the tempered fuel + time target)
+template <typename R>
+__device__ __forceinline__ void mala_propose_at(int64_t e, const R* __restrict__ u,
+                                                const double* __restrict__ gsum, double coef,
+                                                double eps, const Stream& s, R* __restrict__ up) {
+    double z0, z1;
+    normal_pair(draw(s, (uint32_t)e), z0, z1);
+    const double g = coef * gsum[e];
+    up[e] = to_real<R>((double)u[e] + 0.5 * eps * eps * g + eps * z0);
+}
+
+// ---- Langevin decision of particle p: reject a proposal outside the box or
+// violating; accept one if the current particle violates; otherwise accept
+// iff log U < sum_i logw' - sum_i logw + log q(u | u') - log q(u' | u) -----
+template <typename R>
+__device__ __forceinline__ int mala_decide_at(int p, int N, int D, const R* __restrict__ u,
+                                              const R* __restrict__ up,
+                                              const double* __restrict__ g,
+                                              const double* __restrict__ gp_, double coef,
+                                              double eps, const double* __restrict__ logw,
+                                              const double* __restrict__ logw_prop,
+                                              const Stream& s) {
+    const int64_t base = (int64_t)p * N * D;
+    const int64_t n = (int64_t)N * D;
+    bool inside = true;
+    double fwd = 0.0, bwd = 0.0;
+    const double h = 0.5 * eps * eps;
+    for (int64_t e = 0; e < n; ++e) {
+        const double a = (double)u[base + e], b = (double)up[base + e];
+        if (!(b >= 0.0 && b <= 1.0)) inside = false;
+        const double d1 = b - a - h * coef * g[base + e];      // u' given u
+        const double d2 = a - b - h * coef * gp_[base + e];    // u given u'
+        fwd += d1 * d1;
+        bwd += d2 * d2;
+    }
+    double s_new = 0.0, s_old = 0.0;
+    for (int i = 0; i < N; ++i) {
+        s_new += logw_prop[(int64_t)p * N + i];
+        s_old += logw[(int64_t)p * N + i];
+    }
+    if (!inside || s_new == -INFINITY) return 0;
+    if (s_old == -INFINITY) return 1;
+    const double lq = (fwd - bwd) / (2.0 * eps * eps);   // log q(u|u') - log q(u'|u)
+    const Words4 w = draw(s, (uint32_t)p);
+    return log(uniform01(w.w0, w.w1)) < (s_new - s_old) + lq ? 1 : 0;
+}
+
 // ---- Metropolis decision of particle p on the joint target prod_i W_i ----
 __device__ __forceinline__ int accept_decide_at(int p, int N, const double* __restrict__ logw,
                                                 const double* __restrict__ logw_prop,

@@ -64,11 +64,7 @@ def test_batch_init_rejects_mismatch_on_host(change, msg):
     assert e.value.status == smc.SMC_EINVAL and msg in str(e.value)
 
 
-def test_batch_init_rejects_mala_and_bad_scenario():
-    a = _tiny(1, move="mala")
-    with pytest.raises(smc.SmcError) as e:
-        smc.smc_batch_init([a])
-    assert "SMC_MOVE_JITTER" in str(e.value)
+def test_batch_init_rejects_bad_scenario():
     b = _tiny(1)
     b["dt"] = 0.0
     with pytest.raises(smc.SmcError) as e:
