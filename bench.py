@@ -138,7 +138,7 @@ def bench_batch(args, desc):
     import paper_1506_02869_amd as smc
     import synth
 
-    scens = synth.c3()
+    scens = synth.c3(move=args.move) if args.move else synth.c3()
     torch.cuda.set_device(0)
     b = smc.smc_batch_init(scens)
     dev = torch.device("cuda")
@@ -186,7 +186,8 @@ def bench_batch(args, desc):
            "unit": "aircraft-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"C3: {desc}", "scenarios": b.ns,
+           "config": {"workload": f"C3: {desc}" + (f"; {args.move} moves" if args.move else ""),
+                      "scenarios": b.ns,
                       "aircraft": [int(n) for n in b.N], "horizons": [int(h) for h in hz],
                       "particles": int(scens[0]["L"]), "wind_samples": int(scens[0]["M"]),
                       "smc_iterations": int(scens[0]["K"]),
@@ -194,7 +195,8 @@ def bench_batch(args, desc):
                       "graph": True},
            "roofline": roof, "cpu_baseline": None,
            "step_info": {"ms_total_instrumented": info0["ms_total"],
-                         "feasible_frac": info0["feasible_frac"]}}
+                         "feasible_frac": info0["feasible_frac"],
+                         "accept_rate": info0["accept_rate"]}}
     print(json.dumps(out), flush=True)
 
 
@@ -317,6 +319,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="batched workload: autotune the persistent rollout's launch shape first")
+    ap.add_argument("--move", choices=["jitter", "rwmh", "mala"], default=None,
+                    help="batched workload: move of every scenario (default jitter)")
     ap.add_argument("--compare-moves", action="store_true",
                     help="C4: time each move to reach plain SMC's converged cost")
     ap.add_argument("--compare-iters", default="5,10,20,40,80,160")
