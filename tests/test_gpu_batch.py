@@ -67,6 +67,15 @@ def test_batch_equals_single_scenario_runs(lib, precision, move):
         assert 0.0 <= info["accept_rate"] < 1.0
 
 
+def test_batch_mala_many_samples(lib):
+    """Langevin moves with more wind samples than a wavefront (the adjoint
+    sums its samples in chunks through the batch's partial buffer)."""
+    scens = _mixed("fp32", "mala", L=32, M=80, K=2)
+    b = lib.smc_batch_init(scens)
+    out = lib.smc_batch_step(b, mpc_step=1)
+    _assert_same(b, out, _singles(lib, scens, mpc_step=1))
+
+
 def test_batch_horizons_and_inputs_per_update(lib):
     """Horizons below horizon_max (the work plan is re-ordered), changed
     states and wind means: still the single-scenario result."""
