@@ -40,6 +40,8 @@ def plant_step(scen, controls, states, k_active, n_steps, plant_iter, mpc_step,
     arrival that landed or a departure outside its exit radius leaves the
     problem (k_active -1); event is 1 landed, 2 left through the exit
     radius, 0 otherwise.  An aircraft that has not joined keeps its state."""
+    if int(scen.get("wind_model", 0)) != 0:
+        raise NotImplementedError("plant step: static wind model only")
     H = scen["H"] if horizon is None else int(horizon)
     N = scen["N"]
     lo, hi = scen["ctrl_lo"], scen["ctrl_hi"]

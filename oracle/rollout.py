@@ -155,7 +155,8 @@ def step_cost(scen, j, x, y, z, v, chi, z_act):
 def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
             with_margins=False, record=False):
     """Roll out particles ``u_norm`` [L, N, S, 3] (normalised controls in
-    [0, 1]) under wind fields ``W`` [M, G, 2].
+    [0, 1]) under wind fields ``W`` [M, G, 2], or [H, M, G, 2] with one
+    field per step (the paper's time-correlated model).
 
     Returns dict with cost [L, M, N], ft_cost [L, M, N] (its fuel + time part),
     feas [L, M, N] (bool), steps (number of
@@ -169,7 +170,7 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
     k_active = scen["k_active"] if k_active is None else k_active
     H = scen["H"] if horizon is None else int(horizon)
     N, S, dt = scen["N"], scen["S"], scen["dt"]
-    L, M = u_norm.shape[0], W.shape[0]
+    L, M = u_norm.shape[0], (W.shape[1] if W.ndim == 4 else W.shape[0])
     ac = scen["aircraft"]
     Sw, cd0, cd2, cf1, cf2, tmax, m_empty, phi_max, gamma_max = ac.T
     zmin, zmax, vmin, vmax = scen["env"]
@@ -206,7 +207,8 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
         present = active & (k >= kact) & ~done
         steps += int(present.sum())
 
-        wxy = _wind.trilinear(W, m_idx, scen["box"], scen["grid"], x, y, z)
+        Wk = W[k] if W.ndim == 4 else W           # per-step fields (paper's model)
+        wxy = _wind.trilinear(Wk, m_idx, scen["box"], scen["grid"], x, y, z)
         gamma = np.arcsin(zdot / v)               # climb angle from climb rate
         phi = np.arctan(v * chidot / G0)          # bank for the heading rate
         rho = isa_density(z)

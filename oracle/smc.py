@@ -302,8 +302,7 @@ def smc_mpc_step(scen, states=None, k_active=None, horizon=None, mpc_step=None,
     infeasible flag."""
     N, S, L, K = scen["N"], scen["S"], scen["L"], scen["K"]
     step = scen["mpc_step"] if mpc_step is None else mpc_step
-    Lfac = _wind.kron_factor(scen["box"], scen["grid"], scen["wind_sigma"],
-                             scen["wind_ell"], scen["wind_nugget"])
+    Lfac = _wind.factor(scen)
 
     fields = {}
 

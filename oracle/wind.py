@@ -18,6 +18,17 @@ Readings used here (listed with the others in the design notes):
   * one static field per wind sample, drawn afresh every SMC iteration (the
     paper samples new disturbances on every pass of the inner loop);
   * outside the grid, coordinates are clamped to the grid.
+
+The paper's own model is also here (wind_model 1): the exponential
+covariance of the "Wind Model" section, sigma^2 exp(-beta |dxy|) exp(-gamma
+|dz|) with the Euclidean horizontal distance, and the linear Gaussian time
+recursion W(0) = Qhat v(0), W(k+1) = a W(k) + Q v(k+1) with Qhat Qhat^T =
+R-hat, Q Q^T = (1 - a^2) R-hat and a = exp(-dt / G_t): one field per step of
+the horizon.  Its readings: sigma(z) is constant; the factor is taken as
+sigma L_h (x) L_z, L_h = chol(R_h + delta I) over the nx ny horizontal nodes
+and L_z = chol(R_z + delta I) over the nz levels (the covariance is a
+Kronecker product of the two, so this is the Cholesky factor of R-hat); the
+step-k normals of sample m are those of the static model's sample k M + m.
 """
 from __future__ import annotations
 
@@ -94,6 +105,77 @@ def kron_factor(box, grid_n, sigma, ell, nugget):
     return sigma * np.kron(np.kron(Lx, Ly), Lz)
 
 
+def exp_gram_h(ax, ay, beta):
+    """R_h[p, q] = exp(-beta |(x_p - x_q, y_p - y_q)|) over the horizontal
+    nodes p = ix * ny + iy (Euclidean distance, eq. cov)."""
+    pts = [(x, y) for x in ax for y in ay]
+    n = len(pts)
+    K = np.empty((n, n))
+    for p in range(n):
+        for q in range(n):
+            dx, dy = pts[p][0] - pts[q][0], pts[p][1] - pts[q][1]
+            K[p, q] = math.exp(-beta * math.sqrt(dx * dx + dy * dy))
+    return K
+
+
+def exp_gram_z(az, gamma):
+    """R_z[a, b] = exp(-gamma |z_a - z_b|) over the levels (eq. cov)."""
+    n = len(az)
+    K = np.empty((n, n))
+    for a in range(n):
+        for b in range(n):
+            K[a, b] = math.exp(-gamma * abs(az[a] - az[b]))
+    return K
+
+
+def exp_factor(box, grid_n, sigma, beta, gamma, nugget):
+    """Dense G x G factor Qhat = sigma L_h (x) L_z of the exponential
+    covariance (grid point g = (ix * ny + iy) * nz + iz, as kron_factor)."""
+    ax, ay, az = grid_axes(box, grid_n)
+    Kh = exp_gram_h(ax, ay, beta) + nugget * np.eye(len(ax) * len(ay))
+    Kz = exp_gram_z(az, gamma) + nugget * np.eye(len(az))
+    return sigma * np.kron(np.linalg.cholesky(Kh), np.linalg.cholesky(Kz))
+
+
+def ar1_coefficient(dt, tcorr):
+    """a = exp(-dt / G_t) of the time recursion."""
+    return math.exp(-dt / tcorr)
+
+
+def ar1_fields(Qhat, V, a, wind_mean):
+    """The paper's linear Gaussian model over H steps.
+
+    V[k] (H, G, M, 2): the standard normals of step k.  W(0) = Qhat v(0),
+    W(k+1) = a W(k) + Q v(k+1), Q = sqrt(1 - a^2) Qhat; the nominal wind is
+    added to every step's field.  Returns W[k, m, g, c] (H, M, G, 2)."""
+    H, G, M, _ = V.shape
+    Q = math.sqrt(1.0 - a * a) * Qhat
+    out = np.empty((H, M, G, 2))
+    Wk = None
+    for k in range(H):
+        vk = V[k].reshape(G, M * 2)
+        Wk = Qhat @ vk if k == 0 else a * Wk + Q @ vk
+        out[k] = Wk.reshape(G, M, 2).transpose(1, 0, 2)
+    out += np.asarray(wind_mean, dtype=np.float64)[None, None, None, :]
+    return out
+
+
+def ar1_normals(seed, mpc_step, J, G, M, H, scenario=0):
+    """V[k, g, m, c]: the normals of step k, sample m are those the static
+    model draws for sample k M + m."""
+    Z = wind_normals(seed, mpc_step, J, G, H * M, scenario)
+    return Z.reshape(G, H, M, 2).transpose(1, 0, 2, 3).copy()
+
+
+def factor(scen):
+    """The dense factor of the scenario's wind model."""
+    if int(scen.get("wind_model", 0)) == 1:
+        return exp_factor(scen["box"], scen["grid"], scen["wind_sigma"],
+                          scen["wind_beta"], scen["wind_gamma"], scen["wind_nugget"])
+    return kron_factor(scen["box"], scen["grid"], scen["wind_sigma"],
+                       scen["wind_ell"], scen["wind_nugget"])
+
+
 def wind_normals(seed, mpc_step, J, G, M, scenario=0):
     """Standard normals Z[g, m, c] for grid point g, sample m, component c.
 
@@ -117,12 +199,17 @@ def wind_field(Lfac, Z, wind_mean):
 
 
 def sample_field(scen, J, mpc_step=None, Lfac=None):
-    """The wind fields W_J[m, g, c] of one SMC iteration."""
+    """The wind fields of one SMC iteration: W_J[m, g, c] (static model) or
+    W_J[k, m, g, c] for the H steps of the horizon (the paper's model)."""
     if Lfac is None:
-        Lfac = kron_factor(scen["box"], scen["grid"], scen["wind_sigma"],
-                           scen["wind_ell"], scen["wind_nugget"])
+        Lfac = factor(scen)
     step = scen["mpc_step"] if mpc_step is None else mpc_step
     G = int(np.prod(scen["grid"]))
+    if int(scen.get("wind_model", 0)) == 1:
+        V = ar1_normals(scen["seed"], step, J, G, scen["M"], scen["H"],
+                        scen.get("scenario_id", 0))
+        return ar1_fields(Lfac, V, ar1_coefficient(scen["dt"], scen["wind_tcorr"]),
+                          scen["wind_mean"])
     Z = wind_normals(scen["seed"], step, J, G, scen["M"],
                      scen.get("scenario_id", 0))
     return wind_field(Lfac, Z, scen["wind_mean"])

@@ -51,6 +51,7 @@ MIX_WEIGHTS = (0.25, 0.65, 0.10, 0.40, 0.10, 0.25, 0.25)
 
 PRECISION = {"fp64": 0, "fp32": 1}
 MOVES = {"jitter": 0, "rwmh": 1, "mala": 2}
+WIND_MODELS = {"se": 0, "ar1": 1}   # static squared-exponential; the paper's time recursion
 
 
 def _aircraft_params(rng: np.random.Generator, n: int) -> np.ndarray:
@@ -119,7 +120,8 @@ def make_scenario(name: str, *, n_arr: int, n_dep: int, box, grid, H: int,
                   alpha_time: float = 0.2, alpha_noise: float = 0.0,
                   noise_alt: float = 2000.0, pop_n=None, kappa: float = 1.0,
                   sigma_move: float = 0.02, mala_step: float = 1e-2,
-                  mpc_step: int = 0) -> dict:
+                  mpc_step: int = 0, wind_model: str = "se",
+                  wind_tcorr: float = 1800.0) -> dict:
     rng = np.random.default_rng(seed)
     box = tuple(float(b) for b in box)
     N = n_arr + n_dep
@@ -162,6 +164,10 @@ def make_scenario(name: str, *, n_arr: int, n_dep: int, box, grid, H: int,
         sigma_move=float(sigma_move), mala_step=float(mala_step),
         seed=int(seed), states=states, k_active=k_active,
         wind_mean=np.zeros(2), mpc_step=int(mpc_step),
+        # the paper's exponential covariance and time recursion (wind_model
+        # 1): beta, gamma [1/m] as quoted there, G_t [s] a stated choice
+        wind_model=WIND_MODELS[wind_model], wind_beta=1.6e-6, wind_gamma=1.5e-5,
+        wind_tcorr=float(wind_tcorr),
     )
 
 
