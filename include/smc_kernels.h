@@ -61,7 +61,21 @@ smc_status smc_k_wind_gemm(smc_ctx* ctx, const void* Z, const double* wind_mean,
 /* Copy of the context's dense factor Lchol[G][G] (real) into `out`. */
 smc_status smc_k_wind_factor(smc_ctx* ctx, void* out, void* stream);
 
-/* Rollout of P particles under the fields W (Sec. "Trajectory Planning",
+/* The wind fields of iteration `iter` under the context's wind model, as an
+ * update draws them (Sec. "Wind Model").  SMC_WIND_SE: W[M][G][2], the
+ * same as smc_k_wind_normals then smc_k_wind_gemm.  SMC_WIND_EXP_AR1:
+ * W[H][M][G][2] for the H = horizon_max steps: the normals of every step
+ * and sample (those of sample k M + m under the static numbering) go
+ * through the time recursion u(k) = a u(k-1) + sqrt(1 - a^2) v(k), then
+ * through the factor; the factor is linear, so step k's field is the
+ * paper's W(k) plus wind_mean.  W: device, caller-allocated; the context's
+ * normals buffer is the workspace (calls on one context run in stream
+ * order).  wind_mean: host [2]. */
+smc_status smc_k_wind_fields(smc_ctx* ctx, int64_t mpc_step, int32_t iter,
+                             const double* wind_mean, void* W, void* stream);
+
+/* Rollout of P particles under the fields W ([M][G][2], or [H][M][G][2]
+ * for a context with the time-correlated wind: step k reads field k) (Sec. "Trajectory Planning",
  * eq. hor; Sec. "Constraint Handling"; eq. TO_init; Sec. "Particle Costing";
  * eq. avoidance): cost[M][P][N] (double), feas[M][P][N] (uint8).
  * states[N][6] double and k_active[N] int32 are device arrays.

@@ -52,6 +52,9 @@ enum { SMC_FP64 = 0, SMC_FP32 = 1 };
  * gradient of the fuel + time cost (both Metropolis forms act before
  * resampling, with the joint target prod_i W_i) */
 enum { SMC_MOVE_JITTER = 0, SMC_MOVE_RWMH = 1, SMC_MOVE_MALA = 2 };
+/* Wind models: a static squared-exponential field per sample, or the paper's
+ * exponential covariance with its time recursion (one field per step). */
+enum { SMC_WIND_SE = 0, SMC_WIND_EXP_AR1 = 1 };
 
 #define SMC_AC_NPAR 9   /* aircraft parameters per aircraft, see smc_scenario */
 #define SMC_COST_NW 9   /* cost weights, see smc_scenario */
@@ -94,6 +97,19 @@ enum { SMC_MOVE_JITTER = 0, SMC_MOVE_RWMH = 1, SMC_MOVE_MALA = 2 };
  *  kappa (tempering scale: beta_J = kappa floor(3 + 5 e^{0.05 J}),
  *  Sec. "Simulation Setup"), sigma_move (move step in normalised control
  *  units), mala_step, seed (Philox key), scenario_id (Philox stream tag).
+ *  wind_model SMC_WIND_SE: the squared-exponential field above, one static
+ *  field per wind sample and SMC iteration.  SMC_WIND_EXP_AR1 (Sec. "Wind
+ *  Model", eq. cov and the linear Gaussian model after it): covariance
+ *  wind_sigma^2 exp(-wind_beta |dxy|) exp(-wind_gamma |dz|) [1/m], Euclidean
+ *  horizontal distance, the nugget added to the horizontal (nx ny points)
+ *  and vertical (nz levels) Gram matrices, factor Qhat = sigma L_h (x) L_z;
+ *  per sample one field per step k < horizon_max: W(0) = Qhat v(0),
+ *  W(k+1) = a W(k) + sqrt(1 - a^2) Qhat v(k+1), a = exp(-dt / wind_tcorr)
+ *  (wind_tcorr = G_t [s], > 0; infinity freezes the field), v(k) of sample m
+ *  being the normals of sample k M + m; wind_ell is not used.  Limits of
+ *  SMC_WIND_EXP_AR1: n_aircraft <= 20, move not SMC_MOVE_MALA, no
+ *  smc_plant_step, not in the batched form; horizon_max * n_wind * G
+ *  * 2 < 2^31; init factors the (nx ny)^2 horizontal Gram matrix on the host.
  */
 typedef struct {
     int32_t n_aircraft, n_segments, horizon_max, n_particles, n_wind, n_iters;
@@ -116,6 +132,8 @@ typedef struct {
     double kappa, sigma_move, mala_step;
     uint64_t seed;
     int32_t scenario_id;
+    int32_t wind_model;                         /* SMC_WIND_* */
+    double wind_beta, wind_gamma, wind_tcorr;   /* SMC_WIND_EXP_AR1 only */
 } smc_scenario;
 
 /* Diagnostics of one MPC update (optional output).  When requested, device

@@ -60,6 +60,8 @@ class Scenario(C.Structure):
         ("precision", C.c_int32), ("move", C.c_int32),
         ("kappa", C.c_double), ("sigma_move", C.c_double), ("mala_step", C.c_double),
         ("seed", C.c_uint64), ("scenario_id", C.c_int32),
+        ("wind_model", C.c_int32), ("wind_beta", C.c_double), ("wind_gamma", C.c_double),
+        ("wind_tcorr", C.c_double),
     ]
 
 
@@ -132,6 +134,7 @@ _SIGS = {
     "smc_k_wind_normals": (C.c_int, [_VP, C.c_int64, C.c_int32, _VP, _VP]),
     "smc_k_wind_gemm": (C.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "smc_k_wind_factor": (C.c_int, [_VP, _VP, _VP]),
+    "smc_k_wind_fields": (C.c_int, [_VP, C.c_int64, C.c_int32, _VP, _VP, _VP]),
     "smc_k_rollout": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, C.c_int32, _VP, _VP, _VP,
                                 _VP]),
     "smc_k_reduce": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, _VP, _VP, _VP, _VP]),
@@ -288,6 +291,10 @@ def make_scenario_struct(s: dict):
                                              float(s["mala_step"]))
     sc.seed = int(s["seed"]) & 0xFFFFFFFFFFFFFFFF
     sc.scenario_id = int(s.get("scenario_id", 0))
+    sc.wind_model = int(s.get("wind_model", 0))
+    sc.wind_beta = float(s.get("wind_beta", 0.0))
+    sc.wind_gamma = float(s.get("wind_gamma", 0.0))
+    sc.wind_tcorr = float(s.get("wind_tcorr", 0.0))
     return sc, keep
 
 
@@ -437,6 +444,12 @@ def smc_k_wind_gemm(ctx, Z, wind_mean, W, stream=None):
 
 def smc_k_wind_factor(ctx, out, stream=None):
     _check(lib().smc_k_wind_factor(ctx.handle, _ptr(out), _stream(stream)), ctx)
+
+
+def smc_k_wind_fields(ctx, mpc_step, it, wind_mean, W, stream=None):
+    wm_a, p_wm = _hp(wind_mean, np.float64)
+    _check(lib().smc_k_wind_fields(ctx.handle, int(mpc_step), int(it), p_wm, _ptr(W),
+                                   _stream(stream)), ctx)
 
 
 def smc_k_rollout(ctx, u, P, W, states, k_active, horizon, cost, feas, steps=None, stream=None):

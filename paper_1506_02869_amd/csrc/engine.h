@@ -44,6 +44,7 @@ struct RolloutParams {
     double p_run, p_beta, p_chi, p_vs, beta_f;
     double w[9];
     double time_norm, noise_alt, zdot_max;
+    int64_t w_kstride;      // reals between the fields of consecutive steps (0: one static field)
     RollConst<float> cf;    // world-per-lane constants, FP32
     RollConst<double> cd;   // world-per-lane constants, FP64
 };
@@ -51,7 +52,7 @@ struct RolloutParams {
 // Device arrays of one rollout launch.
 struct RolloutArrays {
     const void* u;            // [P][N][S][3] real
-    const void* W;            // [M][G][2] real
+    const void* W;            // [M][G][2] real, or [H][M][G][2] when w_kstride != 0
     const double* states;     // [N][6]
     const int32_t* k_active;  // [N]
     const double* acpar;      // [N][9]
@@ -120,6 +121,11 @@ hipError_t launch_init_particles(int prec, Stream s, int64_t count, void* u,
                                  hipStream_t st);
 hipError_t launch_wind_normals(int prec, Stream s, int G, int M, void* Z,
                                hipStream_t st);
+// Normals of the time-correlated wind model: Z[G][2 H M], column (k M + m, c)
+// holds u(k) = a u(k-1) + b v(k), u(0) = v(0), v(k) the pair of counter
+// (k M + m) G + g; b = sqrt(1 - a^2).
+hipError_t launch_wind_normals_ar1(int prec, Stream s, int G, int M, int H, double a, double b,
+                                   void* Z, hipStream_t st);
 hipError_t launch_kron_expand(int prec, const double* Lx, const double* Ly,
                               const double* Lz, int nx, int ny, int nz,
                               double sigma, void* Lfac, hipStream_t st);
@@ -141,6 +147,9 @@ bool rollout_wm_supported(int N);
 // 1 departure), 0
 hipError_t launch_rollout_wm(int prec, const RolloutParams& p, const RolloutArrays& a,
                              const void* acR, hipStream_t st);
+// The same under one wind field per step (p.w_kstride reals apart).
+hipError_t launch_rollout_wm_tv(int prec, const RolloutParams& p, const RolloutArrays& a,
+                                const void* acR, hipStream_t st);
 // adjoint of the fuel + time cost (sum over wind samples) w.r.t. the
 // normalised controls; partial: chunk partials when M > 64
 bool grad_supported(int H, int S);

@@ -21,6 +21,15 @@ double sample_schedule(int J);
 // positive definite.
 bool axis_factor(int n, double lo, double hi, double ell, double nugget, std::vector<double>& Lo);
 
+// Factors of the exponential covariance (Sec. "Wind Model", eq. cov):
+// Lh = chol(R_h + nugget I) over the nx ny horizontal nodes p = ix ny + iy,
+// R_h[p][q] = exp(-beta |xy_p - xy_q|) (Euclidean), and Lz = chol(R_z +
+// nugget I), R_z[a][b] = exp(-gamma |z_a - z_b|); nodes evenly spaced over
+// the box as for axis_factor.  FP64, row-major; false if not positive
+// definite.
+bool exp_factors(int nx, int ny, int nz, const double box[3], double beta, double gamma,
+                 double nugget, std::vector<double>& Lh, std::vector<double>& Lz);
+
 // Checks one scenario; on failure returns the status and sets msg.
 smc_status validate_scenario(const smc_scenario* s, std::string& msg);
 

@@ -32,6 +32,38 @@ __global__ void k_wind_normals(Stream s, int G, int M, R* Z) {
     normals_at<R>(s, G, g, m, Z + (int64_t)g * (2 * M) + 2 * m);
 }
 
+// Normals of the time-correlated wind model (Sec. "Wind Model", linear
+// Gaussian model): thread per (g, m) runs u(0) = v(0), u(k) = a u(k-1) +
+// b v(k) over the H steps in FP64 registers, v(k) the Box-Muller pair of
+// counter (k M + m) G + g, and stores u(k) in column k M + m.  The factor
+// applied afterwards is linear, so Qhat u(k) follows the paper's recursion
+// W(k) = a W(k-1) + Q v(k) with Q = b Qhat.  Consecutive threads store
+// consecutive pairs of one row.
+template <typename R>
+__global__ void k_wind_normals_ar1(Stream s, int G, int M, int H, double a, double b, R* Z) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)G * M) return;
+    const int m = (int)(t % M);
+    const int g = (int)(t / M);
+    R* row = Z + (int64_t)g * 2 * ((int64_t)H * M);
+    double u0 = 0.0, u1 = 0.0;
+    for (int k = 0; k < H; ++k) {
+        const int64_t col = (int64_t)k * M + m;
+        double z0, z1;
+        normal_pair(draw(s, (uint32_t)(col * G + g)), z0, z1);
+        if (k == 0) {
+            u0 = z0;
+            u1 = z1;
+        } else {
+            const double p0 = a * u0, p1 = a * u1;
+            u0 = p0 + b * z0;
+            u1 = p1 + b * z1;
+        }
+        row[2 * col] = to_real<R>(u0);
+        row[2 * col + 1] = to_real<R>(u1);
+    }
+}
+
 __global__ void k_resample_offsets(Stream s, int N, uint32_t* U) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
@@ -111,6 +143,18 @@ hipError_t launch_wind_normals(int prec, Stream s, int G, int M, void* Z,
     else
         hipLaunchKernelGGL(k_wind_normals<float>, dim3(blocks_for(n, 256)), dim3(256),
                            0, st, s, G, M, (float*)Z);
+    return hipGetLastError();
+}
+
+hipError_t launch_wind_normals_ar1(int prec, Stream s, int G, int M, int H, double a, double b,
+                                   void* Z, hipStream_t st) {
+    const int64_t n = (int64_t)G * M;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_wind_normals_ar1<double>, dim3(blocks_for(n, 256)), dim3(256),
+                           0, st, s, G, M, H, a, b, (double*)Z);
+    else
+        hipLaunchKernelGGL(k_wind_normals_ar1<float>, dim3(blocks_for(n, 256)), dim3(256),
+                           0, st, s, G, M, H, a, b, (float*)Z);
     return hipGetLastError();
 }
 

@@ -22,7 +22,6 @@ k_rollout_wm_batch(const BatchScen* __restrict__ tab, const BatchItem* __restric
     extern __shared__ unsigned char smem_raw[];
     R* uc = reinterpret_cast<R*>(smem_raw);   // [NMAX][3][blockDim.x]
     const int tid = threadIdx.x;
-    const int bd = blockDim.x;
     const int lane = tid & 63;
     // Item fetch without a branch: every lane takes part in the atomic, lane 0
     // adding 1 and the others 0, so lane 0's returned value is the wave's
@@ -59,6 +58,7 @@ k_rollout_wm_batch(const BatchScen* __restrict__ tab, const BatchItem* __restric
         const R* __restrict__ acR = (const R*)sc->acR;
         const int64_t world = (int64_t)item->world0 + lane;
         const unsigned slot = (unsigned)it;
+        constexpr bool kTV = false;
 #include "rollout_wm_body.inc"
     }
 }

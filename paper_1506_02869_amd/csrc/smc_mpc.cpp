@@ -39,6 +39,9 @@ struct smc_ctx {
     double time_norm, noise_alt, kappa, sigma_move, mala_step;
     uint64_t seed;
     int pop_nx, pop_ny, use_noise;
+    int wind_model;         // SMC_WIND_*
+    double war1, bar1;      // time recursion: a = exp(-dt / G_t), b = sqrt(1 - a^2)
+    int Mf;                 // fields per iteration: M (static) or H M (one per step)
     size_t rsz;  // sizeof(real)
     RolloutParams rp;
 
@@ -148,8 +151,24 @@ smc_status validate(const smc_scenario* s) {
     }
     const int64_t G = (int64_t)s->grid_n[0] * s->grid_n[1] * s->grid_n[2];
     if (G > 65536) return fail(nullptr, SMC_EINVAL, "grid has more than 65536 points");
-    if (!(s->wind_sigma >= 0) || !(s->wind_ell > 0) || !(s->wind_nugget >= 0))
+    if (s->wind_model != SMC_WIND_SE && s->wind_model != SMC_WIND_EXP_AR1)
+        return fail(nullptr, SMC_EINVAL, "wind_model must be SMC_WIND_SE or SMC_WIND_EXP_AR1");
+    if (!(s->wind_sigma >= 0) || !(s->wind_nugget >= 0) ||
+        (s->wind_model == SMC_WIND_SE && !(s->wind_ell > 0)))
         return fail(nullptr, SMC_EINVAL, "wind parameters out of range");
+    if (s->wind_model == SMC_WIND_EXP_AR1) {
+        if (!(s->wind_beta > 0) || !(s->wind_gamma > 0) || !(s->wind_tcorr > 0))
+            return fail(nullptr, SMC_EINVAL, "wind_beta, wind_gamma and wind_tcorr must be > 0");
+        if (s->n_aircraft > kWorldLaneMaxN)
+            return fail(nullptr, SMC_EINVAL, "time-correlated wind supports at most %d aircraft",
+                        kWorldLaneMaxN);
+        if (s->move == SMC_MOVE_MALA)
+            return fail(nullptr, SMC_EINVAL, "time-correlated wind does not support the gradient move");
+        if ((int64_t)s->grid_n[0] * s->grid_n[1] > 4096)
+            return fail(nullptr, SMC_EINVAL, "time-correlated wind: at most 4096 horizontal nodes");
+        if ((double)s->horizon_max * s->n_wind * G * 2 >= 2147483648.0)
+            return fail(nullptr, SMC_EINVAL, "time-correlated wind: H M G 2 must be below 2^31");
+    }
     if (!(s->sep_h >= 0) || !(s->sep_v >= 0)) return fail(nullptr, SMC_EINVAL, "separations must be >= 0");
     if (!s->kind || !s->aircraft || !s->targets)
         return fail(nullptr, SMC_EINVAL, "kind, aircraft and targets are required");
@@ -228,6 +247,7 @@ RolloutArrays rollout_arrays(smc_ctx* c, const void* u, const void* W, const dou
 // (or when asked), aircraft-per-lane otherwise.
 hipError_t do_rollout(smc_ctx* c, const RolloutParams& rp, const RolloutArrays& a,
                       hipStream_t st) {
+    if (rp.w_kstride != 0) return launch_rollout_wm_tv(c->prec, rp, a, c->d_acR, st);
     const bool wm = c->layout == 2 || (c->layout == 0 && rollout_wm_supported(c->N));
     if (wm) return launch_rollout_wm(c->prec, rp, a, c->d_acR, st);
     return launch_rollout(c->prec, rp, a, st);
@@ -239,6 +259,15 @@ smc_status check_horizon(smc_ctx* c, int32_t horizon) {
     if (horizon < c->S)
         return fail(c, SMC_EINVAL, "horizon %d shorter than n_segments %d", horizon, c->S);
     return SMC_OK;
+}
+
+// Normals of iteration J for the context's wind model (Sec. "Wind Model"):
+// G x 2 Mf reals, the time recursion applied for the time-correlated model.
+hipError_t wind_normals(smc_ctx* c, int64_t mpc_step, int J, void* Z, hipStream_t st) {
+    const Stream s = make_stream(c->seed, mpc_step, J, P_WIND, c->scen_id);
+    if (c->wind_model == SMC_WIND_EXP_AR1)
+        return launch_wind_normals_ar1(c->prec, s, c->G, c->M, c->Hmax, c->war1, c->bar1, Z, st);
+    return launch_wind_normals(c->prec, s, c->G, c->M, Z, st);
 }
 
 // The SMC loop of one MPC update on device buffers (Alg. 1).
@@ -267,11 +296,10 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     std::vector<int32_t> hflags;
     for (int J = 0; J < c->K; ++J) {
         const double beta = beta_of(c, J);
-        HIP_OK(c, launch_wind_normals(c->prec, make_stream(c->seed, mpc_step, J, P_WIND, c->scen_id),
-                                      c->G, c->M, c->d_Z, st));
+        HIP_OK(c, wind_normals(c, mpc_step, J, c->d_Z, st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_wind[2 * J], st));
         HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G,
-                                   c->M, c->d_W, c->d_wpart, st));
+                                   c->Mf, c->d_W, c->d_wpart, st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_wind[2 * J + 1], st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J], st));
         HIP_OK(c, do_rollout(c, rp,
@@ -458,6 +486,50 @@ bool axis_factor(int n, double lo, double hi, double ell, double nugget, std::ve
     return true;
 }
 
+// Lower Cholesky factor of the n x n matrix K (row-major, FP64), row by row.
+static bool cholesky_rows(int n, const std::vector<double>& K, std::vector<double>& Lo) {
+    Lo.assign((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        const double* Lj = Lo.data() + (size_t)j * n;
+        double s = K[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) s -= Lj[k] * Lj[k];
+        if (!(s > 0.0)) return false;
+        const double d = std::sqrt(s);
+        Lo[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            const double* Li = Lo.data() + (size_t)i * n;
+            double t = K[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= Li[k] * Lj[k];
+            Lo[(size_t)i * n + j] = t / d;
+        }
+    }
+    return true;
+}
+
+bool exp_factors(int nx, int ny, int nz, const double box[3], double beta, double gamma,
+                 double nugget, std::vector<double>& Lh, std::vector<double>& Lz) {
+    auto node = [](int n, double lo, double hi, int a) { return lo + (hi - lo) * a / (n - 1); };
+    const int nh = nx * ny;
+    std::vector<double> K((size_t)nh * nh);
+    for (int p = 0; p < nh; ++p) {
+        const double xp = node(nx, -0.5 * box[0], 0.5 * box[0], p / ny);
+        const double yp = node(ny, -0.5 * box[1], 0.5 * box[1], p % ny);
+        for (int q = 0; q < nh; ++q) {
+            const double dx = xp - node(nx, -0.5 * box[0], 0.5 * box[0], q / ny);
+            const double dy = yp - node(ny, -0.5 * box[1], 0.5 * box[1], q % ny);
+            K[(size_t)p * nh + q] = std::exp(-beta * std::sqrt(dx * dx + dy * dy)) + (p == q ? nugget : 0.0);
+        }
+    }
+    if (!cholesky_rows(nh, K, Lh)) return false;
+    std::vector<double> Kz((size_t)nz * nz);
+    for (int a = 0; a < nz; ++a)
+        for (int b = 0; b < nz; ++b)
+            Kz[(size_t)a * nz + b] =
+                std::exp(-gamma * std::fabs(node(nz, 0.0, box[2], a) - node(nz, 0.0, box[2], b))) +
+                (a == b ? nugget : 0.0);
+    return cholesky_rows(nz, Kz, Lz);
+}
+
 smc_status validate_scenario(const smc_scenario* s, std::string& msg) {
     const smc_status r = validate(s);
     if (r) msg = g_init_error;
@@ -602,14 +674,32 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     c->pop_nx = s->popdense ? s->pop_n[0] : 0;
     c->pop_ny = s->popdense ? s->pop_n[1] : 0;
     c->rsz = c->prec == SMC_FP64 ? sizeof(double) : sizeof(float);
+    c->wind_model = s->wind_model;
+    c->war1 = c->wind_model == SMC_WIND_EXP_AR1 ? std::exp(-s->dt / s->wind_tcorr) : 0.0;
+    c->bar1 = std::sqrt(std::max(0.0, 1.0 - c->war1 * c->war1));
+    c->Mf = c->wind_model == SMC_WIND_EXP_AR1 ? c->Hmax * c->M : c->M;
 
     host::fill_rollout_params(s, c->rp);
+    c->rp.w_kstride = c->wind_model == SMC_WIND_EXP_AR1 ? (int64_t)c->M * c->G * 2 : 0;
 
-    // wind factor per axis (FP64, host)
+    // wind factor (FP64, host): per axis (squared-exponential), or the
+    // horizontal and vertical factors of the exponential covariance, handed
+    // to the Kronecker expansion as (nx ny, 1, nz) axes
     std::vector<double> Lx, Ly, Lz;
-    if (!host::axis_factor(c->nx, -0.5 * c->box[0], 0.5 * c->box[0], c->ell, c->nugget, Lx) ||
-        !host::axis_factor(c->ny, -0.5 * c->box[1], 0.5 * c->box[1], c->ell, c->nugget, Ly) ||
-        !host::axis_factor(c->nz, 0.0, c->box[2], c->ell, c->nugget, Lz)) {
+    int fx = c->nx, fy = c->ny;
+    bool pd;
+    if (c->wind_model == SMC_WIND_EXP_AR1) {
+        fx = c->nx * c->ny;
+        fy = 1;
+        Ly.assign(1, 1.0);
+        pd = host::exp_factors(c->nx, c->ny, c->nz, c->box, s->wind_beta, s->wind_gamma, c->nugget,
+                               Lx, Lz);
+    } else {
+        pd = host::axis_factor(c->nx, -0.5 * c->box[0], 0.5 * c->box[0], c->ell, c->nugget, Lx) &&
+             host::axis_factor(c->ny, -0.5 * c->box[1], 0.5 * c->box[1], c->ell, c->nugget, Ly) &&
+             host::axis_factor(c->nz, 0.0, c->box[2], c->ell, c->nugget, Lz);
+    }
+    if (!pd) {
         g_init_error = "wind covariance not positive definite (raise wind_nugget)";
         delete c;
         return SMC_ENOTSPD;
@@ -639,13 +729,15 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
                 fail(c, SMC_EDEVICE, "hipEventCreate failed");
                 return bail(SMC_EDEVICE);
             }
-    const size_t N = c->N, L = c->L, M = c->M, G = c->G, D = (size_t)c->S * 3;
+    const size_t N = c->N, L = c->L, M = c->M, G = c->G, D = (size_t)c->S * 3, Mf = c->Mf;
     double *d_Lx = nullptr, *d_Ly = nullptr, *d_Lz = nullptr;
     if ((st = dalloc_t(c, &c->d_acpar, N * SMC_AC_NPAR)) || (st = dalloc_t(c, &c->d_targets, N * 4)) ||
         (st = dalloc_t(c, &c->d_kind, N)) ||
-        (st = dalloc(c, &c->d_Lfac, G * G * c->rsz)) || (st = dalloc(c, &c->d_Z, G * 2 * M * c->rsz)) ||
-        (st = dalloc(c, &c->d_W, M * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_Wt, M * G * 2 * c->rsz)) ||
-        (st = dalloc(c, &c->d_wpart, std::max<size_t>(wind_gemm_part_elems((int)G, (int)M), 1) * c->rsz)) || (st = dalloc(c, &c->d_u, L * N * D * c->rsz)) ||
+        (st = dalloc(c, &c->d_Lfac, G * G * c->rsz)) || (st = dalloc(c, &c->d_Z, G * 2 * Mf * c->rsz)) ||
+        (st = dalloc(c, &c->d_W, Mf * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_Wt, M * G * 2 * c->rsz)) ||
+        (st = dalloc(c, &c->d_wpart, std::max<size_t>({wind_gemm_part_elems((int)G, (int)M),
+                                                       wind_gemm_part_elems((int)G, (int)Mf), 1}) * c->rsz)) ||
+        (st = dalloc(c, &c->d_u, L * N * D * c->rsz)) ||
         (st = dalloc(c, &c->d_u2, L * N * D * c->rsz)) ||
         (st = dalloc(c, &c->d_up, (c->move != SMC_MOVE_JITTER ? L : 1) * N * D * c->rsz)) ||
         (st = dalloc_t(c, &c->d_cost, M * L * N)) || (st = dalloc_t(c, &c->d_feas, M * L * N)) ||
@@ -659,7 +751,7 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         (st = dalloc_t(c, &c->d_states, N * 6)) || (st = dalloc_t(c, &c->d_kact, N)) ||
         (st = dalloc_t(c, &c->d_ctrl_out, N * D)) || (st = dalloc_t(c, &c->d_cost_out, 1 + N)) ||
         (st = dalloc_t(c, &c->d_plant_states, N * 6)) || (st = dalloc_t(c, &c->d_plant_i32, 2 * N)) ||
-        (st = dalloc_t(c, &d_Lx, (size_t)c->nx * c->nx)) || (st = dalloc_t(c, &d_Ly, (size_t)c->ny * c->ny)) ||
+        (st = dalloc_t(c, &d_Lx, (size_t)fx * fx)) || (st = dalloc_t(c, &d_Ly, (size_t)fy * fy)) ||
         (st = dalloc_t(c, &d_Lz, (size_t)c->nz * c->nz)))
         return bail(st);
     if ((st = dalloc(c, &c->d_acR, N * kAcR * c->rsz))) return bail(st);
@@ -699,7 +791,7 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     INIT_HIP(hipMemcpy(d_Lx, Lx.data(), Lx.size() * sizeof(double), hipMemcpyHostToDevice));
     INIT_HIP(hipMemcpy(d_Ly, Ly.data(), Ly.size() * sizeof(double), hipMemcpyHostToDevice));
     INIT_HIP(hipMemcpy(d_Lz, Lz.data(), Lz.size() * sizeof(double), hipMemcpyHostToDevice));
-    INIT_HIP(launch_kron_expand(c->prec, d_Lx, d_Ly, d_Lz, c->nx, c->ny, c->nz, c->sigma, c->d_Lfac,
+    INIT_HIP(launch_kron_expand(c->prec, d_Lx, d_Ly, d_Lz, fx, fy, c->nz, c->sigma, c->d_Lfac,
                                 c->stream));
     INIT_HIP(hipStreamSynchronize(c->stream));
 #undef INIT_HIP
@@ -752,6 +844,8 @@ smc_status smc_plant_step(smc_ctx* c, int64_t mpc_step, int32_t plant_iter, cons
     if (vs) return vs;
     if (n_steps < 1 || n_steps > horizon) return fail(c, SMC_EINVAL, "n_steps must be in [1, horizon]");
     if (plant_iter < 0) return fail(c, SMC_EINVAL, "plant_iter must be >= 0");
+    if (c->wind_model != SMC_WIND_SE)
+        return fail(c, SMC_EINVAL, "smc_plant_step: static wind model only");
     hipStream_t st = c->stream;
     const int N = c->N;
     HIP_OK(c, hipMemcpyAsync(c->d_states, states, sizeof(double) * N * 6, hipMemcpyHostToDevice, st));
@@ -801,9 +895,8 @@ smc_status smc_eval_cost(smc_ctx* c, int64_t mpc_step, int32_t iter, const doubl
     }
     HIP_OK(c, hipMemcpyAsync(c->d_states, states, sizeof(double) * c->N * 6, hipMemcpyHostToDevice, st));
     HIP_OK(c, hipMemcpyAsync(c->d_kact, k_active, sizeof(int32_t) * c->N, hipMemcpyHostToDevice, st));
-    HIP_OK(c, launch_wind_normals(c->prec, make_stream(c->seed, mpc_step, iter, P_WIND, c->scen_id),
-                                  c->G, c->M, c->d_Z, st));
-    HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G, c->M,
+    HIP_OK(c, wind_normals(c, mpc_step, iter, c->d_Z, st));
+    HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G, c->Mf,
                                c->d_W, c->d_wpart, st));
     RolloutParams rp = c->rp;
     rp.H = horizon;
@@ -859,6 +952,16 @@ smc_status smc_k_wind_factor(smc_ctx* c, void* out, void* stream) {
     if (!c || !out) return fail(c, SMC_EINVAL, "smc_k_wind_factor: bad arguments");
     HIP_OK(c, hipMemcpyAsync(out, c->d_Lfac, (size_t)c->G * c->G * c->rsz, hipMemcpyDeviceToDevice,
                              pick(c, stream)));
+    return SMC_OK;
+}
+
+smc_status smc_k_wind_fields(smc_ctx* c, int64_t mpc_step, int32_t iter, const double* wind_mean,
+                             void* W, void* stream) {
+    if (!c || !W || !wind_mean || iter < 0) return fail(c, SMC_EINVAL, "smc_k_wind_fields: bad arguments");
+    hipStream_t st = pick(c, stream);
+    HIP_OK(c, wind_normals(c, mpc_step, iter, c->d_Z, st));
+    HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G, c->Mf, W,
+                               c->d_wpart, st));
     return SMC_OK;
 }
 
@@ -946,6 +1049,8 @@ smc_status smc_k_rollout_grad(smc_ctx* c, const void* u, int32_t P, const void* 
                               double* grad, void* stream) {
     if (!c || !u || !W || !states || !k_active || !grad || P < 1)
         return fail(c, SMC_EINVAL, "smc_k_rollout_grad: bad arguments");
+    if (c->wind_model != SMC_WIND_SE)
+        return fail(c, SMC_EINVAL, "smc_k_rollout_grad: static wind model only");
     smc_status vs = check_horizon(c, horizon);
     if (vs) return vs;
     if (!grad_supported(horizon, c->S))
@@ -994,6 +1099,8 @@ smc_status smc_set_rollout_layout(smc_ctx* c, int32_t layout) {
     if (!c || layout < 0 || layout > 2) return fail(c, SMC_EINVAL, "smc_set_rollout_layout: bad arguments");
     if (layout == 2 && !rollout_wm_supported(c->N))
         return fail(c, SMC_EINVAL, "world-per-lane rollout supports at most %d aircraft", kWorldLaneMaxN);
+    if (layout == 1 && c->wind_model != SMC_WIND_SE)
+        return fail(c, SMC_EINVAL, "time-correlated wind runs the world-per-lane rollout only");
     c->layout = layout;
     return SMC_OK;
 }

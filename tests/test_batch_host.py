@@ -93,3 +93,24 @@ def test_tuning_cache_roundtrip(tmp_path):
     assert smc.load_tuning(path, "bad") is None
     tt = smc.BatchTuning.from_dict(t)
     assert tt.as_dict() == t
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(move="mala"), "gradient move"),
+    (dict(n_arr=12, n_dep=9), "at most 20 aircraft"),
+    (dict(wind_tcorr=0.0), "wind_tcorr"),
+    (dict(grid=(65, 64, 2)), "4096 horizontal nodes"),
+])
+def test_time_correlated_wind_limits_are_checked_on_the_host(change, msg):
+    """Scenario checks of the paper's wind model run before any device work."""
+    s = _tiny(3, wind_model="ar1", **change)
+    with pytest.raises(smc.SmcError) as e:
+        smc.smc_mpc_init(s)
+    assert msg in str(e.value)
+    bad = dict(_tiny(4, wind_model="ar1"))
+    bad["wind_beta"] = -1.0
+    with pytest.raises(smc.SmcError):
+        smc.smc_mpc_init(bad)
+    with pytest.raises(smc.SmcError) as e:
+        smc.smc_batch_init([_tiny(1), _tiny(2, wind_model="ar1")])
+    assert "static wind model" in str(e.value)
