@@ -64,6 +64,11 @@ WORKLOADS = {
 }
 
 
+AR1_DESC = ("; the paper's wind model: exponential covariance (beta 1.6e-6, gamma 1.5e-5 1/m, "
+            "sigma 5 m/s), time recursion with G_t = 1800 s, one field per step of the "
+            "horizon for every sample (H M fields per SMC iteration)")
+
+
 def _src_hash(*names):
     h = hashlib.sha256()
     for n in names:
@@ -326,6 +331,9 @@ def main():
     ap.add_argument("--compare-iters", default="5,10,20,40,80,160")
     ap.add_argument("--rolling", type=int, default=0,
                     help="run this many receding-horizon updates (solve + plant) instead")
+    ap.add_argument("--wind", choices=["se", "ar1"], default="se",
+                    help="wind model: static squared-exponential fields (default) or the "
+                         "paper's exponential covariance with its time recursion (c1, c2)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -354,7 +362,14 @@ def main():
     desc, key = WORKLOADS[args.workload]
     if key == "c3":
         return bench_batch(args, desc)
-    scen = getattr(synth, key)()
+    ar1 = args.wind == "ar1"
+    if ar1:
+        if key not in ("c1", "c2"):
+            print("--wind ar1: the time-correlated wind runs with up to 20 aircraft and "
+                  "random-walk or jitter moves (workloads c1, c2)", file=sys.stderr)
+            sys.exit(2)
+        desc += (AR1_DESC)
+    scen = getattr(synth, key)(**({"wind_model": "ar1"} if ar1 else {}))
     torch.cuda.set_device(0)
     ctx = smc.smc_mpc_init(scen)
     dev = torch.device("cuda")
@@ -409,15 +424,18 @@ def main():
     kname, ksrc = ((
         "k_rollout_wm", ("kernels_rollout_wm.hip", "rollout_wm_body.inc", "rollout_math.h"))
         if world_lane else ("k_rollout", ("kernels_rollout.hip", "rollout_math.h")))
+    if ar1:
+        kname = "k_rollout_wm_tv"
     roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 3),
             "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": traffic_for(ksrc, args.workload) if world_lane else None,
+            "traffic": traffic_for(ksrc, args.workload) if world_lane and not ar1 else None,
             "ms_per_launch": round(ms_roll, 4),
             "aircraft_steps_per_launch": int(as_per_launch),
             "pair_tests_per_launch": int(pt_per_launch),
             "flops_per_launch": flops_launch}
     G = int(np.prod(scen["grid"]))
-    gemm_flops = float(G) * (G + 1) * 2 * scen["M"]      # triangular factor x 2M columns
+    # triangular factor x 2M columns (x H steps under the time-correlated wind)
+    gemm_flops = float(G) * (G + 1) * 2 * scen["M"] * (scen["H"] if ar1 else 1)
     gemm_ach = gemm_flops / (ms_wind * 1e-3) / 1e12
     gpeak = PEAK_FP64_MFMA_TFLOPS if fp64 else PEAK_FP32_MFMA_TFLOPS
     wind_roof = {"kernel": "k_wind_gemm", "bound": "mfma", "achieved": round(gemm_ach, 3),
@@ -441,7 +459,7 @@ def main():
                      "ms_per_mpc_step_in_adjoint": round(ms_grad * info0["grad_launches"], 2)}
 
     check = None
-    if not args.no_check:
+    if not args.no_check and not ar1:
         # re-score the returned controls with the FP64 oracle on the last
         # iteration's wind fields
         from oracle import smc as osmc
@@ -455,7 +473,7 @@ def main():
                  "oracle_feasible": bool(rf.all()), "status": int(status.cpu()[0])}
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not ar1:
         cpu = cpu_baseline(scen, args.cpu_particles)
 
     out = {"metric": METRIC, "value": value, "unit": "aircraft-steps/s", "n_gpus": 1,
