@@ -434,8 +434,13 @@ def main():
             "pair_tests_per_launch": int(pt_per_launch),
             "flops_per_launch": flops_launch}
     G = int(np.prod(scen["grid"]))
-    # triangular factor x 2M columns (x H steps under the time-correlated wind)
-    gemm_flops = float(G) * (G + 1) * 2 * scen["M"] * (scen["H"] if ar1 else 1)
+    # triangular factor x 2M columns; under the time-correlated wind the
+    # horizontal factor (nx ny rows) x 2 H M nz columns
+    if ar1:
+        nh = int(scen["grid"][0]) * int(scen["grid"][1])
+        gemm_flops = float(nh) * (nh + 1) * 2 * scen["M"] * scen["H"] * int(scen["grid"][2])
+    else:
+        gemm_flops = float(G) * (G + 1) * 2 * scen["M"]
     gemm_ach = gemm_flops / (ms_wind * 1e-3) / 1e12
     gpeak = PEAK_FP64_MFMA_TFLOPS if fp64 else PEAK_FP32_MFMA_TFLOPS
     wind_roof = {"kernel": "k_wind_gemm", "bound": "mfma", "achieved": round(gemm_ach, 3),

@@ -126,6 +126,15 @@ hipError_t launch_wind_normals(int prec, Stream s, int G, int M, void* Z,
 // (k M + m) G + g; b = sqrt(1 - a^2).
 hipError_t launch_wind_normals_ar1(int prec, Stream s, int G, int M, int H, double a, double b,
                                    void* Z, hipStream_t st);
+// Time-correlated wind with Qhat = sigma L_h (x) L_z: Y[h][col][iz] =
+// sum_j Lz[iz][j] U[h nz + j][col] over the 2 M columns (nz <= 16), then
+// W[m][h nz + iz][c] = w_c + sum_h' (sigma L_h)[h][h'] Y[h'][2 m + c][iz]
+// (the triangular MFMA GEMM with nh rows and 2 M nz columns).
+hipError_t launch_wind_levels(int prec, const void* U, const double* Lz, int nh, int nz, int M,
+                              void* Y, hipStream_t st);
+hipError_t launch_wind_gemm_levels(int prec, const void* Lh, const void* Y, double wm0,
+                                   double wm1, int nh, int nz, int M, void* W, void* part,
+                                   hipStream_t st);
 hipError_t launch_kron_expand(int prec, const double* Lx, const double* Ly,
                               const double* Lz, int nx, int ny, int nz,
                               double sigma, void* Lfac, hipStream_t st);

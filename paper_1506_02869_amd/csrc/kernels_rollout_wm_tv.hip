@@ -16,7 +16,17 @@ k_rollout_wm_tv(const RolloutParams p, const RolloutArrays a, const R* __restric
     R* uc = reinterpret_cast<R*>(smem_raw);   // [N][3][blockDim.x]
     const int tid = threadIdx.x;
     const int bd = blockDim.x;
-    const int64_t world = (int64_t)blockIdx.x * bd + tid;
+    // Workgroups are dispatched round-robin over the 8 XCDs, each with its
+    // own L2; every step reads fresh fields, so each XCD takes a contiguous
+    // range of worlds (whole wind samples) and a step's field of a sample is
+    // fetched into one L2.  Block b runs on XCD b % 8 as its (b / 8)-th
+    // block; the map onto logical blocks is a bijection for any grid size.
+    const unsigned lb = [] {
+        const unsigned nb = gridDim.x, b = blockIdx.x;
+        const unsigned q = nb / 8, r = nb % 8, xcd = b % 8;
+        return xcd * q + min(xcd, r) + b / 8;
+    }();
+    const int64_t world = (int64_t)lb * bd + tid;
     const unsigned slot = blockIdx.x;
 #include "rollout_wm_body.inc"
 }

@@ -158,13 +158,18 @@ __device__ __forceinline__ void gemm_range(const T* __restrict__ A, const T* __r
 
 // W element (g, col) with col = 2 m + c: the mean (wm0, wm1), or
 // wmean[2 (m / mper) + c] per group of mper samples, plus the product.
+// Column col of row g is (field column jj, level iz) = (col / nzo, col % nzo),
+// jj = 2 m + c, and lands at W[m][g nzo + iz][c]: nzo = 1 for the dense
+// factor's product; nzo = nz when the rows are horizontal nodes and each
+// field column carries its nz levels (the horizontal factor's product).
 template <typename T>
-__device__ __forceinline__ void gemm_put(int G, int g, int col, double wm0, double wm1,
+__device__ __forceinline__ void gemm_put(int G, int g, int col, int nzo, double wm0, double wm1,
                                          const double* __restrict__ wmean, int mper, T v,
                                          T* __restrict__ W) {
-    const int m = col >> 1, c = col & 1;
+    const int jj = nzo == 1 ? col : col / nzo, iz = col - jj * nzo;   // nzo is uniform
+    const int m = jj >> 1, c = jj & 1;
     const double base = wmean ? wmean[2 * (m / mper) + c] : (c ? wm1 : wm0);
-    W[((int64_t)m * G + g) * 2 + c] = (T)(base + (double)v);
+    W[(((int64_t)m * G + g) * nzo + iz) * 2 + c] = (T)(base + (double)v);
 }
 
 // The K extent of row block rb is split into chunks of GK_CHUNK (the factor
@@ -184,7 +189,7 @@ __host__ __device__ inline int gemm_nchunks(int G, int rb) {
 // the per-chunk form), then the epilogue.
 template <typename T>
 __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* __restrict__ Z,
-                                              int G, int NC, int rb, int cb, double wm0,
+                                              int G, int NC, int nzo, int rb, int cb, double wm0,
                                               double wm1, const double* __restrict__ wmean,
                                               int mper, T* __restrict__ W, T* As, T* Bs) {
     typedef typename Mfma<T>::acc_t acc_t;
@@ -230,8 +235,8 @@ __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* 
         const int g = row0 + wr + Mfma<T>::row(lane, r);
         if (g >= G) continue;
         const int c0 = col0 + wc + (lane & 15), c1 = c0 + 16;
-        if (c0 < NC) gemm_put<T>(G, g, c0, wm0, wm1, wmean, mper, tot0[r], W);
-        if (c1 < NC) gemm_put<T>(G, g, c1, wm0, wm1, wmean, mper, tot1[r], W);
+        if (c0 < NC) gemm_put<T>(G, g, c0, nzo, wm0, wm1, wmean, mper, tot0[r], W);
+        if (c1 < NC) gemm_put<T>(G, g, c1, nzo, wm0, wm1, wmean, mper, tot1[r], W);
     }
 }
 
@@ -240,7 +245,7 @@ __device__ __forceinline__ void gemm_rowblock(const T* __restrict__ A, const T* 
 template <typename T>
 __global__ void __launch_bounds__(256) k_wind_gemm(const T* __restrict__ A,
                                                    const T* __restrict__ Z, int G, int NC,
-                                                   double wm0, double wm1,
+                                                   int nzo, double wm0, double wm1,
                                                    const double* __restrict__ wmean, int mper,
                                                    T* __restrict__ W) {
     __shared__ T As[2 * GB_K * GA_LD];
@@ -249,10 +254,10 @@ __global__ void __launch_bounds__(256) k_wind_gemm(const T* __restrict__ A,
     const int rb = blockIdx.x;
     const int rb2 = R - 1 - rb;
     const int cb = blockIdx.y;
-    gemm_rowblock<T>(A, Z, G, NC, rb2, cb, wm0, wm1, wmean, mper, W, As, Bs);   // heavy first
+    gemm_rowblock<T>(A, Z, G, NC, nzo, rb2, cb, wm0, wm1, wmean, mper, W, As, Bs);   // heavy first
     if (rb2 != rb) {
         __syncthreads();
-        gemm_rowblock<T>(A, Z, G, NC, rb, cb, wm0, wm1, wmean, mper, W, As, Bs);
+        gemm_rowblock<T>(A, Z, G, NC, nzo, rb, cb, wm0, wm1, wmean, mper, W, As, Bs);
     }
 }
 
@@ -290,7 +295,7 @@ __global__ void __launch_bounds__(256) k_wind_gemm_part(const T* __restrict__ A,
 // Sum of a row's chunk products in chunk order, then the epilogue.
 template <typename T>
 __global__ void __launch_bounds__(256) k_wind_gemm_sum(const T* __restrict__ part, int G, int NC,
-                                                       double wm0, double wm1,
+                                                       int nzo, double wm0, double wm1,
                                                        const double* __restrict__ wmean,
                                                        int mper, T* __restrict__ W) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -299,7 +304,34 @@ __global__ void __launch_bounds__(256) k_wind_gemm_sum(const T* __restrict__ par
     const int nch = gemm_nchunks(G, g / GB_M);
     T tot = 0;
     for (int j = 0; j < nch; ++j) tot += part[(int64_t)j * G * NC + e];
-    gemm_put<T>(G, g, col, wm0, wm1, wmean, mper, tot, W);
+    gemm_put<T>(G, g, col, nzo, wm0, wm1, wmean, mper, tot, W);
+}
+
+// Levels of the time-correlated wind: the vertical factor of Qhat = sigma
+// L_h (x) L_z applied along the nz levels of each horizontal node, and the
+// columns regrouped level-fastest for the horizontal factor's product:
+// Y[h][col][iz] = sum_{j <= iz} Lz[iz][j] U[h nz + j][col] (FP64 sums).
+// Thread per (h, col); the reads of consecutive columns and the writes of a
+// thread's nz levels are contiguous.
+constexpr int kMaxWindLevels = 16;
+template <typename T>
+__global__ void k_wind_levels(const T* __restrict__ U, const double* __restrict__ Lz, int nh,
+                              int nz, int NC, T* __restrict__ Y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nh * NC) return;
+    const int h = (int)(t / NC), col = (int)(t % NC);
+    const T* u = U + (int64_t)h * nz * NC + col;
+    double uv[kMaxWindLevels];
+#pragma unroll
+    for (int j = 0; j < kMaxWindLevels; ++j) uv[j] = j < nz ? (double)u[(int64_t)j * NC] : 0.0;
+    T* y = Y + ((int64_t)h * NC + col) * nz;
+    for (int iz = 0; iz < nz; ++iz) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < kMaxWindLevels; ++j)
+            if (j <= iz) acc += Lz[iz * nz + j] * uv[j];
+        y[iz] = (T)acc;
+    }
 }
 
 hipError_t launch_kron_expand(int prec, const double* Lx, const double* Ly,
@@ -326,8 +358,8 @@ size_t wind_gemm_part_elems(int G, int M) {
 }
 
 static hipError_t wind_gemm(int prec, const void* Lfac, const void* Z, double wm0, double wm1,
-                            const double* wmean, int mper, int G, int M, void* W, void* part,
-                            hipStream_t st) {
+                            const double* wmean, int mper, int G, int M, int nzo, void* W,
+                            void* part, hipStream_t st) {
     const int NC = 2 * M;
     const int R = (G + GB_M - 1) / GB_M;
     const int ncb = (NC + GB_N - 1) / GB_N;
@@ -340,36 +372,59 @@ static hipError_t wind_gemm(int prec, const void* Lfac, const void* Z, double wm
             hipLaunchKernelGGL(k_wind_gemm_part<double>, grid, dim3(256), 0, st,
                                (const double*)Lfac, (const double*)Z, G, NC, (double*)part);
             hipLaunchKernelGGL(k_wind_gemm_sum<double>, dim3(sblocks), dim3(256), 0, st,
-                               (const double*)part, G, NC, wm0, wm1, wmean, mper, (double*)W);
+                               (const double*)part, G, NC, nzo, wm0, wm1, wmean, mper,
+                               (double*)W);
         } else {
             hipLaunchKernelGGL(k_wind_gemm_part<float>, grid, dim3(256), 0, st,
                                (const float*)Lfac, (const float*)Z, G, NC, (float*)part);
             hipLaunchKernelGGL(k_wind_gemm_sum<float>, dim3(sblocks), dim3(256), 0, st,
-                               (const float*)part, G, NC, wm0, wm1, wmean, mper, (float*)W);
+                               (const float*)part, G, NC, nzo, wm0, wm1, wmean, mper,
+                               (float*)W);
         }
         return hipGetLastError();
     }
     dim3 grid((unsigned)((R + 1) / 2), (unsigned)ncb);
     if (prec == 0)
         hipLaunchKernelGGL(k_wind_gemm<double>, grid, dim3(256), 0, st,
-                           (const double*)Lfac, (const double*)Z, G, NC, wm0, wm1, wmean,
+                           (const double*)Lfac, (const double*)Z, G, NC, nzo, wm0, wm1, wmean,
                            mper, (double*)W);
     else
         hipLaunchKernelGGL(k_wind_gemm<float>, grid, dim3(256), 0, st, (const float*)Lfac,
-                           (const float*)Z, G, NC, wm0, wm1, wmean, mper, (float*)W);
+                           (const float*)Z, G, NC, nzo, wm0, wm1, wmean, mper, (float*)W);
     return hipGetLastError();
 }
 
 hipError_t launch_wind_gemm(int prec, const void* Lfac, const void* Z, double wm0,
                             double wm1, int G, int M, void* W, void* part, hipStream_t st) {
-    return wind_gemm(prec, Lfac, Z, wm0, wm1, nullptr, 1, G, M, W, part, st);
+    return wind_gemm(prec, Lfac, Z, wm0, wm1, nullptr, 1, G, M, 1, W, part, st);
+}
+
+hipError_t launch_wind_levels(int prec, const void* U, const double* Lz, int nh, int nz, int M,
+                              void* Y, hipStream_t st) {
+    if (nz < 1 || nz > kMaxWindLevels) return hipErrorInvalidValue;
+    const int NC = 2 * M;
+    const int64_t n = (int64_t)nh * NC;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_wind_levels<double>, dim3(blocks), dim3(256), 0, st,
+                           (const double*)U, Lz, nh, nz, NC, (double*)Y);
+    else
+        hipLaunchKernelGGL(k_wind_levels<float>, dim3(blocks), dim3(256), 0, st,
+                           (const float*)U, Lz, nh, nz, NC, (float*)Y);
+    return hipGetLastError();
+}
+
+hipError_t launch_wind_gemm_levels(int prec, const void* Lh, const void* Y, double wm0,
+                                   double wm1, int nh, int nz, int M, void* W, void* part,
+                                   hipStream_t st) {
+    return wind_gemm(prec, Lh, Y, wm0, wm1, nullptr, 1, nh, M * nz, nz, W, part, st);
 }
 
 hipError_t launch_wind_gemm_grouped(int prec, const void* Lfac, const void* Z,
                                     const double* wmean, int mper, int G, int M, void* W,
                                     void* part, hipStream_t st) {
     if (!wmean || mper < 1) return hipErrorInvalidValue;
-    return wind_gemm(prec, Lfac, Z, 0.0, 0.0, wmean, mper, G, M, W, part, st);
+    return wind_gemm(prec, Lfac, Z, 0.0, 0.0, wmean, mper, G, M, 1, W, part, st);
 }
 
 }  // namespace smc

@@ -60,6 +60,11 @@ struct smc_ctx {
     void* d_Lfac = nullptr;
     void *d_Z = nullptr, *d_W = nullptr, *d_Wt = nullptr;
     void* d_wpart = nullptr;   // wind GEMM chunk products (few-tile shapes)
+    // time-correlated wind: sigma L_h [nh][nh] real, L_z [nz][nz] double, the
+    // level-mixed normals Y [nh][2 Mf][nz] real
+    void* d_Lh = nullptr;
+    double* d_Lzd = nullptr;
+    void* d_Y = nullptr;
     void *d_u = nullptr, *d_u2 = nullptr, *d_up = nullptr;
     double* d_cost = nullptr;
     uint8_t* d_feas = nullptr;
@@ -166,6 +171,8 @@ smc_status validate(const smc_scenario* s) {
             return fail(nullptr, SMC_EINVAL, "time-correlated wind does not support the gradient move");
         if ((int64_t)s->grid_n[0] * s->grid_n[1] > 4096)
             return fail(nullptr, SMC_EINVAL, "time-correlated wind: at most 4096 horizontal nodes");
+        if (s->grid_n[2] > 16)
+            return fail(nullptr, SMC_EINVAL, "time-correlated wind: at most 16 levels");
         if ((double)s->horizon_max * s->n_wind * G * 2 >= 2147483648.0)
             return fail(nullptr, SMC_EINVAL, "time-correlated wind: H M G 2 must be below 2^31");
     }
@@ -262,12 +269,26 @@ smc_status check_horizon(smc_ctx* c, int32_t horizon) {
 }
 
 // Normals of iteration J for the context's wind model (Sec. "Wind Model"):
-// G x 2 Mf reals, the time recursion applied for the time-correlated model.
-hipError_t wind_normals(smc_ctx* c, int64_t mpc_step, int J, void* Z, hipStream_t st) {
+// G x 2 M reals in d_Z (static); for the time-correlated model the time
+// recursion over the H steps (d_Z, G x 2 H M), then the vertical factor
+// along the levels (d_Y).
+hipError_t wind_normals(smc_ctx* c, int64_t mpc_step, int J, hipStream_t st) {
     const Stream s = make_stream(c->seed, mpc_step, J, P_WIND, c->scen_id);
+    if (c->wind_model != SMC_WIND_EXP_AR1) return launch_wind_normals(c->prec, s, c->G, c->M, c->d_Z, st);
+    hipError_t e = launch_wind_normals_ar1(c->prec, s, c->G, c->M, c->Hmax, c->war1, c->bar1,
+                                           c->d_Z, st);
+    if (e != hipSuccess) return e;
+    return launch_wind_levels(c->prec, c->d_Z, c->d_Lzd, c->nx * c->ny, c->nz, c->Mf, c->d_Y, st);
+}
+
+// The fields from the normals: the dense factor's product (static), or the
+// horizontal factor's product over the level-mixed normals.
+hipError_t wind_fields_gemm(smc_ctx* c, const double* wind_mean, void* W, hipStream_t st) {
     if (c->wind_model == SMC_WIND_EXP_AR1)
-        return launch_wind_normals_ar1(c->prec, s, c->G, c->M, c->Hmax, c->war1, c->bar1, Z, st);
-    return launch_wind_normals(c->prec, s, c->G, c->M, Z, st);
+        return launch_wind_gemm_levels(c->prec, c->d_Lh, c->d_Y, wind_mean[0], wind_mean[1],
+                                       c->nx * c->ny, c->nz, c->Mf, W, c->d_wpart, st);
+    return launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G, c->M, W,
+                            c->d_wpart, st);
 }
 
 // The SMC loop of one MPC update on device buffers (Alg. 1).
@@ -296,10 +317,9 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     std::vector<int32_t> hflags;
     for (int J = 0; J < c->K; ++J) {
         const double beta = beta_of(c, J);
-        HIP_OK(c, wind_normals(c, mpc_step, J, c->d_Z, st));
+        HIP_OK(c, wind_normals(c, mpc_step, J, st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_wind[2 * J], st));
-        HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G,
-                                   c->Mf, c->d_W, c->d_wpart, st));
+        HIP_OK(c, wind_fields_gemm(c, wind_mean, c->d_W, st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_wind[2 * J + 1], st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J], st));
         HIP_OK(c, do_rollout(c, rp,
@@ -736,7 +756,9 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         (st = dalloc(c, &c->d_Lfac, G * G * c->rsz)) || (st = dalloc(c, &c->d_Z, G * 2 * Mf * c->rsz)) ||
         (st = dalloc(c, &c->d_W, Mf * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_Wt, M * G * 2 * c->rsz)) ||
         (st = dalloc(c, &c->d_wpart, std::max<size_t>({wind_gemm_part_elems((int)G, (int)M),
-                                                       wind_gemm_part_elems((int)G, (int)Mf), 1}) * c->rsz)) ||
+                                                       c->wind_model == SMC_WIND_EXP_AR1 ? wind_gemm_part_elems(fx, (int)Mf * c->nz) : 0,
+                                                       (size_t)1}) *
+                                         c->rsz)) ||
         (st = dalloc(c, &c->d_u, L * N * D * c->rsz)) ||
         (st = dalloc(c, &c->d_u2, L * N * D * c->rsz)) ||
         (st = dalloc(c, &c->d_up, (c->move != SMC_MOVE_JITTER ? L : 1) * N * D * c->rsz)) ||
@@ -755,6 +777,11 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         (st = dalloc_t(c, &d_Lz, (size_t)c->nz * c->nz)))
         return bail(st);
     if ((st = dalloc(c, &c->d_acR, N * kAcR * c->rsz))) return bail(st);
+    if (c->wind_model == SMC_WIND_EXP_AR1 &&
+        ((st = dalloc(c, &c->d_Lh, (size_t)fx * fx * c->rsz)) ||
+         (st = dalloc_t(c, &c->d_Lzd, (size_t)c->nz * c->nz)) ||
+         (st = dalloc(c, &c->d_Y, G * 2 * Mf * c->rsz))))
+        return bail(st);
     {
         const size_t gl = (c->move == SMC_MOVE_MALA ? L : 1) * N * D;
         if ((st = dalloc_t(c, &c->d_g, gl)) || (st = dalloc_t(c, &c->d_g2, gl)) ||
@@ -793,6 +820,11 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     INIT_HIP(hipMemcpy(d_Lz, Lz.data(), Lz.size() * sizeof(double), hipMemcpyHostToDevice));
     INIT_HIP(launch_kron_expand(c->prec, d_Lx, d_Ly, d_Lz, fx, fy, c->nz, c->sigma, c->d_Lfac,
                                 c->stream));
+    if (c->d_Lh) {   // sigma L_h alone (d_Ly holds the 1 x 1 factor 1), and L_z
+        INIT_HIP(launch_kron_expand(c->prec, d_Lx, d_Ly, d_Ly, fx, 1, 1, c->sigma, c->d_Lh,
+                                    c->stream));
+        INIT_HIP(hipMemcpy(c->d_Lzd, Lz.data(), Lz.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     INIT_HIP(hipStreamSynchronize(c->stream));
 #undef INIT_HIP
     *out = c;
@@ -895,9 +927,8 @@ smc_status smc_eval_cost(smc_ctx* c, int64_t mpc_step, int32_t iter, const doubl
     }
     HIP_OK(c, hipMemcpyAsync(c->d_states, states, sizeof(double) * c->N * 6, hipMemcpyHostToDevice, st));
     HIP_OK(c, hipMemcpyAsync(c->d_kact, k_active, sizeof(int32_t) * c->N, hipMemcpyHostToDevice, st));
-    HIP_OK(c, wind_normals(c, mpc_step, iter, c->d_Z, st));
-    HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G, c->Mf,
-                               c->d_W, c->d_wpart, st));
+    HIP_OK(c, wind_normals(c, mpc_step, iter, st));
+    HIP_OK(c, wind_fields_gemm(c, wind_mean, c->d_W, st));
     RolloutParams rp = c->rp;
     rp.H = horizon;
     rp.P = P;
@@ -959,9 +990,8 @@ smc_status smc_k_wind_fields(smc_ctx* c, int64_t mpc_step, int32_t iter, const d
                              void* W, void* stream) {
     if (!c || !W || !wind_mean || iter < 0) return fail(c, SMC_EINVAL, "smc_k_wind_fields: bad arguments");
     hipStream_t st = pick(c, stream);
-    HIP_OK(c, wind_normals(c, mpc_step, iter, c->d_Z, st));
-    HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G, c->Mf, W,
-                               c->d_wpart, st));
+    HIP_OK(c, wind_normals(c, mpc_step, iter, st));
+    HIP_OK(c, wind_fields_gemm(c, wind_mean, W, st));
     return SMC_OK;
 }
 
