@@ -108,8 +108,9 @@ enum { SMC_WIND_SE = 0, SMC_WIND_EXP_AR1 = 1 };
  *  (wind_tcorr = G_t [s], > 0; infinity freezes the field), v(k) of sample m
  *  being the normals of sample k M + m; wind_ell is not used.  Limits of
  *  SMC_WIND_EXP_AR1: n_aircraft <= 20, move not SMC_MOVE_MALA, no
- *  smc_plant_step, not in the batched form; horizon_max * n_wind * G
- *  * 2 < 2^31; init factors the (nx ny)^2 horizontal Gram matrix on the host.
+ *  smc_plant_step, not in the batched form; horizon_max * n_wind * G * 2
+ *  reals below 2^31 bytes; at most 16 levels (nz); init factors the
+ *  (nx ny)^2 horizontal Gram matrix on the host.
  */
 typedef struct {
     int32_t n_aircraft, n_segments, horizon_max, n_particles, n_wind, n_iters;

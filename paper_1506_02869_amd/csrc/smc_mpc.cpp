@@ -173,8 +173,9 @@ smc_status validate(const smc_scenario* s) {
             return fail(nullptr, SMC_EINVAL, "time-correlated wind: at most 4096 horizontal nodes");
         if (s->grid_n[2] > 16)
             return fail(nullptr, SMC_EINVAL, "time-correlated wind: at most 16 levels");
-        if ((double)s->horizon_max * s->n_wind * G * 2 >= 2147483648.0)
-            return fail(nullptr, SMC_EINVAL, "time-correlated wind: H M G 2 must be below 2^31");
+        const double rbytes = s->precision == SMC_FP64 ? 8.0 : 4.0;
+        if ((double)s->horizon_max * s->n_wind * G * 2 * rbytes >= 2147483648.0)
+            return fail(nullptr, SMC_EINVAL, "time-correlated wind: the fields of all steps must take below 2^31 bytes");
     }
     if (!(s->sep_h >= 0) || !(s->sep_v >= 0)) return fail(nullptr, SMC_EINVAL, "separations must be >= 0");
     if (!s->kind || !s->aircraft || !s->targets)

@@ -62,15 +62,19 @@ def test_fields_match_oracle(lib, prec, grid, M, H):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("which", ["c1", "c2"])
+@pytest.mark.parametrize("which", ["c1", "c2", "c2-short"])
 def test_rollout_reads_one_field_per_step(lib, prec, which):
     """The oracle's per-step fields in, cost and feasibility out, against the
-    oracle's rollout of the same fields (2 and 10 aircraft)."""
+    oracle's rollout of the same fields (2 and 10 aircraft; and a horizon
+    shorter than the steps the fields cover)."""
     import torch
+    horizon = None
     if which == "c1":
         s = _ar1(synth.c1, prec, M=4, grid=(8, 8, 4))
     else:
         s = _ar1(synth.c2, prec, M=4, grid=(8, 8, 4), H=90, S=6)
+        if which == "c2-short":
+            horizon = 61
     ctx = lib.smc_mpc_init(s)
     P, N, M = 96, s["N"], s["M"]
     rnp = np.float64 if prec == "fp64" else np.float32
@@ -79,9 +83,10 @@ def test_rollout_reads_one_field_per_step(lib, prec, which):
     cost = empty((M, P, N), torch.float64)
     feas = empty((M, P, N), torch.uint8)
     steps = zeros((128,), torch.int64)
+    H = s["H"] if horizon is None else horizon
     lib.smc_k_rollout(ctx, dev(u, ctx.real_dtype), P, dev(W, ctx.real_dtype), dev(s["states"]),
-                      dev(np.asarray(s["k_active"], np.int32)), s["H"], cost, feas, steps)
-    ref = oro.rollout(s, u, W, with_margins=True)
+                      dev(np.asarray(s["k_active"], np.int32)), H, cost, feas, steps)
+    ref = oro.rollout(s, u, W, horizon=H, with_margins=True)
     got_c = host(cost).transpose(1, 0, 2)
     got_f = host(feas).transpose(1, 0, 2).astype(bool)
     cnt = host(steps)
