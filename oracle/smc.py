@@ -25,7 +25,9 @@ Build-specific readings (listed in the design notes): the inner loop draws M
 wind samples per iteration and the growing SampleSchedule(J) becomes the
 tempering exponent beta_J = kappa * SampleSchedule(J) of
 log W = -beta_J * mean_m(cost) (a product of S(J) objective values is
-exp(S(J) * mean log J)); resampling quantises the normalised weights to
+exp(S(J) * mean log J)); with the paper's literal weighting (weighting 1)
+iteration J makes S(J) + 1 passes, pass j under wind sample j, and
+log W = sum_j log(1 - cost_j); resampling quantises the normalised weights to
 integers so that its FP64 prefix sum is exact; an all-zero weight row keeps
 its particles (identity ancestors); the random-walk move is a Metropolis step
 on the joint particle with the product of aircraft weights as target.
@@ -78,6 +80,34 @@ def expected_cost(cost, feas):
 def log_weights(chat, feasible, b):
     """log W = -beta * c_hat, or -inf for a violating aircraft."""
     return np.where(feasible, -b * chat, -np.inf)
+
+
+def product_weighting(scen) -> bool:
+    """The paper's literal weighting (Alg. 1 inner loop, Sec. "Weight
+    Scaling") in place of the tempered mean."""
+    return int(scen.get("weighting", 0)) == 1
+
+
+def inner_samples(J: int) -> int:
+    """Inner-loop passes of iteration J: j = 0 .. SampleSchedule(J)."""
+    return sample_schedule(J) + 1
+
+
+def product_log_weights(cost, feas):
+    """Sec. "Weight Scaling": from W = 1/L every pass j multiplies the weight
+    by the objective value J_T = 1 - cost (costs are 1 - J here), and a
+    violation in any pass zeroes it: log W = sum_j log(1 - cost_j) up to the
+    common log(1/L), or -inf.  cost, feas: [L, n, N] over the n passes."""
+    L, n, N = cost.shape
+    out = np.empty((L, N))
+    for l in range(L):
+        for i in range(N):
+            if not feas[l, :, i].all():
+                out[l, i] = -np.inf
+                continue
+            terms = [math.log1p(-c) if c < 1.0 else -math.inf for c in cost[l, :, i]]
+            out[l, i] = -math.inf if -math.inf in terms else math.fsum(terms)
+    return out
 
 
 # --- resampling --------------------------------------------------------------
@@ -234,7 +264,8 @@ def run_smc(scen, evaluate, L, K, N, S, mpc_step=None, trace=None,
             u_init=None, grad=None):
     """Generic SMC optimiser (Alg. 1 with the readings above).
 
-    ``evaluate(u, J)`` -> (c_hat [L, N], feasible [L, N]); ``grad(u, J)`` ->
+    ``evaluate(u, J)`` -> (c_hat [L, N], feasible [L, N]) or (c_hat,
+    feasible, log W) when it weights by itself; ``grad(u, J)`` ->
     d/du sum_i c_hat_i of the differentiable (fuel + time) part, needed by the
     Langevin move.  Returns dict with the final particles, c_hat,
     log-weights, the selected index and status."""
@@ -243,14 +274,16 @@ def run_smc(scen, evaluate, L, K, N, S, mpc_step=None, trace=None,
     acc_rate = []
     for J in range(K):
         b = beta(scen, J)
-        chat, feas = evaluate(u, J)
-        logw = log_weights(chat, feas, b)
+        ev = evaluate(u, J)
+        chat, feas = ev[0], ev[1]
+        logw = ev[2] if len(ev) > 2 else log_weights(chat, feas, b)
         if trace is not None:
             trace.append(dict(J=J, u=u.copy(), chat=chat.copy(), logw=logw.copy()))
         if move == 1:   # random-walk Metropolis on the joint particle
             up = rw_propose(scen, u, J, mpc_step)
-            chat_p, feas_p = evaluate(up, J)
-            logw_p = log_weights(chat_p, feas_p, b)
+            ev = evaluate(up, J)
+            chat_p, feas_p = ev[0], ev[1]
+            logw_p = ev[2] if len(ev) > 2 else log_weights(chat_p, feas_p, b)
             acc = mh_accept(scen, J, logw, logw_p, mpc_step)
             u = np.where(acc[:, None, None, None], up, u)
             chat = np.where(acc[:, None], chat_p, chat)
@@ -313,6 +346,11 @@ def smc_mpc_step(scen, states=None, k_active=None, horizon=None, mpc_step=None,
         return fields[J]
 
     def evaluate(u, J):
+        if product_weighting(scen):
+            # pass j of the inner loop draws sample j of the iteration's fields
+            r = _rollout.rollout(scen, u, field(J)[:inner_samples(J)], states, k_active, horizon)
+            chat, feas = expected_cost(r["cost"], r["feas"])
+            return chat, feas, product_log_weights(r["cost"], r["feas"])
         r = _rollout.rollout(scen, u, field(J), states, k_active, horizon)
         return expected_cost(r["cost"], r["feas"])
 
