@@ -334,6 +334,9 @@ def main():
     ap.add_argument("--wind", choices=["se", "ar1"], default="se",
                     help="wind model: static squared-exponential fields (default) or the "
                          "paper's exponential covariance with its time recursion (c1, c2)")
+    ap.add_argument("--weighting", choices=["tempered", "product"], default="tempered",
+                    help="SMC weights: tempered mean over all samples (default) or the paper's "
+                         "literal product over SampleSchedule(J) + 1 passes")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -370,6 +373,11 @@ def main():
             sys.exit(2)
         desc += (AR1_DESC)
     scen = getattr(synth, key)(**({"wind_model": "ar1"} if ar1 else {}))
+    product = args.weighting == "product"
+    if product:
+        scen["weighting"] = 1
+        desc += ("; the paper's literal weighting: SampleSchedule(J) + 1 passes at iteration J "
+                 "(one wind sample each), log W = sum log(1 - cost)")
     torch.cuda.set_device(0)
     ctx = smc.smc_mpc_init(scen)
     dev = torch.device("cuda")
@@ -471,7 +479,9 @@ def main():
         c_ctrl = ctrl.cpu().numpy()
         c_cost = cost.cpu().numpy()
         u = (c_ctrl - scen["ctrl_lo"]) / (scen["ctrl_hi"] - scen["ctrl_lo"])
-        rc, rf = osmc.eval_cost(scen, u[None], scen["K"] - 1)
+        # the returned cost averages the passes of the last iteration
+        sc = dict(scen, M=osmc.inner_samples(scen["K"] - 1)) if product else scen
+        rc, rf = osmc.eval_cost(sc, u[None], scen["K"] - 1)
         rel = abs(float(rc.sum()) - float(c_cost[0])) / max(abs(float(rc.sum())), 1e-3)
         check = {"gpu_cost": float(c_cost[0]), "oracle_rescored_cost": float(rc.sum()),
                  "rel_err": rel, "within_1e-3": bool(rel <= 1e-3),

@@ -55,6 +55,10 @@ enum { SMC_MOVE_JITTER = 0, SMC_MOVE_RWMH = 1, SMC_MOVE_MALA = 2 };
 /* Wind models: a static squared-exponential field per sample, or the paper's
  * exponential covariance with its time recursion (one field per step). */
 enum { SMC_WIND_SE = 0, SMC_WIND_EXP_AR1 = 1 };
+/* Weighting: tempered (log W = -kappa SampleSchedule(J) mean cost over the
+ * n_wind samples) or the paper's literal product over SampleSchedule(J) + 1
+ * passes. */
+enum { SMC_WEIGHT_TEMPERED = 0, SMC_WEIGHT_PRODUCT = 1 };
 
 #define SMC_AC_NPAR 9   /* aircraft parameters per aircraft, see smc_scenario */
 #define SMC_COST_NW 9   /* cost weights, see smc_scenario */
@@ -111,6 +115,15 @@ enum { SMC_WIND_SE = 0, SMC_WIND_EXP_AR1 = 1 };
  *  smc_plant_step, not in the batched form; horizon_max * n_wind * G * 2
  *  reals below 2^31 bytes; at most 16 levels (nz); init factors the
  *  (nx ny)^2 horizontal Gram matrix on the host.
+ *  weighting SMC_WEIGHT_TEMPERED: every iteration J rolls out all n_wind
+ *  samples and log W = -kappa SampleSchedule(J) c_hat.  SMC_WEIGHT_PRODUCT
+ *  (Alg. 1 inner loop, Sec. "Weight Scaling"): iteration J makes
+ *  SampleSchedule(J) + 1 passes, pass j under wind sample j (the first
+ *  samples of the iteration's fields), and each multiplies the weight by
+ *  the objective value 1 - cost: log W = sum_j log(1 - cost_j), -inf after
+ *  a violation; c_hat is the mean over the passes.  Needs n_wind >=
+ *  SampleSchedule(n_iters - 1) + 1, the static wind model and a move other
+ *  than SMC_MOVE_MALA; not in the batched form.
  */
 typedef struct {
     int32_t n_aircraft, n_segments, horizon_max, n_particles, n_wind, n_iters;
@@ -135,6 +148,7 @@ typedef struct {
     int32_t scenario_id;
     int32_t wind_model;                         /* SMC_WIND_* */
     double wind_beta, wind_gamma, wind_tcorr;   /* SMC_WIND_EXP_AR1 only */
+    int32_t weighting;                          /* SMC_WEIGHT_* */
 } smc_scenario;
 
 /* Diagnostics of one MPC update (optional output).  When requested, device

@@ -185,6 +185,9 @@ hipError_t launch_accept_apply(int prec, int P, int N, int D, void* u, const voi
                                double* chat, const double* chat_prop, uint8_t* feas_pn,
                                const uint8_t* feas_prop, double* logw, const double* logw_prop,
                                const int32_t* flags, hipStream_t st);
+// The paper's literal weighting over M passes: log W = sum_m log(1 - cost_m).
+hipError_t launch_reduce_product(int P, int M, int N, const double* cost, const uint8_t* feas,
+                                 double* chat, uint8_t* feas_pn, double* logw, hipStream_t st);
 hipError_t launch_reduce(int P, int M, int N, const double* cost,
                          const uint8_t* feas, double beta, double* chat,
                          uint8_t* feas_pn, double* logw, hipStream_t st);

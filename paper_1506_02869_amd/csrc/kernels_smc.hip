@@ -14,6 +14,39 @@ __global__ void k_reduce(int P, int M, int N, const double* __restrict__ cost,
     reduce_at(t, PN, M, cost, feas, beta, chat, feas_pn, logw);
 }
 
+// The paper's literal weighting (Alg. 1 inner loop; Sec. "Weight Scaling"):
+// every pass m multiplies the weight by the objective value 1 - cost_m and a
+// violation zeroes it, so log W = sum_m log(1 - cost_m) (Kahan-compensated,
+// pass order) or -inf; c_hat and feasibility as in k_reduce.
+__global__ void k_reduce_product(int P, int M, int N, const double* __restrict__ cost,
+                                 const uint8_t* __restrict__ feas, double* __restrict__ chat,
+                                 uint8_t* __restrict__ feas_pn, double* __restrict__ logw) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t PN = (int64_t)P * N;
+    if (t >= PN) return;
+    double sum = 0.0, comp = 0.0, ls = 0.0, lc = 0.0;
+    int ok = 1, zero = 0;
+    for (int m = 0; m < M; ++m) {
+        const double x = cost[(int64_t)m * PN + t];
+        const double y = x - comp;
+        const double s = sum + y;
+        comp = (s - sum) - y;
+        sum = s;
+        ok &= feas[(int64_t)m * PN + t];
+        if (x >= 1.0) {
+            zero = 1;
+        } else {
+            const double ly = log1p(-x) - lc;
+            const double lt = ls + ly;
+            lc = (lt - ls) - ly;
+            ls = lt;
+        }
+    }
+    chat[t] = sum / (double)M;
+    feas_pn[t] = (uint8_t)ok;
+    logw[t] = (ok && !zero) ? ls : -INFINITY;
+}
+
 // One workgroup per aircraft row i.
 __global__ void __launch_bounds__(RS_THREADS) k_resample(int P, int N,
                                                          const double* __restrict__ logw,
@@ -53,6 +86,14 @@ hipError_t launch_reduce(int P, int M, int N, const double* cost, const uint8_t*
     const int64_t n = (int64_t)P * N;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, M, N,
                        cost, feas, beta, chat, feas_pn, logw);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_product(int P, int M, int N, const double* cost, const uint8_t* feas,
+                                 double* chat, uint8_t* feas_pn, double* logw, hipStream_t st) {
+    const int64_t n = (int64_t)P * N;
+    hipLaunchKernelGGL(k_reduce_product, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, M,
+                       N, cost, feas, chat, feas_pn, logw);
     return hipGetLastError();
 }
 

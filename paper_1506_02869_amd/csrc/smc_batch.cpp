@@ -155,6 +155,8 @@ smc_status validate_batch(const smc_scenario* sc, int ns) {
     int64_t rows = 0;
     for (int s = 0; s < ns; ++s) {
         std::string msg;
+        if (sc[s].weighting != SMC_WEIGHT_TEMPERED)
+            return bfail(nullptr, SMC_EINVAL, "scenario %d: the batched form takes the tempered weighting only", s);
         if (sc[s].wind_model != SMC_WIND_SE)
             return bfail(nullptr, SMC_EINVAL, "scenario %d: the batched form takes the static wind model only", s);
         if (host::validate_scenario(&sc[s], msg))

@@ -42,6 +42,7 @@ struct smc_ctx {
     int wind_model;         // SMC_WIND_*
     double war1, bar1;      // time recursion: a = exp(-dt / G_t), b = sqrt(1 - a^2)
     int Mf;                 // fields per iteration: M (static) or H M (one per step)
+    int weighting;          // SMC_WEIGHT_*
     size_t rsz;  // sizeof(real)
     RolloutParams rp;
 
@@ -161,6 +162,18 @@ smc_status validate(const smc_scenario* s) {
     if (!(s->wind_sigma >= 0) || !(s->wind_nugget >= 0) ||
         (s->wind_model == SMC_WIND_SE && !(s->wind_ell > 0)))
         return fail(nullptr, SMC_EINVAL, "wind parameters out of range");
+    if (s->weighting != SMC_WEIGHT_TEMPERED && s->weighting != SMC_WEIGHT_PRODUCT)
+        return fail(nullptr, SMC_EINVAL, "weighting must be SMC_WEIGHT_TEMPERED or SMC_WEIGHT_PRODUCT");
+    if (s->weighting == SMC_WEIGHT_PRODUCT) {
+        const int need = (int)host::sample_schedule(s->n_iters - 1) + 1;
+        if (s->n_wind < need)
+            return fail(nullptr, SMC_EINVAL, "product weighting needs n_wind >= SampleSchedule(n_iters - 1) + 1 = %d",
+                        need);
+        if (s->move == SMC_MOVE_MALA)
+            return fail(nullptr, SMC_EINVAL, "product weighting does not support the gradient move");
+        if (s->wind_model != SMC_WIND_SE)
+            return fail(nullptr, SMC_EINVAL, "product weighting takes the static wind model");
+    }
     if (s->wind_model == SMC_WIND_EXP_AR1) {
         if (!(s->wind_beta > 0) || !(s->wind_gamma > 0) || !(s->wind_tcorr > 0))
             return fail(nullptr, SMC_EINVAL, "wind_beta, wind_gamma and wind_tcorr must be > 0");
@@ -211,6 +224,15 @@ smc_status validate(const smc_scenario* s) {
     if ((double)G * s->n_wind >= 4294967295.0)
         return fail(nullptr, SMC_EINVAL, "wind normals exceed 2^32 elements");
     return SMC_OK;
+}
+
+// Chunk-product workspace of the wind GEMM for every sample count an update
+// may use (each count up to M under the literal weighting).
+size_t part_elems_upto(const smc_ctx* c) {
+    size_t e = wind_gemm_part_elems(c->G, c->M);
+    if (c->weighting == SMC_WEIGHT_PRODUCT)
+        for (int m = 1; m < c->M; ++m) e = std::max(e, wind_gemm_part_elems(c->G, m));
+    return e;
 }
 
 smc_status ensure_eval(smc_ctx* c, int64_t P) {
@@ -273,9 +295,10 @@ smc_status check_horizon(smc_ctx* c, int32_t horizon) {
 // G x 2 M reals in d_Z (static); for the time-correlated model the time
 // recursion over the H steps (d_Z, G x 2 H M), then the vertical factor
 // along the levels (d_Y).
-hipError_t wind_normals(smc_ctx* c, int64_t mpc_step, int J, hipStream_t st) {
+hipError_t wind_normals(smc_ctx* c, int64_t mpc_step, int J, hipStream_t st, int Ms = 0) {
     const Stream s = make_stream(c->seed, mpc_step, J, P_WIND, c->scen_id);
-    if (c->wind_model != SMC_WIND_EXP_AR1) return launch_wind_normals(c->prec, s, c->G, c->M, c->d_Z, st);
+    if (c->wind_model != SMC_WIND_EXP_AR1)
+        return launch_wind_normals(c->prec, s, c->G, Ms ? Ms : c->M, c->d_Z, st);
     hipError_t e = launch_wind_normals_ar1(c->prec, s, c->G, c->M, c->Hmax, c->war1, c->bar1,
                                            c->d_Z, st);
     if (e != hipSuccess) return e;
@@ -284,12 +307,28 @@ hipError_t wind_normals(smc_ctx* c, int64_t mpc_step, int J, hipStream_t st) {
 
 // The fields from the normals: the dense factor's product (static), or the
 // horizontal factor's product over the level-mixed normals.
-hipError_t wind_fields_gemm(smc_ctx* c, const double* wind_mean, void* W, hipStream_t st) {
+hipError_t wind_fields_gemm(smc_ctx* c, const double* wind_mean, void* W, hipStream_t st,
+                            int Ms = 0) {
     if (c->wind_model == SMC_WIND_EXP_AR1)
         return launch_wind_gemm_levels(c->prec, c->d_Lh, c->d_Y, wind_mean[0], wind_mean[1],
                                        c->nx * c->ny, c->nz, c->Mf, W, c->d_wpart, st);
-    return launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G, c->M, W,
-                            c->d_wpart, st);
+    return launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G,
+                            Ms ? Ms : c->M, W, c->d_wpart, st);
+}
+
+// Samples (passes) of iteration J: all of them for the tempered weighting,
+// SampleSchedule(J) + 1 for the paper's literal product (the first ones of
+// the iteration's draw: the normals of sample m are counter m G + g).
+int samples_of(const smc_ctx* c, int J) {
+    return c->weighting == SMC_WEIGHT_PRODUCT ? (int)host::sample_schedule(J) + 1 : c->M;
+}
+
+// Weights of one pass set: tempered mean or the literal product.
+hipError_t weigh(smc_ctx* c, int P, int Ms, double beta, double* chat, uint8_t* feaspn,
+                 double* logw, hipStream_t st) {
+    if (c->weighting == SMC_WEIGHT_PRODUCT)
+        return launch_reduce_product(P, Ms, c->N, c->d_cost, c->d_feas, chat, feaspn, logw, st);
+    return launch_reduce(P, Ms, c->N, c->d_cost, c->d_feas, beta, chat, feaspn, logw, st);
 }
 
 // The SMC loop of one MPC update on device buffers (Alg. 1).
@@ -318,9 +357,11 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     std::vector<int32_t> hflags;
     for (int J = 0; J < c->K; ++J) {
         const double beta = beta_of(c, J);
-        HIP_OK(c, wind_normals(c, mpc_step, J, st));
+        const int Ms = samples_of(c, J);
+        rp.M = Ms;
+        HIP_OK(c, wind_normals(c, mpc_step, J, st, Ms));
         if (info) HIP_OK(c, hipEventRecord(c->ev_wind[2 * J], st));
-        HIP_OK(c, wind_fields_gemm(c, wind_mean, c->d_W, st));
+        HIP_OK(c, wind_fields_gemm(c, wind_mean, c->d_W, st, Ms));
         if (info) HIP_OK(c, hipEventRecord(c->ev_wind[2 * J + 1], st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J], st));
         HIP_OK(c, do_rollout(c, rp,
@@ -329,8 +370,7 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
                                  st));
         if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J + 1], st));
         ++n_roll;
-        HIP_OK(c, launch_reduce(L, c->M, N, c->d_cost, c->d_feas, beta, c->d_chat, c->d_feaspn,
-                                c->d_logw, st));
+        HIP_OK(c, weigh(c, L, Ms, beta, c->d_chat, c->d_feaspn, c->d_logw, st));
         if (c->move == SMC_MOVE_RWMH) {
             const Stream sm = make_stream(c->seed, mpc_step, J, P_MOVE, c->scen_id);
             HIP_OK(c, launch_propose(c->prec, count, u, c->d_up, sm, c->sigma_move, st));
@@ -341,8 +381,7 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
                                      st));
             if (info) HIP_OK(c, hipEventRecord(c->ev_roll[4 * J + 3], st));
             ++n_roll2;
-            HIP_OK(c, launch_reduce(L, c->M, N, c->d_cost, c->d_feas, beta, c->d_chat2,
-                                    c->d_feaspn2, c->d_logw2, st));
+            HIP_OK(c, weigh(c, L, Ms, beta, c->d_chat2, c->d_feaspn2, c->d_logw2, st));
             HIP_OK(c, launch_accept(c->prec, L, N, D, u, c->d_up, c->d_chat, c->d_chat2,
                                     c->d_feaspn, c->d_feaspn2, c->d_logw, c->d_logw2,
                                     make_stream(c->seed, mpc_step, J, P_ACCEPT, c->scen_id),
@@ -699,6 +738,7 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     c->war1 = c->wind_model == SMC_WIND_EXP_AR1 ? std::exp(-s->dt / s->wind_tcorr) : 0.0;
     c->bar1 = std::sqrt(std::max(0.0, 1.0 - c->war1 * c->war1));
     c->Mf = c->wind_model == SMC_WIND_EXP_AR1 ? c->Hmax * c->M : c->M;
+    c->weighting = s->weighting;
 
     host::fill_rollout_params(s, c->rp);
     c->rp.w_kstride = c->wind_model == SMC_WIND_EXP_AR1 ? (int64_t)c->M * c->G * 2 : 0;
@@ -756,7 +796,7 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         (st = dalloc_t(c, &c->d_kind, N)) ||
         (st = dalloc(c, &c->d_Lfac, G * G * c->rsz)) || (st = dalloc(c, &c->d_Z, G * 2 * Mf * c->rsz)) ||
         (st = dalloc(c, &c->d_W, Mf * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_Wt, M * G * 2 * c->rsz)) ||
-        (st = dalloc(c, &c->d_wpart, std::max<size_t>({wind_gemm_part_elems((int)G, (int)M),
+        (st = dalloc(c, &c->d_wpart, std::max<size_t>({part_elems_upto(c),
                                                        c->wind_model == SMC_WIND_EXP_AR1 ? wind_gemm_part_elems(fx, (int)Mf * c->nz) : 0,
                                                        (size_t)1}) *
                                          c->rsz)) ||
