@@ -94,6 +94,16 @@ smc_status smc_k_reduce(smc_ctx* ctx, int32_t P, const double* cost,
                         const uint8_t* feas, double beta, double* chat,
                         uint8_t* feas_pn, double* logw, void* stream);
 
+/* The paper's literal weighting over M passes (Alg. 1 inner loop, Sec.
+ * "Weight Scaling"): cost[M][P][N], feas[M][P][N] as smc_k_rollout writes
+ * them for M samples (1 <= M <= the context's n_wind); c_hat and
+ * feasibility as smc_k_reduce; logw = sum_m log(1 - cost_m)
+ * (Kahan-compensated FP64, pass order), -inf if any pass violates or has
+ * cost >= 1. */
+smc_status smc_k_reduce_product(smc_ctx* ctx, int32_t P, int32_t M, const double* cost,
+                                const uint8_t* feas, double* chat, uint8_t* feas_pn,
+                                double* logw, void* stream);
+
 /* First Philox word of the RESAMPLE stream for each aircraft row:
  * U[N] uint32. */
 smc_status smc_k_resample_offsets(smc_ctx* ctx, int64_t mpc_step, int32_t iter,

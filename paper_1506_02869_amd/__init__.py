@@ -138,6 +138,7 @@ _SIGS = {
     "smc_k_rollout": (C.c_int, [_VP, _VP, C.c_int32, _VP, _VP, _VP, C.c_int32, _VP, _VP, _VP,
                                 _VP]),
     "smc_k_reduce": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_double, _VP, _VP, _VP, _VP]),
+    "smc_k_reduce_product": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
     "smc_k_resample_offsets": (C.c_int, [_VP, C.c_int64, C.c_int32, _VP, _VP]),
     "smc_k_resample": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
     "smc_k_gather_move": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, C.c_int64, C.c_int32,
@@ -462,6 +463,11 @@ def smc_k_rollout(ctx, u, P, W, states, k_active, horizon, cost, feas, steps=Non
 def smc_k_reduce(ctx, P, cost, feas, beta, chat, feas_pn, logw, stream=None):
     _check(lib().smc_k_reduce(ctx.handle, int(P), _ptr(cost), _ptr(feas), float(beta),
                               _ptr(chat), _ptr(feas_pn), _ptr(logw), _stream(stream)), ctx)
+
+
+def smc_k_reduce_product(ctx, P, M, cost, feas, chat, feas_pn, logw, stream=None):
+    _check(lib().smc_k_reduce_product(ctx.handle, int(P), int(M), _ptr(cost), _ptr(feas),
+                                      _ptr(chat), _ptr(feas_pn), _ptr(logw), _stream(stream)), ctx)
 
 
 def smc_k_resample_offsets(ctx, mpc_step, iter_, U, stream=None):

@@ -1053,6 +1053,15 @@ smc_status smc_k_rollout(smc_ctx* c, const void* u, int32_t P, const void* W, co
     return SMC_OK;
 }
 
+smc_status smc_k_reduce_product(smc_ctx* c, int32_t P, int32_t M, const double* cost,
+                                const uint8_t* feas, double* chat, uint8_t* feas_pn, double* logw,
+                                void* stream) {
+    if (!c || !cost || !feas || !chat || !feas_pn || !logw || P < 1 || M < 1 || M > c->M)
+        return fail(c, SMC_EINVAL, "smc_k_reduce_product: bad arguments");
+    HIP_OK(c, launch_reduce_product(P, M, c->N, cost, feas, chat, feas_pn, logw, pick(c, stream)));
+    return SMC_OK;
+}
+
 smc_status smc_k_reduce(smc_ctx* c, int32_t P, const double* cost, const uint8_t* feas, double beta,
                         double* chat, uint8_t* feas_pn, double* logw, void* stream) {
     if (!c || !cost || !feas || !chat || !feas_pn || !logw || P < 1)

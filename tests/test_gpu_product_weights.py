@@ -48,3 +48,35 @@ def test_product_weighting_limits(lib):
     s["weighting"] = 1
     with pytest.raises(lib.SmcError):
         lib.smc_mpc_init(s)
+
+
+@pytest.mark.parametrize("M", [1, 9, 16])
+def test_reduce_product_matches_oracle(lib, M):
+    """The literal weights of random passes (with violations and a zero
+    objective) against the oracle's, element by element."""
+    import torch
+    from tests.gpu_helpers import dev, empty, host
+    s = synth.c1()
+    ctx = lib.smc_mpc_init(s)
+    P, N = 301, s["N"]
+    rng = np.random.default_rng(M)
+    cost = rng.uniform(0, 1, (M, P, N))
+    cost[0, 5, 0] = 1.0
+    feas = rng.uniform(size=(M, P, N)) > 0.01
+    chat = empty((P, N), torch.float64)
+    fpn = empty((P, N), torch.uint8)
+    logw = empty((P, N), torch.float64)
+    lib.smc_k_reduce_product(ctx, P, M, dev(cost), dev(feas.astype(np.uint8)), chat, fpn, logw)
+    c_t, f_t = cost.transpose(1, 0, 2), feas.transpose(1, 0, 2)
+    rc, rf = osmc.expected_cost(c_t, f_t)
+    rl = osmc.product_log_weights(c_t, f_t)
+    gl = host(logw)
+    assert np.abs(host(chat) - rc).max() < 4e-16
+    assert np.array_equal(host(fpn).astype(bool), rf)
+    assert gl[5, 0] == -np.inf
+    assert np.array_equal(np.isfinite(gl), np.isfinite(rl))
+    fin = np.isfinite(rl)
+    assert np.all(np.abs(gl[fin] - rl[fin]) <= 1e-14 * np.maximum(np.abs(rl[fin]), 1.0))
+    with pytest.raises(lib.SmcError):
+        lib.smc_k_reduce_product(ctx, P, s["M"] + 1, dev(cost), dev(feas.astype(np.uint8)),
+                                 chat, fpn, logw)
