@@ -126,6 +126,11 @@ hipError_t launch_wind_normals(int prec, Stream s, int G, int M, void* Z,
 // (k M + m) G + g; b = sqrt(1 - a^2).
 hipError_t launch_wind_normals_ar1(int prec, Stream s, int G, int M, int H, double a, double b,
                                    void* Z, hipStream_t st);
+// The recursion and the vertical factor in one pass (nz divides 64): writes
+// Y[h][col][iz] as launch_wind_levels does from Z.
+hipError_t launch_wind_normals_ar1_levels(int prec, Stream s, int G, int M, int H, int nz,
+                                          double a, double b, const double* Lz, void* Y,
+                                          hipStream_t st);
 // Time-correlated wind with Qhat = sigma L_h (x) L_z: Y[h][col][iz] =
 // sum_j Lz[iz][j] U[h nz + j][col] over the 2 M columns (nz <= 16), then
 // W[m][h nz + iz][c] = w_c + sum_h' (sigma L_h)[h][h'] Y[h'][2 m + c][iz]

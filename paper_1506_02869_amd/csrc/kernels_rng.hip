@@ -64,6 +64,55 @@ __global__ void k_wind_normals_ar1(Stream s, int G, int M, int H, double a, doub
     }
 }
 
+// The same recursion with the vertical factor applied on the fly (nz
+// divides 64): lane per (h, m, iz), the nz levels of a horizontal node in
+// consecutive lanes of one wave, which exchange their u(k) by shuffles and
+// store Y[h][col][iz] = sum_{j <= iz} Lz[iz][j] u_j(k) (FP64 sums), the
+// input of the horizontal factor's product.  The normals are those of
+// k_wind_normals_ar1 (counter (k M + m) G + g, g = h nz + iz).
+template <typename R>
+__global__ void k_wind_normals_ar1_levels(Stream s, int G, int M, int H, int nz, double a,
+                                          double b, const double* __restrict__ Lz, R* Y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // G M is a multiple of nz and nz divides 64: a level group is wholly in
+    // or out of range, and wholly inside one wave
+    if (t >= (int64_t)G * M) return;
+    const int iz = (int)(t % nz);
+    const int64_t r = t / nz;
+    const int m = (int)(r % M);
+    const int h = (int)(r / M);
+    const int g = h * nz + iz;
+    const int base = (int)(threadIdx.x & 63) - iz;
+    const int64_t NC = 2 * (int64_t)H * M;
+    R* yrow = Y + (int64_t)h * NC * nz + iz;
+    double u0 = 0.0, u1 = 0.0;
+    for (int k = 0; k < H; ++k) {
+        const int64_t col = (int64_t)k * M + m;
+        double z0, z1;
+        normal_pair(draw(s, (uint32_t)(col * G + g)), z0, z1);
+        if (k == 0) {
+            u0 = z0;
+            u1 = z1;
+        } else {
+            const double p0 = a * u0, p1 = a * u1;
+            u0 = p0 + b * z0;
+            u1 = p1 + b * z1;
+        }
+        double y0 = 0.0, y1 = 0.0;
+        for (int j = 0; j < nz; ++j) {
+            const double v0 = __shfl(u0, base + j, 64);
+            const double v1 = __shfl(u1, base + j, 64);
+            if (j <= iz) {
+                const double l = Lz[iz * nz + j];
+                y0 += l * v0;
+                y1 += l * v1;
+            }
+        }
+        yrow[(2 * col) * nz] = to_real<R>(y0);
+        yrow[(2 * col + 1) * nz] = to_real<R>(y1);
+    }
+}
+
 __global__ void k_resample_offsets(Stream s, int N, uint32_t* U) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
@@ -155,6 +204,20 @@ hipError_t launch_wind_normals_ar1(int prec, Stream s, int G, int M, int H, doub
     else
         hipLaunchKernelGGL(k_wind_normals_ar1<float>, dim3(blocks_for(n, 256)), dim3(256),
                            0, st, s, G, M, H, a, b, (float*)Z);
+    return hipGetLastError();
+}
+
+hipError_t launch_wind_normals_ar1_levels(int prec, Stream s, int G, int M, int H, int nz,
+                                          double a, double b, const double* Lz, void* Y,
+                                          hipStream_t st) {
+    if (nz < 1 || 64 % nz != 0 || G % nz != 0) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)G * M;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_wind_normals_ar1_levels<double>, dim3(blocks_for(n, 256)), dim3(256),
+                           0, st, s, G, M, H, nz, a, b, Lz, (double*)Y);
+    else
+        hipLaunchKernelGGL(k_wind_normals_ar1_levels<float>, dim3(blocks_for(n, 256)), dim3(256),
+                           0, st, s, G, M, H, nz, a, b, Lz, (float*)Y);
     return hipGetLastError();
 }
 

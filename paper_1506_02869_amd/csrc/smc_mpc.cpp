@@ -299,6 +299,9 @@ hipError_t wind_normals(smc_ctx* c, int64_t mpc_step, int J, hipStream_t st, int
     const Stream s = make_stream(c->seed, mpc_step, J, P_WIND, c->scen_id);
     if (c->wind_model != SMC_WIND_EXP_AR1)
         return launch_wind_normals(c->prec, s, c->G, Ms ? Ms : c->M, c->d_Z, st);
+    if (64 % c->nz == 0)   // the levels of a node fit the lanes of one wave
+        return launch_wind_normals_ar1_levels(c->prec, s, c->G, c->M, c->Hmax, c->nz, c->war1,
+                                              c->bar1, c->d_Lzd, c->d_Y, st);
     hipError_t e = launch_wind_normals_ar1(c->prec, s, c->G, c->M, c->Hmax, c->war1, c->bar1,
                                            c->d_Z, st);
     if (e != hipSuccess) return e;
