@@ -144,3 +144,52 @@ def test_time_correlated_wind_rejects_unsupported_calls(lib):
     with pytest.raises(lib.SmcError):
         lib.smc_k_rollout_grad(ctx, u, P, W, dev(s["states"]),
                                dev(np.asarray(s["k_active"], np.int32)), s["H"], g)
+
+
+def test_full_size_c2_fields_and_rollout_sampled(lib):
+    """C2 at full size under the paper's wind (8192 particles x 64 samples x
+    10 aircraft x 120 steps; 120 x 64 fields of 8192 points), the launches
+    the benchmark times: the GPU's fields of two samples against the
+    oracle's recursion for those samples (normals drawn by the oracle from
+    their counters), then 24 worlds of those samples, rolled out on the
+    GPU's own fields, against the oracle's rollout on the oracle's fields."""
+    import torch
+    from oracle import philox
+    s = synth.c2(wind_model="ar1")
+    ctx = lib.smc_mpc_init(s)
+    P, M, N, S, H = s["L"], s["M"], s["N"], s["S"], s["H"]
+    G, J = ctx.G, 5
+    W = empty((H, M, G, 2), torch.float32)
+    lib.smc_k_wind_fields(ctx, s["mpc_step"], J, s["wind_mean"], W)
+    rng = np.random.default_rng(21)
+    u = rng.uniform(0, 1, (P, N, S, 3)).astype(np.float32)
+    cost = empty((M, P, N), torch.float64)
+    feas = empty((M, P, N), torch.uint8)
+    lib.smc_k_rollout(ctx, dev(u), P, W, dev(s["states"]), dev(np.asarray(s["k_active"], np.int32)),
+                      H, cost, feas)
+    gc, gf, Wg = host(cost), host(feas).astype(bool), host(W)
+    Q = owind.factor(s)
+    a = owind.ar1_coefficient(s["dt"], s["wind_tcorr"])
+    ax, ay, az = owind.grid_axes(s["box"], s["grid"])
+    kap = (np.linalg.cond(owind.exp_gram_h(ax, ay, s["wind_beta"]) + s["wind_nugget"] * np.eye(len(ax) * len(ay)))
+           + np.linalg.cond(owind.exp_gram_z(az, s["wind_gamma"]) + s["wind_nugget"] * np.eye(len(az))))
+    u32 = 2.0 ** -24
+    compared = 0
+    for m in (0, M - 1):
+        e = ((np.arange(H, dtype=np.int64)[:, None] * M + m) * G
+             + np.arange(G, dtype=np.int64)[None, :]).reshape(-1)
+        z0, z1 = philox.normals_pair(s["seed"], s["mpc_step"], J, philox.WIND, e, 0)
+        V = np.stack([z0.reshape(H, G), z1.reshape(H, G)], axis=-1)[:, :, None, :]
+        Wo = owind.ar1_fields(Q, V, a, s["wind_mean"])                     # [H, 1, G, 2]
+        bound = _field_bound(Q, V, a).transpose(0, 2, 1, 3)
+        tol = (2 * u32 * (4 + np.sqrt(G) + H) + 4 * 2.0 ** -53 * kap) * bound + u32 * np.abs(Wo)
+        err = np.abs(Wg[:, m:m + 1].astype(np.float64) - Wo)
+        assert np.all(err <= tol), (m, err.max())
+        for p in rng.integers(P, size=12):
+            r = oro.rollout(s, u[p:p + 1].astype(np.float64), Wo, with_margins=True)
+            if (r["margin"] < 1e-4).any():
+                continue
+            compared += 1
+            assert np.array_equal(gf[m, p], r["feas"][0, 0]), (p, m)
+            assert np.all(rel_err(gc[m, p], r["cost"][0, 0]) < 2e-5), (p, m)
+    assert compared >= 16
