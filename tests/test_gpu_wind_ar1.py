@@ -193,3 +193,21 @@ def test_full_size_c2_fields_and_rollout_sampled(lib):
             assert np.array_equal(gf[m, p], r["feas"][0, 0]), (p, m)
             assert np.all(rel_err(gc[m, p], r["cost"][0, 0]) < 2e-5), (p, m)
     assert compared >= 16
+
+
+@pytest.mark.parametrize("grid", [(6, 5, 3), (8, 8, 4)])
+def test_frozen_time_correlation_repeats_the_first_field(lib, grid):
+    """G_t = infinity: a = 1 and Q = 0, so every step's field is the first
+    one bit for bit (both the two-pass and the fused normals kernels), and
+    the first is the oracle's."""
+    import math
+    s = _ar1(synth.c1, "fp32", grid=grid, M=3, H=10, S=5)
+    s["wind_tcorr"] = math.inf
+    ctx = lib.smc_mpc_init(s)
+    W = empty((10, 3, ctx.G, 2), ctx.real_dtype)
+    lib.smc_k_wind_fields(ctx, 0, 2, s["wind_mean"], W)
+    got = host(W)
+    for k in range(1, 10):
+        assert np.array_equal(got[k], got[0]), k
+    ref = owind.sample_field(s, 2)
+    assert np.abs(got[0] - ref[0]).max() < 1e-4 * s["wind_sigma"]
