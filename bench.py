@@ -363,14 +363,18 @@ def main():
     if args.rolling > 0:
         return rolling(args)
     desc, key = WORKLOADS[args.workload]
+    ar1 = args.wind == "ar1"
+    if ar1 and key not in ("c1", "c2"):
+        print("--wind ar1: the time-correlated wind runs in the single-scenario form with up "
+              "to 20 aircraft and random-walk or jitter moves (workloads c1, c2)", file=sys.stderr)
+        sys.exit(2)
+    if args.weighting == "product" and key in ("c3", "c4"):
+        print("--weighting product: the literal weighting runs in the single-scenario form with "
+              "random-walk or jitter moves (workloads c1, c2, c5)", file=sys.stderr)
+        sys.exit(2)
     if key == "c3":
         return bench_batch(args, desc)
-    ar1 = args.wind == "ar1"
     if ar1:
-        if key not in ("c1", "c2"):
-            print("--wind ar1: the time-correlated wind runs with up to 20 aircraft and "
-                  "random-walk or jitter moves (workloads c1, c2)", file=sys.stderr)
-            sys.exit(2)
         desc += (AR1_DESC)
     scen = getattr(synth, key)(**({"wind_model": "ar1"} if ar1 else {}))
     product = args.weighting == "product"
