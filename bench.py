@@ -320,7 +320,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-particles", type=int, default=64)
+    ap.add_argument("--cpu-particles", type=int, default=256)
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="batched workload: autotune the persistent rollout's launch shape first")
