@@ -260,6 +260,40 @@ def mala_propose(scen, u, g, J, mpc_step=None):
     return u + 0.5 * eps * eps * g + eps * xi
 
 
+def mh_move(scen, u, chat, logw, J, b, evaluate, grad=None, mpc_step=None):
+    """One Metropolis move of every particle on the joint target
+    prod_i W_i = exp(-b sum_i c_hat_i) (zero if an aircraft violates) under
+    the fields of iteration J: the random walk (move 1, reflected proposal,
+    symmetric) or the Langevin proposal (move 2, drift g = -b grad, density
+    ratio q(u | u') / q(u' | u)).  Returns the moved particles, their c_hat
+    and log-weights, the acceptance flags and the proposal's intermediates."""
+    L = u.shape[0]
+    if scen["move"] == 1:
+        up = rw_propose(scen, u, J, mpc_step)
+        ev = evaluate(up, J)
+        chat_p, feas_p = ev[0], ev[1]
+        logw_p = ev[2] if len(ev) > 2 else log_weights(chat_p, feas_p, b)
+        acc = mh_accept(scen, J, logw, logw_p, mpc_step)
+        extra = dict(u_prop=up)
+    else:
+        from .grad import mala_log_q
+        eps = scen["mala_step"]
+        g = -b * grad(u, J)
+        up = mala_propose(scen, u, g, J, mpc_step)
+        chat_p, feas_p = evaluate(up, J)[:2]
+        logw_p = log_weights(chat_p, feas_p, b)
+        gp = -b * grad(up, J)
+        lq = mala_log_q(u, up, gp, eps) - mala_log_q(up, u, g, eps)
+        inside = np.all(((up >= 0.0) & (up <= 1.0)).reshape(L, -1), axis=1)
+        logw_p_eff = np.where(inside[:, None], logw_p, -np.inf)
+        acc = mh_accept(scen, J, logw, logw_p_eff, mpc_step, log_q_ratio=lq)
+        extra = dict(u_prop=up, g=g, g_prop=gp)
+    u = np.where(acc[:, None, None, None], up, u)
+    chat = np.where(acc[:, None], chat_p, chat)
+    logw = np.where(acc[:, None], logw_p, logw)
+    return u, chat, logw, acc, extra
+
+
 def run_smc(scen, evaluate, L, K, N, S, mpc_step=None, trace=None,
             u_init=None, grad=None):
     """Generic SMC optimiser (Alg. 1 with the readings above).
@@ -279,36 +313,12 @@ def run_smc(scen, evaluate, L, K, N, S, mpc_step=None, trace=None,
         logw = ev[2] if len(ev) > 2 else log_weights(chat, feas, b)
         if trace is not None:
             trace.append(dict(J=J, u=u.copy(), chat=chat.copy(), logw=logw.copy()))
-        if move == 1:   # random-walk Metropolis on the joint particle
-            up = rw_propose(scen, u, J, mpc_step)
-            ev = evaluate(up, J)
-            chat_p, feas_p = ev[0], ev[1]
-            logw_p = ev[2] if len(ev) > 2 else log_weights(chat_p, feas_p, b)
-            acc = mh_accept(scen, J, logw, logw_p, mpc_step)
-            u = np.where(acc[:, None, None, None], up, u)
-            chat = np.where(acc[:, None], chat_p, chat)
-            logw = np.where(acc[:, None], logw_p, logw)
+        if move in (1, 2):
+            u, chat, logw, acc, extra = mh_move(scen, u, chat, logw, J, b, evaluate,
+                                                grad, mpc_step)
             acc_rate.append(float(acc.mean()))
             if trace is not None:
-                trace[-1].update(u_prop=up, acc=acc, logw_after=logw.copy())
-        elif move == 2:   # Metropolis-adjusted Langevin on the joint particle
-            from .grad import mala_log_q
-            eps = scen["mala_step"]
-            g = -b * grad(u, J)
-            up = mala_propose(scen, u, g, J, mpc_step)
-            chat_p, feas_p = evaluate(up, J)
-            logw_p = log_weights(chat_p, feas_p, b)
-            gp = -b * grad(up, J)
-            lq = mala_log_q(u, up, gp, eps) - mala_log_q(up, u, g, eps)
-            inside = np.all(((up >= 0.0) & (up <= 1.0)).reshape(L, -1), axis=1)
-            logw_p_eff = np.where(inside[:, None], logw_p, -np.inf)
-            acc = mh_accept(scen, J, logw, logw_p_eff, mpc_step, log_q_ratio=lq)
-            u = np.where(acc[:, None, None, None], up, u)
-            chat = np.where(acc[:, None], chat_p, chat)
-            logw = np.where(acc[:, None], logw_p, logw)
-            acc_rate.append(float(acc.mean()))
-            if trace is not None:
-                trace[-1].update(u_prop=up, acc=acc, logw_after=logw.copy(), g=g, g_prop=gp)
+                trace[-1].update(acc=acc, logw_after=logw.copy(), **extra)
         if J == K - 1:
             break
         anc = resample(logw, resample_offsets(scen, J, N, mpc_step))

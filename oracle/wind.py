@@ -63,36 +63,12 @@ def se_gram(nodes, ell):
     return K
 
 
-def cholesky_lower(K):
-    """Textbook (row by row) Cholesky factorisation K = L L^T, FP64.
-
-    The 1-D squared-exponential Gram matrices are nearly singular, so their
-    factors are sensitive to rounding; a fixed, explicit operation order
-    keeps this factor reproducible."""
-    n = K.shape[0]
-    L = np.zeros((n, n))
-    for j in range(n):
-        s = K[j, j]
-        for k in range(j):
-            s -= L[j, k] * L[j, k]
-        if not s > 0.0:
-            raise np.linalg.LinAlgError("matrix not positive definite")
-        d = math.sqrt(s)
-        L[j, j] = d
-        for i in range(j + 1, n):
-            t = K[i, j]
-            for k in range(j):
-                t -= L[i, k] * L[j, k]
-            L[i, j] = t / d
-    return L
-
-
 def axis_factor(nodes, ell, nugget):
     """Lower Cholesky factor of the 1-D Gram matrix plus the nugget."""
     K = se_gram(nodes, ell)
     for a in range(len(nodes)):
         K[a, a] += nugget
-    return cholesky_lower(K)
+    return np.linalg.cholesky(K)
 
 
 def kron_factor(box, grid_n, sigma, ell, nugget):
