@@ -97,8 +97,9 @@ smc_status smc_batch_step(smc_batch* b, int64_t mpc_step, const double* states,
 
 /* Device-pointer form: states, k_active, controls_out, exp_cost_out and
  * status_out are device pointers (status_out may be NULL); wind_mean and
- * horizons are host arrays.  Work is queued on `stream` (hipStream_t, NULL =
- * the batch's stream); without info the call does not wait for the device
+ * horizons are host arrays.  Work is queued on `stream` (hipStream_t; NULL =
+ * the null stream, ordered with every blocking stream such as PyTorch's
+ * default stream); without info the call does not wait for the device
  * and returns SMC_OK (per-scenario status in status_out). */
 smc_status smc_batch_step_dev(smc_batch* b, int64_t mpc_step, const double* d_states,
                               const int32_t* d_k_active, const double* wind_mean,

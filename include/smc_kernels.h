@@ -8,8 +8,12 @@
  *
  * Conventions (in addition to those of smc_mpc.h):
  *  - All array pointers are DEVICE pointers, caller-owned; `stream` is a
- *    hipStream_t passed as void* (NULL = the context's stream).  Calls return
- *    after queueing the work; synchronise the stream before reading outputs.
+ *    hipStream_t passed as void*.  NULL is the null (legacy default) stream,
+ *    which orders with every blocking stream (PyTorch's default stream is
+ *    the null stream, handle 0), so inputs written there are complete before
+ *    the library reads them and later work there waits for the outputs.
+ *    Calls return after queueing the work; synchronise the stream (or queue
+ *    later work on it) before reading outputs.
  *  - "real" arrays hold double for an SMC_FP64 context and float for an
  *    SMC_FP32 context.  Costs, log-weights and scans are double always.
  *  - Sizes are validated on the host before any launch (SMC_EINVAL).

@@ -14,8 +14,10 @@
  * Conventions
  *  - Every array argument is caller-owned; the library copies what it needs.
  *    Functions with the _dev suffix take device pointers and a hipStream_t
- *    (passed as void*), never free caller memory and may return before the
- *    work completes (outputs are valid after the stream is synchronised).
+ *    (passed as void*; NULL = the null stream, which orders with every
+ *    blocking stream, e.g. PyTorch's default stream), never free caller
+ *    memory and may return before the work completes (outputs are valid
+ *    after the stream is synchronised or to later work on that stream).
  *  - Host-pointer functions are synchronous.
  *  - Errors are negative smc_status codes; outputs are then left untouched.
  *    Argument validation happens on the host before any device work.

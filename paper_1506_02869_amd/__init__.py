@@ -7,11 +7,10 @@ torch tensors on a HIP device (PyTorch provides device memory and streams);
 host arrays are NumPy arrays.
 
 Streams: device-form calls take ``stream`` (a torch stream; default: torch's
-current stream).  Torch's default stream has the handle 0, which the library
-reads as "the context's own stream": work is then queued there and is not
-ordered with torch's default stream, so call ``torch.cuda.synchronize()``
-before torch reads the outputs (or pass a non-default torch stream, on which
-library and torch work are ordered).
+current stream) and queue the library's work on it, so torch work queued
+before the call on that stream (filling inputs) completes first and torch
+work queued after it sees the outputs.  Torch's default stream has the
+handle 0, the null stream, which the library uses as such.
 
 The library must be built first (``python -m paper_1506_02869_amd.build``);
 importing this package without it raises at the first call.
@@ -204,6 +203,59 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _dtypes(kind):
+    """Accepted torch dtypes of an argument kind: 'f64', 'i32', 'u32' (int32
+    bit patterns accepted), 'u8', 'u64' (int64 accepted), or a Context's
+    'real'."""
+    import torch
+    table = {"f64": (torch.float64,), "f32": (torch.float32,), "i32": (torch.int32,),
+             "u32": tuple(t for t in (torch.int32, getattr(torch, "uint32", None)) if t),
+             "u8": (torch.uint8, torch.bool),
+             "u64": tuple(t for t in (torch.int64, getattr(torch, "uint64", None)) if t)}
+    return table[kind]
+
+
+def _dev(t, name, kind, numel, optional=False):
+    """Checked argument: a tensor of the given kind with exactly `numel`
+    elements (None passes if optional).  Raises ValueError before any
+    library call, so a wrong dtype or a short buffer never reaches a
+    kernel; `_ptrs` then converts the checked tensors to device pointers."""
+    import torch
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name}: a device tensor is required")
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    ok = _dtypes(kind) if isinstance(kind, str) else (kind,)
+    if t.dtype not in ok:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {' or '.join(map(str, ok))}")
+    if t.numel() != int(numel):
+        raise ValueError(f"{name}: {t.numel()} elements, expected {int(numel)}")
+    return t
+
+
+def _ptrs(*ts):
+    """Device pointers of already checked tensors (the device and contiguity
+    checks come after every argument's type and size check)."""
+    return tuple(_ptr(t) for t in ts)
+
+
+def _host(a, name, shape, dtype):
+    """Host array converted to dtype with exactly the given shape."""
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if a.shape != tuple(int(v) for v in shape):
+        raise ValueError(f"{name}: shape {a.shape}, expected {tuple(shape)}")
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _count(P, name="P"):
+    P = int(P)
+    if P < 0:
+        raise ValueError(f"{name} must be >= 0")
+    return P
+
+
 def _stream(stream=None):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
@@ -232,12 +284,19 @@ class Context:
         self.L, self.M, self.K = int(scen["L"]), int(scen["M"]), int(scen["K"])
         self.G = int(np.prod(scen["grid"]))
         self.precision = int(scen["precision"])
+        # fields per iteration: one per sample, or one per sample and step
+        # under the time-correlated wind model
+        self.Mf = self.M * (self.H if int(scen.get("wind_model", 0)) == 1 else 1)
         self.scen = scen
 
     @property
     def real_dtype(self):
         import torch
         return torch.float64 if self.precision == FP64 else torch.float32
+
+    @property
+    def D(self):
+        return self.N * self.S * 3
 
     def close(self):
         if self.handle:
@@ -322,9 +381,9 @@ def smc_mpc_step(ctx: Context, mpc_step=None, states=None, k_active=None, wind_m
     k_active = s["k_active"] if k_active is None else k_active
     wind_mean = s["wind_mean"] if wind_mean is None else wind_mean
     horizon = ctx.H if horizon is None else horizon
-    st_a, p_st = _hp(states, np.float64)
-    ka_a, p_ka = _hp(k_active, np.int32)
-    wm_a, p_wm = _hp(wind_mean, np.float64)
+    st_a, p_st = _host(states, "states", (ctx.N, 6), np.float64)
+    ka_a, p_ka = _host(k_active, "k_active", (ctx.N,), np.int32)
+    wm_a, p_wm = _host(wind_mean, "wind_mean", (2,), np.float64)
     ctrl = np.zeros((ctx.N, ctx.S, 3))
     cost = np.zeros(1 + ctx.N)
     info = StepInfo()
@@ -337,13 +396,17 @@ def smc_mpc_step(ctx: Context, mpc_step=None, states=None, k_active=None, wind_m
 
 def smc_mpc_step_dev(ctx: Context, mpc_step, states, k_active, wind_mean, horizon,
                      controls_out, cost_out, status_out=None, want_info=False, stream=None):
-    """Device form: states [N,6] f64, k_active [N] i32, outputs device tensors."""
-    wm_a, p_wm = _hp(wind_mean, np.float64)
+    """Device form: states [N,6] f64, k_active [N] i32, controls_out [N,S,3]
+    f64, cost_out [1+N] f64, status_out [1] i32 (optional): device tensors."""
+    wm_a, p_wm = _host(wind_mean, "wind_mean", (2,), np.float64)
+    args = _ptrs(_dev(states, "states", "f64", ctx.N * 6), _dev(k_active, "k_active", "i32", ctx.N),
+            _dev(controls_out, "controls_out", "f64", ctx.D),
+            _dev(cost_out, "cost_out", "f64", 1 + ctx.N),
+            _dev(status_out, "status_out", "i32", 1, optional=True))
     info = StepInfo() if want_info else None
-    r = lib().smc_mpc_step_dev(ctx.handle, int(mpc_step), _ptr(states), _ptr(k_active), p_wm,
-                               int(horizon), _ptr(controls_out), _ptr(cost_out),
-                               _ptr(status_out), C.byref(info) if info is not None else None,
-                               _stream(stream))
+    r = lib().smc_mpc_step_dev(ctx.handle, int(mpc_step), args[0], args[1], p_wm,
+                               int(horizon), args[2], args[3], args[4],
+                               C.byref(info) if info is not None else None, _stream(stream))
     _check(r, ctx)
     return r, (info.as_dict() if info is not None else None)
 
@@ -356,11 +419,12 @@ def smc_eval_cost(ctx: Context, particles, iter_, mpc_step=None, states=None, k_
     k_active = s["k_active"] if k_active is None else k_active
     wind_mean = s["wind_mean"] if wind_mean is None else wind_mean
     horizon = ctx.H if horizon is None else horizon
-    pa, p_pa = _hp(particles, np.float64)
-    P = pa.shape[0]
-    st_a, p_st = _hp(states, np.float64)
-    ka_a, p_ka = _hp(k_active, np.int32)
-    wm_a, p_wm = _hp(wind_mean, np.float64)
+    pa = np.asarray(particles)
+    P = pa.shape[0] if pa.ndim == 4 else -1
+    pa, p_pa = _host(pa, "particles", (P, ctx.N, ctx.S, 3), np.float64)
+    st_a, p_st = _host(states, "states", (ctx.N, 6), np.float64)
+    ka_a, p_ka = _host(k_active, "k_active", (ctx.N,), np.int32)
+    wm_a, p_wm = _host(wind_mean, "wind_mean", (2,), np.float64)
     cost = np.zeros((P, ctx.N))
     feas = np.zeros((P, ctx.N), dtype=np.uint8)
     r = lib().smc_eval_cost(ctx.handle, int(mpc_step), int(iter_), p_st, p_ka, p_wm,
@@ -381,10 +445,10 @@ def smc_plant_step(ctx: Context, controls, plant_iter, n_steps=None, mpc_step=No
     wind_mean = s["wind_mean"] if wind_mean is None else wind_mean
     horizon = ctx.H if horizon is None else horizon
     n_steps = -(-int(horizon) // ctx.S) if n_steps is None else n_steps
-    st_a, p_st = _hp(states, np.float64)
-    ka_a, p_ka = _hp(k_active, np.int32)
-    wm_a, p_wm = _hp(wind_mean, np.float64)
-    c_a, p_c = _hp(controls, np.float64)
+    st_a, p_st = _host(states, "states", (ctx.N, 6), np.float64)
+    ka_a, p_ka = _host(k_active, "k_active", (ctx.N,), np.int32)
+    wm_a, p_wm = _host(wind_mean, "wind_mean", (2,), np.float64)
+    c_a, p_c = _host(controls, "controls", (ctx.N, ctx.S, 3), np.float64)
     st_out = np.zeros((ctx.N, 6))
     ka_out = np.zeros(ctx.N, dtype=np.int32)
     ev = np.zeros(ctx.N, dtype=np.int32)
@@ -424,83 +488,121 @@ def rolling_window(ctx: Context, n_updates, plant_iter=None, states=None, k_acti
 # ---- kernel-level entry points (device tensors) -----------------------------
 
 def smc_k_philox(seed, mpc_step, iter_, purpose, scenario, e0, n, out, stream=None):
+    p_out = _ptr(_dev(out, "out", "u32", 4 * _count(n, "n")))
     _check(lib().smc_k_philox(int(seed) & 0xFFFFFFFFFFFFFFFF, int(mpc_step), int(iter_),
-                              int(purpose), int(scenario), int(e0), int(n), _ptr(out),
+                              int(purpose), int(scenario), int(e0), int(n), p_out,
                               _stream(stream)))
 
 
 def smc_k_init_particles(ctx, mpc_step, P, u, stream=None):
-    _check(lib().smc_k_init_particles(ctx.handle, int(mpc_step), int(P), _ptr(u),
+    p_u = _ptr(_dev(u, "u", ctx.real_dtype, _count(P) * ctx.D))
+    _check(lib().smc_k_init_particles(ctx.handle, int(mpc_step), int(P), p_u,
                                       _stream(stream)), ctx)
 
 
 def smc_k_wind_normals(ctx, mpc_step, iter_, Z, stream=None):
-    _check(lib().smc_k_wind_normals(ctx.handle, int(mpc_step), int(iter_), _ptr(Z),
+    p_z = _ptr(_dev(Z, "Z", ctx.real_dtype, ctx.G * 2 * ctx.M))
+    _check(lib().smc_k_wind_normals(ctx.handle, int(mpc_step), int(iter_), p_z,
                                     _stream(stream)), ctx)
 
 
 def smc_k_wind_gemm(ctx, Z, wind_mean, W, stream=None):
-    wm_a, p_wm = _hp(wind_mean, np.float64)
-    _check(lib().smc_k_wind_gemm(ctx.handle, _ptr(Z), p_wm, _ptr(W), _stream(stream)), ctx)
+    wm_a, p_wm = _host(wind_mean, "wind_mean", (2,), np.float64)
+    p_z, p_w = _ptrs(_dev(Z, "Z", ctx.real_dtype, ctx.G * 2 * ctx.M),
+                     _dev(W, "W", ctx.real_dtype, ctx.M * ctx.G * 2))
+    _check(lib().smc_k_wind_gemm(ctx.handle, p_z, p_wm, p_w, _stream(stream)), ctx)
 
 
 def smc_k_wind_factor(ctx, out, stream=None):
-    _check(lib().smc_k_wind_factor(ctx.handle, _ptr(out), _stream(stream)), ctx)
+    p_o = _ptr(_dev(out, "out", ctx.real_dtype, ctx.G * ctx.G))
+    _check(lib().smc_k_wind_factor(ctx.handle, p_o, _stream(stream)), ctx)
 
 
 def smc_k_wind_fields(ctx, mpc_step, it, wind_mean, W, stream=None):
-    wm_a, p_wm = _hp(wind_mean, np.float64)
-    _check(lib().smc_k_wind_fields(ctx.handle, int(mpc_step), int(it), p_wm, _ptr(W),
+    wm_a, p_wm = _host(wind_mean, "wind_mean", (2,), np.float64)
+    p_w = _ptr(_dev(W, "W", ctx.real_dtype, ctx.Mf * ctx.G * 2))
+    _check(lib().smc_k_wind_fields(ctx.handle, int(mpc_step), int(it), p_wm, p_w,
                                    _stream(stream)), ctx)
 
 
 def smc_k_rollout(ctx, u, P, W, states, k_active, horizon, cost, feas, steps=None, stream=None):
-    _check(lib().smc_k_rollout(ctx.handle, _ptr(u), int(P), _ptr(W), _ptr(states),
-                               _ptr(k_active), int(horizon), _ptr(cost), _ptr(feas),
-                               _ptr(steps), _stream(stream)), ctx)
+    P = _count(P)
+    a = _ptrs(_dev(u, "u", ctx.real_dtype, P * ctx.D), _dev(W, "W", ctx.real_dtype, ctx.Mf * ctx.G * 2),
+         _dev(states, "states", "f64", ctx.N * 6), _dev(k_active, "k_active", "i32", ctx.N),
+         _dev(cost, "cost", "f64", ctx.M * P * ctx.N), _dev(feas, "feas", "u8", ctx.M * P * ctx.N),
+         _dev(steps, "steps", "u64", 128, optional=True))
+    _check(lib().smc_k_rollout(ctx.handle, a[0], P, a[1], a[2], a[3], int(horizon), a[4], a[5],
+                               a[6], _stream(stream)), ctx)
 
 
 def smc_k_reduce(ctx, P, cost, feas, beta, chat, feas_pn, logw, stream=None):
-    _check(lib().smc_k_reduce(ctx.handle, int(P), _ptr(cost), _ptr(feas), float(beta),
-                              _ptr(chat), _ptr(feas_pn), _ptr(logw), _stream(stream)), ctx)
+    P = _count(P)
+    a = _ptrs(_dev(cost, "cost", "f64", ctx.M * P * ctx.N), _dev(feas, "feas", "u8", ctx.M * P * ctx.N),
+         _dev(chat, "chat", "f64", P * ctx.N), _dev(feas_pn, "feas_pn", "u8", P * ctx.N),
+         _dev(logw, "logw", "f64", P * ctx.N))
+    _check(lib().smc_k_reduce(ctx.handle, P, a[0], a[1], float(beta), a[2], a[3], a[4],
+                              _stream(stream)), ctx)
 
 
 def smc_k_reduce_product(ctx, P, M, cost, feas, chat, feas_pn, logw, stream=None):
-    _check(lib().smc_k_reduce_product(ctx.handle, int(P), int(M), _ptr(cost), _ptr(feas),
-                                      _ptr(chat), _ptr(feas_pn), _ptr(logw), _stream(stream)), ctx)
+    P, M = _count(P), _count(M, "M")
+    a = _ptrs(_dev(cost, "cost", "f64", M * P * ctx.N), _dev(feas, "feas", "u8", M * P * ctx.N),
+         _dev(chat, "chat", "f64", P * ctx.N), _dev(feas_pn, "feas_pn", "u8", P * ctx.N),
+         _dev(logw, "logw", "f64", P * ctx.N))
+    _check(lib().smc_k_reduce_product(ctx.handle, P, M, a[0], a[1], a[2], a[3], a[4],
+                                      _stream(stream)), ctx)
 
 
 def smc_k_resample_offsets(ctx, mpc_step, iter_, U, stream=None):
-    _check(lib().smc_k_resample_offsets(ctx.handle, int(mpc_step), int(iter_), _ptr(U),
+    p_u = _ptr(_dev(U, "U", "u32", ctx.N))
+    _check(lib().smc_k_resample_offsets(ctx.handle, int(mpc_step), int(iter_), p_u,
                                         _stream(stream)), ctx)
 
 
 def smc_k_resample(ctx, P, logw, U, anc, ess=None, stream=None):
-    _check(lib().smc_k_resample(ctx.handle, int(P), _ptr(logw), _ptr(U), _ptr(anc), _ptr(ess),
-                                _stream(stream)), ctx)
+    P = _count(P)
+    a = _ptrs(_dev(logw, "logw", "f64", P * ctx.N), _dev(U, "U", "u32", ctx.N),
+         _dev(anc, "anc", "i32", ctx.N * P), _dev(ess, "ess", "f64", ctx.N, optional=True))
+    _check(lib().smc_k_resample(ctx.handle, P, a[0], a[1], a[2], a[3], _stream(stream)), ctx)
 
 
 def smc_k_gather_move(ctx, P, u_in, anc, u_out, mpc_step, iter_, jitter, stream=None):
-    _check(lib().smc_k_gather_move(ctx.handle, int(P), _ptr(u_in), _ptr(anc), _ptr(u_out),
-                                   int(mpc_step), int(iter_), int(jitter), _stream(stream)), ctx)
+    P = _count(P)
+    a = _ptrs(_dev(u_in, "u_in", ctx.real_dtype, P * ctx.D), _dev(anc, "anc", "i32", ctx.N * P),
+         _dev(u_out, "u_out", ctx.real_dtype, P * ctx.D))
+    _check(lib().smc_k_gather_move(ctx.handle, P, a[0], a[1], a[2], int(mpc_step), int(iter_),
+                                   int(jitter), _stream(stream)), ctx)
 
 
 def smc_k_propose(ctx, P, u, u_prop, mpc_step, iter_, stream=None):
-    _check(lib().smc_k_propose(ctx.handle, int(P), _ptr(u), _ptr(u_prop), int(mpc_step),
-                               int(iter_), _stream(stream)), ctx)
+    P = _count(P)
+    a = _ptrs(_dev(u, "u", ctx.real_dtype, P * ctx.D), _dev(u_prop, "u_prop", ctx.real_dtype, P * ctx.D))
+    _check(lib().smc_k_propose(ctx.handle, P, a[0], a[1], int(mpc_step), int(iter_),
+                               _stream(stream)), ctx)
+
+
+def _pn_args(ctx, P, chat, chat_prop, feas_pn, feas_prop, logw, logw_prop):
+    n = P * ctx.N
+    return (_dev(chat, "chat", "f64", n), _dev(chat_prop, "chat_prop", "f64", n),
+            _dev(feas_pn, "feas_pn", "u8", n), _dev(feas_prop, "feas_prop", "u8", n),
+            _dev(logw, "logw", "f64", n), _dev(logw_prop, "logw_prop", "f64", n))
 
 
 def smc_k_accept(ctx, P, u, u_prop, chat, chat_prop, feas_pn, feas_prop, logw, logw_prop,
                  mpc_step, iter_, accepted=None, stream=None):
-    _check(lib().smc_k_accept(ctx.handle, int(P), _ptr(u), _ptr(u_prop), _ptr(chat),
-                              _ptr(chat_prop), _ptr(feas_pn), _ptr(feas_prop), _ptr(logw),
-                              _ptr(logw_prop), int(mpc_step), int(iter_), _ptr(accepted),
+    P = _count(P)
+    a = _ptrs(_dev(u, "u", ctx.real_dtype, P * ctx.D), _dev(u_prop, "u_prop", ctx.real_dtype, P * ctx.D),
+              *_pn_args(ctx, P, chat, chat_prop, feas_pn, feas_prop, logw, logw_prop),
+              _dev(accepted, "accepted", "i32", P, optional=True))
+    _check(lib().smc_k_accept(ctx.handle, P, *a[:8], int(mpc_step), int(iter_), a[8],
                               _stream(stream)), ctx)
 
 
 def smc_k_select(ctx, P, logw, chat, beta, best, stream=None):
-    _check(lib().smc_k_select(ctx.handle, int(P), _ptr(logw), _ptr(chat), float(beta),
-                              _ptr(best), _stream(stream)), ctx)
+    P = _count(P)
+    a = _ptrs(_dev(logw, "logw", "f64", P * ctx.N), _dev(chat, "chat", "f64", P * ctx.N),
+         _dev(best, "best", "i32", 2))
+    _check(lib().smc_k_select(ctx.handle, P, a[0], a[1], float(beta), a[2], _stream(stream)), ctx)
 
 
 def smc_set_rollout_layout(ctx, layout):
@@ -509,22 +611,31 @@ def smc_set_rollout_layout(ctx, layout):
 
 
 def smc_k_rollout_grad(ctx, u, P, W, states, k_active, horizon, grad, stream=None):
-    _check(lib().smc_k_rollout_grad(ctx.handle, _ptr(u), int(P), _ptr(W), _ptr(states),
-                                    _ptr(k_active), int(horizon), _ptr(grad), _stream(stream)), ctx)
+    P = _count(P)
+    a = _ptrs(_dev(u, "u", ctx.real_dtype, P * ctx.D), _dev(W, "W", ctx.real_dtype, ctx.Mf * ctx.G * 2),
+         _dev(states, "states", "f64", ctx.N * 6), _dev(k_active, "k_active", "i32", ctx.N),
+         _dev(grad, "grad", "f64", P * ctx.D))
+    _check(lib().smc_k_rollout_grad(ctx.handle, a[0], P, a[1], a[2], a[3], int(horizon), a[4],
+                                    _stream(stream)), ctx)
 
 
 def smc_k_mala_propose(ctx, P, u, grad, beta, u_prop, mpc_step, iter_, stream=None):
-    _check(lib().smc_k_mala_propose(ctx.handle, int(P), _ptr(u), _ptr(grad), float(beta),
-                                    _ptr(u_prop), int(mpc_step), int(iter_), _stream(stream)), ctx)
+    P = _count(P)
+    a = _ptrs(_dev(u, "u", ctx.real_dtype, P * ctx.D), _dev(grad, "grad", "f64", P * ctx.D),
+         _dev(u_prop, "u_prop", ctx.real_dtype, P * ctx.D))
+    _check(lib().smc_k_mala_propose(ctx.handle, P, a[0], a[1], float(beta), a[2], int(mpc_step),
+                                    int(iter_), _stream(stream)), ctx)
 
 
 def smc_k_mala_accept(ctx, P, u, u_prop, grad, grad_prop, beta, chat, chat_prop, feas_pn,
                       feas_prop, logw, logw_prop, mpc_step, iter_, accepted, stream=None):
-    _check(lib().smc_k_mala_accept(ctx.handle, int(P), _ptr(u), _ptr(u_prop), _ptr(grad),
-                                   _ptr(grad_prop), float(beta), _ptr(chat), _ptr(chat_prop),
-                                   _ptr(feas_pn), _ptr(feas_prop), _ptr(logw), _ptr(logw_prop),
-                                   int(mpc_step), int(iter_), _ptr(accepted), _stream(stream)),
-           ctx)
+    P = _count(P)
+    a = _ptrs(_dev(u, "u", ctx.real_dtype, P * ctx.D), _dev(u_prop, "u_prop", ctx.real_dtype, P * ctx.D),
+              _dev(grad, "grad", "f64", P * ctx.D), _dev(grad_prop, "grad_prop", "f64", P * ctx.D),
+              *_pn_args(ctx, P, chat, chat_prop, feas_pn, feas_prop, logw, logw_prop),
+              _dev(accepted, "accepted", "i32", P))
+    _check(lib().smc_k_mala_accept(ctx.handle, P, a[0], a[1], a[2], a[3], float(beta), *a[4:10],
+                                   int(mpc_step), int(iter_), a[10], _stream(stream)), ctx)
 
 
 # ---- batched form (include/smc_batch.h) --------------------------------------
@@ -595,8 +706,11 @@ def _batch_inputs(b: Batch, states, k_active, wind_mean, horizons):
     k_active = np.concatenate([s["k_active"] for s in sc]) if k_active is None else k_active
     wind_mean = np.stack([s["wind_mean"] for s in sc]) if wind_mean is None else wind_mean
     horizons = np.array(b.H) if horizons is None else horizons
-    return (_hp(states, np.float64), _hp(k_active, np.int32), _hp(wind_mean, np.float64),
-            _hp(horizons, np.int32))
+    rows = int(b.row_off[-1])
+    return (_host(states, "states", (rows, 6), np.float64),
+            _host(k_active, "k_active", (rows,), np.int32),
+            _host(wind_mean, "wind_mean", (b.ns, 2), np.float64),
+            _host(horizons, "horizons", (b.ns,), np.int32))
 
 
 def smc_batch_step(b: Batch, mpc_step=0, states=None, k_active=None, wind_mean=None,
@@ -620,11 +734,15 @@ def smc_batch_step_dev(b: Batch, mpc_step, states, k_active, wind_mean, horizons
                        cost_out, status_out=None, want_info=False, stream=None):
     """Device form: states [sum N, 6] f64, k_active [sum N] i32 and the
     outputs are device tensors; wind_mean [n_scen, 2] and horizons are host."""
-    wm_a, p_wm = _hp(wind_mean, np.float64)
-    h_a, p_h = _hp(horizons, np.int32)
+    wm_a, p_wm = _host(wind_mean, "wind_mean", (b.ns, 2), np.float64)
+    h_a, p_h = _host(horizons, "horizons", (b.ns,), np.int32)
+    rows = int(b.row_off[-1])
+    a = _ptrs(_dev(states, "states", "f64", rows * 6), _dev(k_active, "k_active", "i32", rows),
+         _dev(controls_out, "controls_out", "f64", int(b.ctrl_off[-1])),
+         _dev(cost_out, "cost_out", "f64", int(b.cost_off[-1])),
+         _dev(status_out, "status_out", "i32", b.ns, optional=True))
     info = BatchInfo() if want_info else None
-    r = lib().smc_batch_step_dev(b.handle, int(mpc_step), _ptr(states), _ptr(k_active), p_wm,
-                                 p_h, _ptr(controls_out), _ptr(cost_out), _ptr(status_out),
+    r = lib().smc_batch_step_dev(b.handle, int(mpc_step), a[0], a[1], p_wm, p_h, a[2], a[3], a[4],
                                  C.byref(info) if info is not None else None, _stream(stream))
     _bcheck(r, b)
     return r, (info.as_dict() if info is not None else None)

@@ -491,6 +491,7 @@ const char* smc_batch_last_error(const smc_batch* b) {
 
 void smc_batch_destroy(smc_batch* b) {
     if (!b) return;
+    (void)hipDeviceSynchronize();   // device-form calls may be queued on caller streams
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
     for (void* p : b->bufs) (void)hipFree(p);
@@ -763,7 +764,9 @@ smc_status smc_batch_step_dev(smc_batch* b, int64_t mpc_step, const double* d_st
     if (!b) return bfail(nullptr, SMC_EINVAL, "batch is NULL");
     if (!d_states || !d_k_active || !d_controls_out || !d_exp_cost_out)
         return bfail(b, SMC_EINVAL, "NULL device pointer");
-    hipStream_t st = stream ? (hipStream_t)stream : b->stream;
+    // NULL is the null (legacy default) stream: ordered with the caller's
+    // default-stream work, as in the single-scenario device form
+    hipStream_t st = (hipStream_t)stream;
     smc_status r = run_update(b, mpc_step, d_states, d_k_active, true, wind_mean, horizons, info, st);
     if (r < 0) return r;
     BHIP(b, hipMemcpyAsync(d_controls_out, b->d_ctrl, sizeof(double) * b->off_ctrl[b->ns],

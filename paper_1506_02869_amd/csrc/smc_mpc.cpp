@@ -131,7 +131,12 @@ smc_status dalloc_t(smc_ctx* c, T** p, size_t count) {
     return s;
 }
 
-hipStream_t pick(smc_ctx* c, void* stream) { return stream ? (hipStream_t)stream : c->stream; }
+// Stream of a device-form call: the caller's handle as given.  NULL is the
+// null (legacy default) stream, which every blocking stream orders with, so a
+// caller that queues its inputs on its default stream (PyTorch's default
+// stream has the handle 0) sees them written before the library reads them,
+// and its later work waits for the library's outputs.
+hipStream_t pick(smc_ctx*, void* stream) { return (hipStream_t)stream; }
 
 double beta_of(const smc_ctx* c, int J) { return c->kappa * host::sample_schedule(J); }
 
@@ -695,6 +700,9 @@ const char* smc_last_error(const smc_ctx* ctx) {
 
 void smc_destroy(smc_ctx* c) {
     if (!c) return;
+    // device-form calls queue on the caller's streams: wait for all of them
+    // before the buffers go
+    (void)hipDeviceSynchronize();
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto& b : c->bufs) (void)hipFree(b.p);
     for (hipEvent_t e : c->ev_roll) (void)hipEventDestroy(e);

@@ -136,6 +136,8 @@ def test_batch_device_form_and_streams(lib):
         lib.smc_batch_set_graph(b, use_graph)
         for want_info in (False, True):
             ctrl.fill_(-1.0)
+            # the fill and the inputs were queued on the default stream
+            st.wait_stream(torch.cuda.current_stream())
             with torch.cuda.stream(st):
                 lib.smc_batch_step_dev(b, 4, states, kact, wm, hz, ctrl, cost, status,
                                        want_info=want_info, stream=st)

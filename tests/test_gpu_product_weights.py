@@ -77,6 +77,9 @@ def test_reduce_product_matches_oracle(lib, M):
     assert np.array_equal(np.isfinite(gl), np.isfinite(rl))
     fin = np.isfinite(rl)
     assert np.all(np.abs(gl[fin] - rl[fin]) <= 1e-14 * np.maximum(np.abs(rl[fin]), 1.0))
+    # more passes than the context's samples: refused by the library (the
+    # buffers are sized for them, so the binding's size checks pass)
+    big = np.zeros((s["M"] + 1,) + cost.shape[1:])
     with pytest.raises(lib.SmcError):
-        lib.smc_k_reduce_product(ctx, P, s["M"] + 1, dev(cost), dev(feas.astype(np.uint8)),
+        lib.smc_k_reduce_product(ctx, P, s["M"] + 1, dev(big), dev(big.astype(np.uint8)),
                                  chat, fpn, logw)
