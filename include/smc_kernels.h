@@ -123,6 +123,22 @@ smc_status smc_k_resample(smc_ctx* ctx, int32_t P, const double* logw,
                           const uint32_t* U, int32_t* anc, double* ess,
                           void* stream);
 
+/* The same resampling with no allocation and no context, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the prefix-scan workspace
+ * is a static device array of 2^22 doubles (32 MiB) that each device holds
+ * from the first call on it until the process ends; the call makes no
+ * hipMalloc / hipFree and no allocating library call.  N in [1, 64], P >= 1,
+ * N * P <= 2^22 (SMC_EINVAL otherwise, message in smc_last_error(NULL)).
+ * Arguments and results as smc_k_resample (logw [P][N], U [N], anc [N][P],
+ * ess [N] or NULL; device pointers; stream NULL = the null stream).  Every
+ * call on a device shares its workspace: calls that may overlap on one
+ * device (different streams, threads) race and must be serialised by the
+ * caller. */
+smc_status smc_k_resample_noalloc(int32_t N, int32_t P, const double* logw,
+                                  const uint32_t* U, int32_t* anc, double* ess,
+                                  void* stream);
+
 /* Gather by ancestors, then (if jitter != 0) the paper's Gaussian white-noise
  * perturbation u += sigma_move xi (MOVE stream of `iter`), clamped to [0, 1]
  * (Alg. 1 resample / perturb).  u_in, u_out [P][N][S][3] real (distinct). */
@@ -189,12 +205,20 @@ smc_status smc_k_mala_accept(smc_ctx* ctx, int32_t P, void* u, const void* u_pro
                              int32_t* accepted, void* stream);
 
 /* Rollout kernel layout used by every pass of this context:
- *  0 automatic (world-per-lane for N <= 16, aircraft-per-lane above),
+ *  0 automatic (world-per-lane for N <= 20; above, particle-per-wave in
+ *    FP32 and aircraft-per-lane in FP64),
  *  1 aircraft-per-lane: one lane per (particle, sample, aircraft), the world's
  *    aircraft in consecutive lanes of a wavefront, positions exchanged in LDS;
  *  2 world-per-lane: one lane per (particle, sample) holding all N aircraft
- *    in registers (N <= 16).
- * Both compute the same rollout; SMC_EINVAL for an unsupported choice. */
+ *    in registers (N <= 20);
+ *  3 particle-per-wave (FP32, N <= 64): the lanes of a wavefront are 64 wind
+ *    samples of one particle; each aircraft's wind-independent step (speed,
+ *    thrust, fuel, mass, altitude, heading, unary checks) is computed once
+ *    per particle and step, and only pairs within the vertical separation
+ *    get the horizontal test (exact: the altitudes do not depend on the
+ *    wind).  Uses the context's workspace for a sample-interleaved copy of
+ *    the fields, so calls on one context must run in stream order.
+ * All compute the same rollout; SMC_EINVAL for an unsupported choice. */
 smc_status smc_set_rollout_layout(smc_ctx* ctx, int32_t layout);
 
 #ifdef __cplusplus

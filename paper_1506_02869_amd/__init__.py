@@ -140,6 +140,7 @@ _SIGS = {
     "smc_k_reduce_product": (C.c_int, [_VP, C.c_int32, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
     "smc_k_resample_offsets": (C.c_int, [_VP, C.c_int64, C.c_int32, _VP, _VP]),
     "smc_k_resample": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
+    "smc_k_resample_noalloc": (C.c_int, [C.c_int32, C.c_int32, _VP, _VP, _VP, _VP, _VP]),
     "smc_k_gather_move": (C.c_int, [_VP, C.c_int32, _VP, _VP, _VP, C.c_int64, C.c_int32,
                                     C.c_int32, _VP]),
     "smc_k_propose": (C.c_int, [_VP, C.c_int32, _VP, _VP, C.c_int64, C.c_int32, _VP]),
@@ -564,6 +565,15 @@ def smc_k_resample(ctx, P, logw, U, anc, ess=None, stream=None):
     a = _ptrs(_dev(logw, "logw", "f64", P * ctx.N), _dev(U, "U", "u32", ctx.N),
          _dev(anc, "anc", "i32", ctx.N * P), _dev(ess, "ess", "f64", ctx.N, optional=True))
     _check(lib().smc_k_resample(ctx.handle, P, a[0], a[1], a[2], a[3], _stream(stream)), ctx)
+
+
+def smc_k_resample_noalloc(N, P, logw, U, anc, ess=None, stream=None):
+    """Context-free resampling with the library's static scan workspace
+    (no device allocation; include/smc_kernels.h)."""
+    N, P = _count(N, "N"), _count(P)
+    a = _ptrs(_dev(logw, "logw", "f64", P * N), _dev(U, "U", "u32", N),
+              _dev(anc, "anc", "i32", N * P), _dev(ess, "ess", "f64", N, optional=True))
+    _check(lib().smc_k_resample_noalloc(N, P, a[0], a[1], a[2], a[3], _stream(stream)))
 
 
 def smc_k_gather_move(ctx, P, u_in, anc, u_out, mpc_step, iter_, jitter, stream=None):

@@ -155,6 +155,14 @@ hipError_t launch_wind_gemm(int prec, const void* Lfac, const void* Z,
 hipError_t launch_rollout(int prec, const RolloutParams& p,
                           const RolloutArrays& a, hipStream_t st);
 bool rollout_wm_supported(int N);
+// Particle-per-wave rollout (FP32, N <= 64): the 64 lanes of a wave are 64
+// wind samples of one particle; Wt holds the fields sample-interleaved,
+// [G][M][2] (launch_wind_transpose).
+bool rollout_pw_supported(int N, int prec);
+hipError_t launch_rollout_pw(const RolloutParams& p, const RolloutArrays& a, const void* acR,
+                             const void* Wt, hipStream_t st);
+// W[M][G][2] -> Wt[G][M][2] (pairs of reals), coalesced through LDS tiles.
+hipError_t launch_wind_transpose(int prec, const void* W, int M, int G, void* Wt, hipStream_t st);
 // acR: [N][kAcR] real: wing area, C_D0, C_D2, dt C_f1, dt C_f1 / C_f2,
 // T_max, empty mass, tan(phi_max), sin(gamma_max), theta_F, Z, v_D, D_TMA,
 // (1 - alpha_time - alpha_noise) w_speed / speed span, kind (0 arrival,
@@ -200,6 +208,12 @@ hipError_t launch_resample_offsets(Stream s, int N, uint32_t* U, hipStream_t st)
 hipError_t launch_resample(int P, int N, const double* logw, const uint32_t* U,
                            double* scan, int32_t* anc, double* ess,
                            hipStream_t st);
+// The same with the scan workspace in a static device array (no
+// allocation): P N <= kStaticScanDoubles, else hipErrorInvalidValue.
+constexpr int64_t kStaticScanDoubles = int64_t(1) << 22;
+constexpr int kMaxDevices = 64;
+hipError_t launch_resample_static(int P, int N, const double* logw, const uint32_t* U,
+                                  int32_t* anc, double* ess, hipStream_t st);
 hipError_t launch_gather_move(int prec, int P, int N, int D, const void* u_in,
                               const int32_t* anc, void* u_out, Stream s,
                               double sigma, int jitter, hipStream_t st);

@@ -496,20 +496,25 @@ bool grad_supported(int H, int S) {
     return S <= GR_MAXS && (H + GR_CK - 1) / GR_CK <= GR_MAXSEG;
 }
 
+hipError_t launch_wind_transpose(int prec, const void* W, int M, int G, void* Wt, hipStream_t st) {
+    if (M <= 0 || G <= 0) return hipSuccess;
+    const dim3 tg((unsigned)((G + 31) / 32), (unsigned)((M + 31) / 32));
+    if (prec == 0)
+        hipLaunchKernelGGL(k_wind_transpose<double>, tg, dim3(256), 0, st, (const double2*)W, M, G,
+                           (double2*)Wt);
+    else
+        hipLaunchKernelGGL(k_wind_transpose<float>, tg, dim3(256), 0, st, (const float2*)W, M, G,
+                           (float2*)Wt);
+    return hipGetLastError();
+}
+
 hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u, const void* W,
                                const double* states, const int32_t* k_active, const double* acpar,
                                const double* targets, const int8_t* kind, void* Wt, double* partial,
                                double* grad_out, hipStream_t st) {
     if (!grad_supported(rp.H, rp.S)) return hipErrorInvalidValue;
     {
-        const dim3 tg((unsigned)((rp.G + 31) / 32), (unsigned)((rp.M + 31) / 32));
-        if (prec == 0)
-            hipLaunchKernelGGL(k_wind_transpose<double>, tg, dim3(256), 0, st, (const double2*)W,
-                               rp.M, rp.G, (double2*)Wt);
-        else
-            hipLaunchKernelGGL(k_wind_transpose<float>, tg, dim3(256), 0, st, (const float2*)W,
-                               rp.M, rp.G, (float2*)Wt);
-        const hipError_t e = hipGetLastError();
+        const hipError_t e = launch_wind_transpose(prec, W, rp.M, rp.G, Wt, st);
         if (e != hipSuccess) return e;
     }
     GradParams gp;

@@ -1,0 +1,422 @@
+// Rollout, particle-per-wave layout (FP32, 21 .. 64 aircraft): the 64 lanes
+// of a wavefront are 64 wind samples of ONE particle, so every lane flies
+// the same control sequences through its own wind field.
+//
+// The per-step arithmetic is that of the other layouts (paper, Sec.
+// "Trajectory Planning", eq. hor; Sec. "Constraint Handling"; eq. TO_init;
+// Sec. "Particle Costing", "Noise Pollution Reduction"; eq. avoidance).
+// What the layout exploits: in the model the wind moves an aircraft only
+// horizontally (x, y); its airspeed ramp, climb, heading, bank, density,
+// drag, thrust, fuel flow and mass, and with them every unary constraint,
+// the altitude-dependent cost elements and the altitude itself, are the
+// same in all wind samples of a particle until the aircraft lands in one of
+// them.  So each step has two phases:
+//   1. lanes i < N each compute aircraft i's wind-independent step once for
+//      the particle and store a small record in LDS (one wavefront's slice);
+//   2. every lane (one world = one wind sample) runs the aircraft in turn,
+//      reading the record by a broadcast LDS load: trilinear wind at its own
+//      position, horizontal Euler update, landing test and the horizontal
+//      cost elements.
+// Separation (eq. avoidance) needs |dz| < sep_v AND dh < sep_h.  The
+// altitudes are wave-uniform, so the vertical test of every pair is one
+// ballot per aircraft over the phase-1 lanes; only pairs inside sep_v (a
+// uniform bit mask) get the horizontal test, which reads the partner's
+// position from registers by a uniform dynamic index (two vector halves of
+// at most 32, indexed through the GPR index mode).  Skipping the other pairs
+// is exact: their |dz| is at least sep_v in the same FP32 arithmetic.
+// An aircraft that has landed in a world is parked far away (x = kGoneX +
+// i kGoneDX) from the next step on, so the horizontal test needs no
+// presence check.
+// The fuel element is folded into the per-step sum: each simulated step adds
+// (1 - alpha_time - alpha_noise) w_fuel fuel_k / (dt T_max eta(v_max)), so
+// the element sum over the steps divided by their number is the fuel
+// element plus the mean of the other elements.
+#include "rollout_math.h"
+
+namespace smc {
+
+namespace {
+
+typedef float v32f __attribute__((ext_vector_type(32)));
+template <int NB> struct PwHalf { typedef float t __attribute__((ext_vector_type(NB))); };
+
+constexpr int kPwWaves = 4;     // wavefronts per workgroup (independent)
+constexpr int kPwRec = 16;      // floats of an aircraft-step record
+constexpr int kPwPar = 24;      // floats of an aircraft parameter row
+
+// record fields (phase 1 -> phase 2)
+enum : int {
+    R_VX = 0, R_VY, R_ZN, R_CHIN, R_GZ, R_TZ, R_UDEP, R_IVT, R_NA, R_FUEL, R_FLAGS
+};
+// parameter row fields (LDS, whole workgroup)
+enum : int {
+    A_SW = 0, A_CD0, A_CD2, A_CF, A_CFV, A_TMAX, A_MEMP, A_TPHI, A_SGAM, A_THF, A_ZT, A_VD,
+    A_DTMA, A_CSPD, A_CFUEL, A_M0, A_D0, A_Z0, A_V0, A_CHI0, A_K0
+};
+constexpr uint32_t F_VIOL = 1u, F_LANDOK = 2u, F_DEP = 4u;
+
+template <int NMAX>
+constexpr int pw_nb() { return NMAX <= 32 ? 8 : NMAX - 32; }
+// waves per SIMD the register budget is set for: the world state takes
+// 3 NMAX VGPRs (x, y and the cost sum of every aircraft)
+template <int NMAX>
+constexpr int pw_waves() { return NMAX <= 48 ? 2 : 1; }
+
+}  // namespace
+
+// One aircraft of phase 2 in every world of the wave (aircraft i, index ii
+// = i - 32 HI into the upper halves).  x, y, acc: this half's vectors;
+// xlo, ylo: the lower halves (pair partners below 32); masks per half.
+template <bool HI, typename VX>
+__device__ __forceinline__ void pw_aircraft(
+    const RolloutParams& p, const RolloutArrays& a, const float* __restrict__ par,
+    const float* __restrict__ rec, const __amdgpu_buffer_rsrc_t wrs, int s_z, int s_y, int s_x,
+    int vbase, int M, int i, uint64_t actk, float zn_lane, VX& x, VX& y, VX& acc,
+    const v32f& xlo, const v32f& ylo, uint32_t done0, uint32_t& done, uint32_t& bad,
+    uint32_t& sepbad, uint32_t& sepbad_lo) {
+    typedef Ops<float> O;
+    const RollConst<float>& q = p.cf;
+    const int ii = HI ? i - 32 : i;
+    const uint32_t bit = 1u << ii;
+    const float4* r4 = reinterpret_cast<const float4*>(rec + i * kPwRec);
+    const float4 ra = r4[0], rb = r4[1], rc = r4[2];
+    // wave-uniform flags of the record, moved to a scalar register so that
+    // the arrival / departure choice is a uniform branch
+    const uint32_t flags = __builtin_amdgcn_readfirstlane(__float_as_uint(rc.z));
+    const bool wasdone = (done0 & bit) != 0u;
+    const float xi = x[ii], yi = y[ii];
+
+    // trilinear wind of this world's sample at (x, y, z)
+    const float fx = clampr(m_fma(xi, q.inv_hx, q.ox), 0.f, q.fnx1);
+    const float fy = clampr(m_fma(yi, q.inv_hy, q.oy), 0.f, q.fny1);
+    const float flx = m_floor(clampr(fx, 0.f, q.fnx2));
+    const float fly = m_floor(clampr(fy, 0.f, q.fny2));
+    const float tx = fx - flx, ty = fy - fly, tz = rb.y;
+    const int g = (int)m_fma(m_fma(flx, q.fny, fly), q.fnz, rb.x);
+    const int vo = g * (M * 8) + vbase;
+    typedef float F2 __attribute__((ext_vector_type(2)));
+    const F2 c000 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, 0, 0));
+    const F2 c001 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_z, 0));
+    const F2 c010 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_y, 0));
+    const F2 c011 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_y + s_z, 0));
+    const F2 c100 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_x, 0));
+    const F2 c101 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_x + s_z, 0));
+    const F2 c110 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_x + s_y, 0));
+    const F2 c111 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_x + s_y + s_z, 0));
+    const float a00x = c000.x + tz * (c001.x - c000.x), a00y = c000.y + tz * (c001.y - c000.y);
+    const float a01x = c010.x + tz * (c011.x - c010.x), a01y = c010.y + tz * (c011.y - c010.y);
+    const float a10x = c100.x + tz * (c101.x - c100.x), a10y = c100.y + tz * (c101.y - c100.y);
+    const float a11x = c110.x + tz * (c111.x - c110.x), a11y = c110.y + tz * (c111.y - c110.y);
+    const float b0x = a00x + ty * (a01x - a00x), b0y = a00y + ty * (a01y - a00y);
+    const float b1x = a10x + ty * (a11x - a10x), b1y = a10y + ty * (a11y - a10y);
+    const float wx = b0x + tx * (b1x - b0x);
+    const float wy = b0y + tx * (b1y - b0y);
+
+    const float xn = m_fma(q.dt, ra.x + wx, xi);
+    const float yn = m_fma(q.dt, ra.y + wy, yi);
+    const float zn = ra.z, chin = ra.w;
+    // geometry at the new state
+    const float r = O::sqrt(xn * xn + yn * yn);
+    const float theta = O::atan2(yn, xn);
+    const float tha = m_abs(theta);
+    float cst;
+    bool landed = false;
+    if (!(flags & F_DEP)) {   // arrival (uniform)
+        const float ratio = tha > 1e-4f ? tha * O::rcp(maxr(O::sin(tha), 1e-6f))
+                                        : 1.f + tha * tha * (1.f / 6.f);
+        const float s_arc = r * ratio;
+        const float beta = O::atan2(zn, s_arc);
+        landed = !wasdone & (r <= q.p_run) & (beta <= q.p_beta) & (tha <= q.p_chi) &
+                 ((flags & F_LANDOK) != 0u);
+        const float hdg = m_abs(wrap_angle<float>(chin - (Consts<float>::pi + 2.f * theta)));
+        const float tt = m_min(s_arc * rb.w, 1.f);
+        cst = landed ? 0.f : q.c_hdg * hdg + q.c_gl * m_abs(beta - q.beta_f) + q.a_time * tt;
+    } else {                  // departure
+        const float* pi_ = par + i * kPwPar;
+        const float brg = m_abs(wrap_angle<float>(theta - pi_[A_THF]));
+        const float tt = m_min(m_max(pi_[A_DTMA] - r, 0.f) * rb.w, 1.f);
+        cst = q.c_brg * brg + rb.z + q.a_time * tt;
+    }
+    if (p.use_noise) {
+        const float fpx = clampr(m_fma(xn, q.pop_inv_hx, q.pop_ox), 0.f, q.fpnx1);
+        const float fpy = clampr(m_fma(yn, q.pop_inv_hy, q.pop_oy), 0.f, q.fpny1);
+        const int px = min((int)fpx, p.pop_nx - 2), py = min((int)fpy, p.pop_ny - 2);
+        const float ux = fpx - (float)px, uy = fpy - (float)py;
+        const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)a.pop, (short)0, p.pop_nx * p.pop_ny * 4, 0x00020000);
+        const int po = (py * p.pop_nx + px) * 4;
+        const F2 p0 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(prs, po, 0, 0));
+        const F2 p1 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(prs, po, p.pop_nx * 4, 0));
+        const float pd = (1.f - ux) * (1.f - uy) * p0.x + ux * (1.f - uy) * p0.y +
+                         (1.f - ux) * uy * p1.x + ux * uy * p1.y;
+        if (!landed) cst += rc.x * pd;
+    }
+    const float ai = acc[ii];
+    acc[ii] = wasdone ? ai : ai + (cst + rc.y);
+    if (landed) done |= bit;
+    if (flags & F_VIOL) {     // uniform: a unary violation at this step
+        if (!wasdone) bad |= bit;
+    }
+    // parked from the step after landing on
+    const float xs = wasdone ? (float)kGoneX + (float)kGoneDX * (float)i : xn;
+    const float ys = wasdone ? yi : yn;
+    x[ii] = xs;
+    y[ii] = ys;
+
+    // separation against the aircraft already moved this step whose altitude
+    // is within sep_v (a uniform candidate mask)
+    const uint64_t vclose = __ballot(m_abs(zn_lane - zn) < q.sep_v);
+    const uint64_t cand = vclose & actk & ((1ull << i) - 1ull);
+    uint32_t c_lo = (uint32_t)cand;
+    while (c_lo) {
+        const int jj = __builtin_ctz(c_lo);
+        c_lo &= c_lo - 1u;
+        const float dx = xs - xlo[jj], dy = ys - ylo[jj];
+        const bool hit = dx * dx + dy * dy < q.sep_h2;
+        if (__builtin_expect(__ballot(hit) != 0ull, 0)) {
+            if (hit) { sepbad |= bit; sepbad_lo |= 1u << jj; }
+        }
+    }
+    if (HI) {
+        uint32_t c_hi = (uint32_t)(cand >> 32);
+        while (c_hi) {
+            const int jj = __builtin_ctz(c_hi);
+            c_hi &= c_hi - 1u;
+            const float dx = xs - x[jj], dy = ys - y[jj];
+            const bool hit = dx * dx + dy * dy < q.sep_h2;
+            if (__builtin_expect(__ballot(hit) != 0ull, 0)) {
+                if (hit) sepbad |= bit | (1u << jj);
+            }
+        }
+    }
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(64 * kPwWaves, pw_waves<NMAX>())
+k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restrict__ acR,
+             const float* __restrict__ Wt) {
+    typedef typename PwHalf<pw_nb<NMAX>()>::t vBf;
+    typedef Ops<float> O;
+    __shared__ __attribute__((aligned(16))) float par[NMAX * kPwPar];
+    __shared__ __attribute__((aligned(16))) float recs[kPwWaves * NMAX * kPwRec];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int N = p.N, S = p.S, H = p.H, M = p.M;
+    const int nmb = (M + 63) >> 6;                      // 64-sample blocks per particle
+    const int64_t wave = (int64_t)blockIdx.x * kPwWaves + wv;
+    const int64_t nwave = (int64_t)p.P * nmb;
+    const bool wvalid = wave < nwave;
+    const int l = wvalid ? (int)(wave / nmb) : 0;
+    const int m = (wvalid ? (int)(wave % nmb) : 0) * 64 + lane;
+    const bool valid = wvalid && m < M;
+    const RollConst<float>& q = p.cf;
+
+    // per-aircraft parameters for the workgroup (host constants from acR,
+    // the initial state and the fuel element's per-step coefficient)
+    if (tid < N) {
+        const int i = tid;
+        const float* c = acR + kAcR * i;
+        float* r = par + i * kPwPar;
+#pragma unroll
+        for (int f = 0; f < 14; ++f) r[f] = c[f];
+        const double* ac = a.acpar + 9 * i;
+        const double wf = a.kind[i] == 0 ? p.w[2] : p.w[4];
+        r[A_CFUEL] = (float)((1.0 - p.w[7] - p.w[8]) * wf /
+                             (p.dt * ac[5] * (ac[3] * (1.0 + p.vmax / ac[4]))));
+        const double* st = a.states + 6 * i;
+        r[A_M0] = (float)st[5];
+        r[A_D0] = fabsf(c[10] - (float)st[2]);
+        r[A_Z0] = (float)st[2];
+        r[A_V0] = (float)st[3];
+        r[A_CHI0] = (float)st[4];
+        r[A_K0] = __int_as_float(a.k_active[i]);
+    }
+    __syncthreads();
+
+    // phase-1 lane state: aircraft j = lane (j < N), wind-independent
+    const int j = lane < N ? lane : N - 1;
+    const float* pj = par + j * kPwPar;
+    float zj = pj[A_Z0], vj = pj[A_V0], chij = pj[A_CHI0], burnj = 0.f;
+    const int k0j = __float_as_int(pj[A_K0]);
+    const bool actj = lane < N && k0j >= 0 && k0j < H;
+    const bool arrj = a.kind[j] == 0;
+    const float* ubj = (const float*)a.u + ((int64_t)l * N + j) * S * 3;
+    float chidot = 0.f, vc = 0.f, zdot = 0.f;
+    float* recw = recs + wv * NMAX * kPwRec;
+
+    // phase-2 state: one world per lane, all aircraft; aircraft i < 32 in
+    // the lower halves, i >= 32 in the upper ones
+    v32f xa, ya, acca;
+    vBf xb, yb, accb;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const int ic = i < N ? i : 0;
+        xa[i] = (float)a.states[6 * ic];
+        ya[i] = (float)a.states[6 * ic + 1];
+        acca[i] = 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < pw_nb<NMAX>(); ++i) {
+        const int ic = i + 32 < N ? i + 32 : 0;
+        xb[i] = (float)a.states[6 * ic];
+        yb[i] = (float)a.states[6 * ic + 1];
+        accb[i] = 0.f;
+    }
+    uint32_t done_lo = 0u, done_hi = 0u, bad_lo = 0u, bad_hi = 0u, sep_lo = 0u, sep_hi = 0u;
+    int nsim = 0, npair = 0;
+
+    // field of this world's sample in the sample-interleaved layout
+    // Wt[g][m][c]: the corner (ix, iy, iz) of lane m sits at byte
+    // (g M + m) 8, the other corners at uniform offsets
+    const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)Wt, (short)0, p.G * M * 8, 0x00020000);
+    const int s_z = M * 8, s_y = p.nz * M * 8, s_x = p.ny * p.nz * M * 8;
+    const int vbase = m * 8;
+    const int nlo = N < 32 ? N : 32;
+
+    int s_cur = -1, k_end = 0;
+    for (int k = 0; k < H; ++k) {
+        if (k == k_end) {   // uniform: the next control segment
+            const int s = ++s_cur;
+            k_end = ((s + 1) * H + S - 1) / S;
+            chidot = q.lo[0] + ubj[s * 3 + 0] * q.span[0];
+            vc = q.lo[1] + ubj[s * 3 + 1] * q.span[1];
+            zdot = q.lo[2] + ubj[s * 3 + 2] * q.span[2];
+        }
+        // ---- phase 1: aircraft j's wind-independent step (lane j) ----
+        const bool act = actj && k >= k0j;
+        const uint64_t actk = __ballot(act);
+        float zn_lane;
+        {
+            const float inv_rem = O::rcp((float)(k_end - k));
+            const float sg = zdot * O::rcp(vj);
+            const float cg = O::sqrt(1.f - sg * sg);
+            const float tphi = vj * chidot * q.inv_g;
+            const float inv_cphi = O::sqrt(1.f + tphi * tphi);
+            const float zc = clampr(zj, 0.f, 11000.f);
+            const float rho = q.rho0 * O::pow_pos(1.f - q.isa_c * zc, q.isa_e);
+            const float qS = 0.5f * rho * vj * vj * pj[A_SW];
+            const float mass = pj[A_M0] - burnj;
+            const float CL = O::div(mass * q.g0 * inv_cphi, qS);
+            const float D = qS * (pj[A_CD0] + pj[A_CD2] * CL * CL);
+            const float dv = (vc - vj) * inv_rem;
+            const float vn = vj + dv;
+            const float T = mass * (dv * q.inv_dt + q.g0 * sg) + D;
+            const float fuel = m_fma(vj, pj[A_CFV], pj[A_CF]) * m_max(T, 0.f);
+            float sc, cc;
+            O::sincos(chij, &sc, &cc);
+            const float vcg = vj * cg;
+            const float zn = m_fma(q.dt, zdot, zj);
+            const float chin = m_fma(q.dt, chidot, chij);
+            const float mn = mass - fuel;
+            const bool viol = (T > pj[A_TMAX]) | (m_abs(tphi) >= pj[A_TPHI]) |
+                              (m_abs(sg) > pj[A_SGAM]) | (zn < q.zmin) | (zn > q.zmax) |
+                              (vn < q.vmin) | (vn > q.vmax) | (mn < pj[A_MEMP]);
+            // wind cell along z at the current altitude (shared by the worlds)
+            const float fz = clampr(zj * q.inv_hz, 0.f, q.fnz1);
+            const float flz = m_floor(clampr(fz, 0.f, q.fnz2));
+            const float ivt = q.inv_tnorm * O::rcp(maxr(vn, q.vmin));
+            float udep = 0.f;
+            bool landok = false;
+            if (arrj) {
+                landok = (m_abs(wrap_angle<float>(chin - Consts<float>::pi)) <= q.p_chi) &
+                         (vn <= q.p_vs);
+            } else {
+                const float span = q.zdm_dt * (float)max(k + 1 - k0j, 1);
+                const float sup = pj[A_D0] + span;
+                const float inf = m_max(pj[A_D0] - span, 0.f);
+                const float alt = clampr(O::div(m_abs(pj[A_ZT] - zn) - inf, sup - inf), 0.f, 1.f);
+                udep = q.c_alt * alt + pj[A_CSPD] * m_abs(vn - pj[A_VD]);
+            }
+            float na = 0.f;
+            if (p.use_noise) {
+                const float za = zn * q.inv_Ac;
+                na = q.a_noise * m_max(1.f - za * za, 0.f);
+            }
+            const uint32_t fl = (viol ? F_VIOL : 0u) | (landok ? F_LANDOK : 0u) |
+                                (arrj ? 0u : F_DEP);
+            wave_sync();   // the previous step's records were read
+            if (lane < N) {
+                float4* r4 = reinterpret_cast<float4*>(recw + lane * kPwRec);
+                r4[0] = make_float4(vcg * cc, vcg * sc, zn, chin);
+                r4[1] = make_float4(flz, fz - flz, udep, ivt);
+                r4[2] = make_float4(na, pj[A_CFUEL] * fuel, __uint_as_float(fl), 0.f);
+            }
+            zn_lane = zn;
+            if (act) { zj = zn; vj = vn; chij = chin; burnj = burnj + fuel; }
+            wave_sync();   // records visible to every lane
+        }
+
+        // ---- phase 2: every world runs the aircraft in turn ----
+        const uint32_t d0lo = done_lo, d0hi = done_hi;
+        for (int i = 0; i < nlo; ++i) {
+            if (!((actk >> i) & 1ull)) continue;                    // uniform
+            pw_aircraft<false>(p, a, par, recw, wrs, s_z, s_y, s_x, vbase, M, i, actk, zn_lane,
+                               xa, ya, acca, xa, ya, d0lo, done_lo, bad_lo, sep_lo, sep_lo);
+        }
+        if (NMAX > 32) {
+            for (int i = 32; i < N; ++i) {
+                if (!((actk >> i) & 1ull)) continue;                // uniform
+                pw_aircraft<true>(p, a, par, recw, wrs, s_z, s_y, s_x, vbase, M, i, actk, zn_lane,
+                                  xb, yb, accb, xa, ya, d0hi, done_hi, bad_hi, sep_hi, sep_lo);
+            }
+        }
+        {   // aircraft simulated this step and pair tests with both present
+            const uint64_t pres = actk & ~(((uint64_t)d0hi << 32) | d0lo);
+            const int np = __popcll(pres);
+            nsim += np;
+            npair += np * (np - 1) / 2;
+        }
+    }
+
+    if (valid) {
+        const uint64_t badm = ((uint64_t)(bad_hi | sep_hi) << 32) | (bad_lo | sep_lo);
+        for (int i = 0; i < N; ++i) {
+            const int k0 = a.k_active[i];
+            const float ai = i < 32 ? acca[i] : accb[(i - 32) & (pw_nb<NMAX>() - 1)];
+            const double cost = (k0 >= 0 && k0 < H) ? (double)ai / (double)(H - k0) : 0.0;
+            const int64_t o = ((int64_t)m * p.P + l) * N + i;
+            a.cost[o] = cost;
+            a.feas[o] = ((badm >> i) & 1ull) ? 0 : 1;
+        }
+    }
+    if (a.steps) {
+        int cnt = valid ? nsim : 0;
+        int cp = valid ? npair : 0;
+        for (int off = 32; off > 0; off >>= 1) {
+            cnt += __shfl_xor(cnt, off);
+            cp += __shfl_xor(cp, off);
+        }
+        if (lane == 0) {
+            const unsigned slot = (unsigned)(wave & (kStepSlots - 1));
+            if (cnt) atomicAdd(&a.steps[slot], (unsigned long long)cnt);
+            if (cp) atomicAdd(&a.steps[kStepSlots + slot], (unsigned long long)cp);
+        }
+    }
+}
+
+bool rollout_pw_supported(int N, int prec) { return prec == 1 && N >= 1 && N <= 64; }
+
+template <int NMAX>
+static hipError_t launch_pw_n(const RolloutParams& p, const RolloutArrays& a, const void* acR,
+                              const void* Wt, hipStream_t st) {
+    const int64_t nwave = (int64_t)p.P * ((p.M + 63) / 64);
+    const int64_t blocks = (nwave + kPwWaves - 1) / kPwWaves;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_rollout_pw<NMAX>), dim3((unsigned)blocks), dim3(64 * kPwWaves), 0, st,
+                       p, a, (const float*)acR, (const float*)Wt);
+    return hipGetLastError();
+}
+
+// Wt: the fields in the sample-interleaved layout [G][M][2] (FP32).
+hipError_t launch_rollout_pw(const RolloutParams& p, const RolloutArrays& a, const void* acR,
+                             const void* Wt, hipStream_t st) {
+    if (!rollout_pw_supported(p.N, 1) || p.w_kstride != 0) return hipErrorInvalidValue;
+    if (p.P <= 0 || p.M <= 0) return hipSuccess;
+    if ((int64_t)p.G * p.M * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    if (p.N <= 32) return launch_pw_n<32>(p, a, acR, Wt, st);
+    if (p.N <= 40) return launch_pw_n<40>(p, a, acR, Wt, st);
+    if (p.N <= 48) return launch_pw_n<48>(p, a, acR, Wt, st);
+    return launch_pw_n<64>(p, a, acR, Wt, st);
+}
+
+}  // namespace smc

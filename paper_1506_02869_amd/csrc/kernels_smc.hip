@@ -1,5 +1,7 @@
 // SMC weighting, resampling and selection kernels (Alg. 1; Sec. "Weight
 // Scaling", "Particle Resampling and Perturbation", "Final Sample Selection").
+#include <mutex>
+
 #include "smc_steps.h"
 
 namespace smc {
@@ -102,6 +104,43 @@ hipError_t launch_resample(int P, int N, const double* logw, const uint32_t* U, 
     hipLaunchKernelGGL(k_resample, dim3(N), dim3(RS_THREADS), 0, st, P, N, logw, U, scan, anc,
                        ess);
     return hipGetLastError();
+}
+
+// ---- resampling with a static workspace ------------------------------------
+// The prefix-scan workspace of smc_k_resample_noalloc: a file-scope device
+// array, so the call allocates nothing.  Each device holds its own copy
+// (32 MiB) from the library's first use on it until the process ends.  Host
+// code never passes the array's name to a kernel (in host code it is a
+// host-side stand-in): the device address comes from hipGetSymbolAddress,
+// once per device, with that device current.  The scan is written in full
+// before it is read, so nothing needs clearing between calls; calls that
+// overlap on one device share the array and race.
+static __device__ __align__(256) double scratch[kStaticScanDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t launch_resample_static(int P, int N, const double* logw, const uint32_t* U,
+                                  int32_t* anc, double* ess, hipStream_t st) {
+    if (P < 1 || N < 1 || (int64_t)P * N > kStaticScanDoubles) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    double* scan = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_dev[dev]) {
+            void* p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            g_scratch_dev[dev] = static_cast<double*>(p);
+        }
+        scan = g_scratch_dev[dev];
+    }
+    return launch_resample(P, N, logw, U, scan, anc, ess, st);
 }
 
 hipError_t launch_select(int P, int N, const double* logw, const double* chat, double beta,

@@ -55,7 +55,8 @@ struct smc_ctx {
     // device buffers
     double *d_acpar = nullptr, *d_targets = nullptr;
     void* d_acR = nullptr;       // [N][kAcR] per-aircraft parameters, real
-    int layout = 0;              // rollout layout: 0 auto, 1 aircraft/lane, 2 world/lane
+    int layout = 0;              // rollout layout: 0 auto, 1 aircraft/lane, 2 world/lane,
+                                 // 3 particle/wave
     int8_t* d_kind = nullptr;
     float* d_pop = nullptr;
     void* d_Lfac = nullptr;
@@ -278,14 +279,28 @@ RolloutArrays rollout_arrays(smc_ctx* c, const void* u, const void* W, const dou
     return a;
 }
 
-// The rollout launch behind every pass: world-per-lane when N allows it
-// (or when asked), aircraft-per-lane otherwise.
+// The rollout launch behind every pass: world-per-lane when N allows it,
+// particle-per-wave above that in FP32 (after a copy of the fields into the
+// sample-interleaved layout the wave's lanes read), aircraft-per-lane
+// otherwise; or the layout asked for.
+int rollout_layout(const smc_ctx* c) {
+    if (c->layout != 0) return c->layout;
+    if (rollout_wm_supported(c->N)) return 2;
+    return rollout_pw_supported(c->N, c->prec) ? 3 : 1;
+}
+
 hipError_t do_rollout(smc_ctx* c, const RolloutParams& rp, const RolloutArrays& a,
                       hipStream_t st) {
     if (rp.w_kstride != 0) return launch_rollout_wm_tv(c->prec, rp, a, c->d_acR, st);
-    const bool wm = c->layout == 2 || (c->layout == 0 && rollout_wm_supported(c->N));
-    if (wm) return launch_rollout_wm(c->prec, rp, a, c->d_acR, st);
-    return launch_rollout(c->prec, rp, a, st);
+    switch (rollout_layout(c)) {
+    case 2: return launch_rollout_wm(c->prec, rp, a, c->d_acR, st);
+    case 3: {
+        const hipError_t e = launch_wind_transpose(c->prec, a.W, rp.M, rp.G, c->d_Wt, st);
+        if (e != hipSuccess) return e;
+        return launch_rollout_pw(rp, a, c->d_acR, c->d_Wt, st);
+    }
+    default: return launch_rollout(c->prec, rp, a, st);
+    }
 }
 
 smc_status check_horizon(smc_ctx* c, int32_t horizon) {
@@ -1100,6 +1115,20 @@ smc_status smc_k_resample(smc_ctx* c, int32_t P, const double* logw, const uint3
     return SMC_OK;
 }
 
+smc_status smc_k_resample_noalloc(int32_t N, int32_t P, const double* logw, const uint32_t* U,
+                                  int32_t* anc, double* ess, void* stream) {
+    if (!logw || !U || !anc || N < 1 || N > SMC_MAX_AIRCRAFT || P < 1)
+        return fail(nullptr, SMC_EINVAL, "smc_k_resample_noalloc: bad arguments");
+    if ((int64_t)N * P > kStaticScanDoubles)
+        return fail(nullptr, SMC_EINVAL,
+                    "smc_k_resample_noalloc: N * P = %lld exceeds the static workspace of %lld",
+                    (long long)N * P, (long long)kStaticScanDoubles);
+    const hipError_t e = launch_resample_static(P, N, logw, U, anc, ess, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(nullptr, SMC_EDEVICE, "smc_k_resample_noalloc: %s", hipGetErrorString(e));
+    return SMC_OK;
+}
+
 smc_status smc_k_gather_move(smc_ctx* c, int32_t P, const void* u_in, const int32_t* anc,
                              void* u_out, int64_t mpc_step, int32_t iter, int32_t jitter,
                              void* stream) {
@@ -1187,10 +1216,12 @@ smc_status smc_k_mala_accept(smc_ctx* c, int32_t P, void* u, const void* u_prop,
 }
 
 smc_status smc_set_rollout_layout(smc_ctx* c, int32_t layout) {
-    if (!c || layout < 0 || layout > 2) return fail(c, SMC_EINVAL, "smc_set_rollout_layout: bad arguments");
+    if (!c || layout < 0 || layout > 3) return fail(c, SMC_EINVAL, "smc_set_rollout_layout: bad arguments");
     if (layout == 2 && !rollout_wm_supported(c->N))
         return fail(c, SMC_EINVAL, "world-per-lane rollout supports at most %d aircraft", kWorldLaneMaxN);
-    if (layout == 1 && c->wind_model != SMC_WIND_SE)
+    if (layout == 3 && !rollout_pw_supported(c->N, c->prec))
+        return fail(c, SMC_EINVAL, "particle-per-wave rollout: FP32 contexts only");
+    if ((layout == 1 || layout == 3) && c->wind_model != SMC_WIND_SE)
         return fail(c, SMC_EINVAL, "time-correlated wind runs the world-per-lane rollout only");
     c->layout = layout;
     return SMC_OK;
