@@ -270,7 +270,9 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
     const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
         (void*)Wt, (short)0, p.G * M * 8, 0x00020000);
     const int s_z = M * 8, s_y = p.nz * M * 8, s_x = p.ny * p.nz * M * 8;
-    const int vbase = m * 8;
+    // lanes past the last sample (M not a multiple of 64) read sample M - 1
+    // and write nothing
+    const int vbase = (m < M ? m : M - 1) * 8;
     const int nlo = N < 32 ? N : 32;
 
     int s_cur = -1, k_end = 0;

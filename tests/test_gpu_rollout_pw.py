@@ -32,7 +32,10 @@ def test_rollout_pw_aircraft_counts(lib, N, M):
                                             layout=PW)
     n_near = _compare_rollout(gc, gf, ref, 1)
     assert steps == ref["steps"]
-    assert n_near <= 0.02 * 11 * M + 2
+    # a wind-independent margin (thrust, bank, climb, speed, altitude, mass)
+    # is the same in all M samples of a particle: one near-threshold particle
+    # takes its M worlds out of the strict comparison
+    assert n_near <= 0.02 * 11 * M + 2 * M
 
 
 @pytest.mark.parametrize("N", [12, 33, 40, 41, 64])
@@ -54,7 +57,7 @@ def test_rollout_pw_close_traffic_separation(lib, N):
                                             layout=PW)
     n_near = _compare_rollout(gc, gf, ref, 1)
     assert steps == ref["steps"]
-    assert n_near <= 0.02 * 9 * 66 + 2
+    assert n_near <= 0.02 * 9 * 66 + 2 * 66
     assert (~ref["feas"]).mean() > 0.2
 
 
@@ -85,7 +88,7 @@ def test_rollout_pw_noise_term(lib):
     ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=6, layout=PW)
     n_near = _compare_rollout(gc, gf, ref, 1)
     assert steps == ref["steps"]
-    assert n_near <= 0.02 * 6 * 3 * 40
+    assert n_near <= 0.02 * 6 * 3 * 40 + 2 * 3
 
 
 def test_rollout_pw_refused_in_fp64(lib):
