@@ -729,6 +729,20 @@ void smc_destroy(smc_ctx* c) {
     delete c;
 }
 
+// No single device holds more (2^44 bytes = 16 TiB).
+constexpr double kMaxDeviceBytes = 17592186044416.0;
+
+// Bytes of the context's largest device buffers (a lower bound of what the
+// initialisation allocates), in floating point so that no size overflows:
+// per-world costs and feasibility, two particle control sets, the
+// expanded wind factor, the normals, fields and their transposed copy.
+double device_bytes_lower_bound(const smc_ctx* c) {
+    const double L = c->L, N = c->N, M = c->M, G = c->G, Mf = c->Mf, D = 3.0 * c->S;
+    const double r = (double)c->rsz;
+    return M * L * N * (8.0 + 1.0) + 2.0 * L * N * D * r + G * G * r + G * 2.0 * Mf * r * 2.0 +
+           M * G * 2.0 * r;
+}
+
 smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     if (!out) return fail(nullptr, SMC_EINVAL, "out is NULL");
     *out = nullptr;
@@ -798,10 +812,28 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         smc_destroy(c);
         return code;
     };
+    // the context's device memory, from its largest buffers (a lower bound
+    // of the total): refused before any device work when no device could
+    // hold it, and before the first allocation when this device's free
+    // memory cannot
+    const double need = device_bytes_lower_bound(c);
+    if (need > kMaxDeviceBytes) {
+        fail(c, SMC_ENOMEM, "the context needs at least %.4g bytes of device memory", need);
+        return bail(SMC_ENOMEM);
+    }
     hipError_t he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (he != hipSuccess) {
         fail(c, SMC_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(he));
         return bail(SMC_EDEVICE);
+    }
+    {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > (double)free_b) {
+            fail(c, SMC_ENOMEM, "the context needs at least %.4g bytes of device memory, %zu free",
+                 need, free_b);
+            return bail(SMC_ENOMEM);
+        }
+        (void)hipGetLastError();
     }
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         fail(c, SMC_EDEVICE, "hipEventCreate failed");
