@@ -183,19 +183,25 @@ smc_status smc_k_rollout_grad(smc_ctx* ctx, const void* u, int32_t P, const void
                               const double* states, const int32_t* k_active,
                               int32_t horizon, double* grad, void* stream);
 
-/* Langevin proposal u' = u + (eps^2/2) g + eps xi with g = -(beta/M) grad
- * (grad as returned by smc_k_rollout_grad), eps = the scenario's mala_step,
- * xi from the MALA stream of `iter`.  No clamping: a proposal outside the
- * control box is rejected by smc_k_mala_accept. */
+/* Langevin proposal in logit coordinates theta = log(u / (1 - u)), which map
+ * the control box (0, 1)^D one-to-one onto R^D:
+ *   u' = logistic(theta + (eps^2/2) (g u (1 - u) + 1 - 2 u) + eps xi),
+ * the drift being the log-gradient in theta of the tempered target carried
+ * to logit coordinates (its Jacobian prod u (1 - u) included), with
+ * g = -(beta/M) grad the gradient in u (grad as returned by
+ * smc_k_rollout_grad), eps = the scenario's mala_step (a standard deviation
+ * in logit units), xi from the MALA stream of `iter`.  u in (0, 1). */
 smc_status smc_k_mala_propose(smc_ctx* ctx, int32_t P, const void* u,
                               const double* grad, double beta, void* u_prop,
                               int64_t mpc_step, int32_t iter, void* stream);
 
 /* Metropolis-adjusted acceptance of the Langevin proposal with the full
- * target prod_i W_i: reject outside the box or if the proposal violates,
- * accept if the current particle violates, otherwise accept iff
- * log U < sum_i logw' - sum_i logw + log q(u|u') - log q(u'|u) (ACCEPT
- * stream, element p).  Accepted rows of u, chat, feas_pn, logw are replaced;
+ * target prod_i W_i: reject a proposal that rounds onto a face of the box
+ * (u' = 0 or 1 in the context's precision) or violates, accept if the
+ * current particle violates, otherwise accept iff
+ * log U < sum_i logw' - sum_i logw + log q(theta|theta') - log q(theta'|theta)
+ *         + sum log(u'(1 - u')) - sum log(u(1 - u))
+ * (logits of the stored controls; ACCEPT stream, element p).  Accepted rows of u, chat, feas_pn, logw are replaced;
  * accepted[P] (device int32) receives the decisions. */
 smc_status smc_k_mala_accept(smc_ctx* ctx, int32_t P, void* u, const void* u_prop,
                              const double* grad, const double* grad_prop, double beta,

@@ -102,7 +102,9 @@ enum { SMC_WEIGHT_TEMPERED = 0, SMC_WEIGHT_PRODUCT = 1 };
  *  accumulation over wind samples are FP64 in both), move SMC_MOVE_*,
  *  kappa (tempering scale: beta_J = kappa floor(3 + 5 e^{0.05 J}),
  *  Sec. "Simulation Setup"), sigma_move (move step in normalised control
- *  units), mala_step, seed (Philox key), scenario_id (Philox stream tag).
+ *  units), mala_step (standard deviation of the Langevin proposal in logit
+ *  coordinates of the normalised controls), seed (Philox key), scenario_id
+ *  (Philox stream tag).
  *  wind_model SMC_WIND_SE: the squared-exponential field above, one static
  *  field per wind sample and SMC iteration.  SMC_WIND_EXP_AR1 (Sec. "Wind
  *  Model", eq. cov and the linear Gaussian model after it): covariance

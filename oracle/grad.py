@@ -143,10 +143,40 @@ def grad_fuel_time(scen, u_norm, W, states=None, k_active=None, horizon=None):
     return chat.detach().numpy(), u.grad.detach().numpy()
 
 
+# --- the Langevin move in logit coordinates ---------------------------------
+# The controls live in the box (0, 1)^D under a uniform prior (Sec.
+# "Particles").  The move runs on theta = logit(u), which maps the box onto
+# R^D one-to-one, so no proposal can leave the box.  Carried to theta, the
+# tempered target exp(-beta sum_i c_hat_i) on the box gains the Jacobian of
+# u = logistic(theta), prod_d u_d (1 - u_d); its log-gradient in theta is
+#   g u (1 - u) + 1 - 2 u,   g = -beta grad_u sum_i c_hat_i,
+# and the proposal is theta' = theta + (eps^2 / 2) (that gradient) + eps xi:
+# eps is a standard deviation in logit units.
+
+def logit(u):
+    return np.log(u) - np.log1p(-u)
+
+
+def logistic(t):
+    e = np.exp(-np.abs(t))
+    return np.where(t >= 0, 1.0 / (1.0 + e), e / (1.0 + e))
+
+
+def log_jacobian(u):
+    """log prod_d u_d (1 - u_d) per particle: log |du / dtheta|."""
+    lj = np.log(u) + np.log1p(-u)
+    return np.sum(lj.reshape(lj.shape[0], -1), axis=1)
+
+
+def mala_drift(u, g, eps):
+    """(eps^2 / 2) times the log-gradient in theta of the target carried to
+    logit coordinates, at u = logistic(theta), from g (the gradient in u)."""
+    return 0.5 * eps * eps * (g * u * (1.0 - u) + 1.0 - 2.0 * u)
+
+
 def mala_log_q(u_to, u_from, g_from, eps):
-    """log q(u_to | u_from) up to a constant for the Langevin proposal
-    N(u_from + eps^2/2 g_from, eps^2 I), per particle."""
-    d = u_to - u_from - 0.5 * eps * eps * g_from
+    """log q(theta_to | theta_from) up to a constant, per particle: the
+    Gaussian N(theta_from + drift(u_from), eps^2 I) of the Langevin proposal
+    in logit coordinates."""
+    d = logit(u_to) - logit(u_from) - mala_drift(u_from, g_from, eps)
     return -np.sum(d.reshape(d.shape[0], -1) ** 2, axis=1) / (2.0 * eps * eps)
-
-

@@ -254,19 +254,41 @@ def select_best(logw, chat, b):
 # --- one MPC update ----------------------------------------------------------
 
 def mala_propose(scen, u, g, J, mpc_step=None):
-    """Langevin proposal u + (eps^2 / 2) g + eps xi (MALA stream)."""
+    """Langevin proposal in logit coordinates (MALA stream):
+    u' = logistic(logit(u) + drift + eps xi), drift from `grad.mala_drift`."""
+    from .grad import logistic, logit, mala_drift
     eps = scen["mala_step"]
     xi = move_normals(scen, J, u.shape, purpose=philox.MALA, mpc_step=mpc_step)
-    return u + 0.5 * eps * eps * g + eps * xi
+    return logistic(logit(u) + mala_drift(u, g, eps) + eps * xi)
+
+
+def mala_log_ratio(scen, u, up, g, gp):
+    """Per particle: whether the proposal u' lies inside the open box, and
+    log q(theta | theta') - log q(theta' | theta) + log J(u') - log J(u) of
+    the Langevin move in logit coordinates (J the Jacobian of the logit map;
+    0 for a proposal on a face)."""
+    from .grad import log_jacobian, mala_log_q
+    eps = scen["mala_step"]
+    L = u.shape[0]
+    inside = np.all(((up > 0.0) & (up < 1.0)).reshape(L, -1), axis=1)
+    up_safe = np.where(inside[:, None, None, None], up, u)
+    lq = (mala_log_q(u, up_safe, gp, eps) - mala_log_q(up_safe, u, g, eps)
+          + log_jacobian(up_safe) - log_jacobian(u))
+    return inside, np.where(inside, lq, 0.0)
 
 
 def mh_move(scen, u, chat, logw, J, b, evaluate, grad=None, mpc_step=None):
     """One Metropolis move of every particle on the joint target
     prod_i W_i = exp(-b sum_i c_hat_i) (zero if an aircraft violates) under
     the fields of iteration J: the random walk (move 1, reflected proposal,
-    symmetric) or the Langevin proposal (move 2, drift g = -b grad, density
-    ratio q(u | u') / q(u' | u)).  Returns the moved particles, their c_hat
-    and log-weights, the acceptance flags and the proposal's intermediates."""
+    symmetric) or the Langevin proposal in logit coordinates (move 2, drift
+    from g = -b grad; the ratio adds the proposal densities
+    q(theta | theta') / q(theta' | theta) and the Jacobians
+    prod u'(1 - u') / prod u(1 - u) of the logit map).  A Langevin proposal
+    that rounds onto a face of the box (u' = 0 or 1, logit coordinate beyond
+    about 37) is rejected: the carried target vanishes there.  Returns the
+    moved particles, their c_hat and log-weights, the acceptance flags and
+    the proposal's intermediates."""
     L = u.shape[0]
     if scen["move"] == 1:
         up = rw_propose(scen, u, J, mpc_step)
@@ -276,15 +298,12 @@ def mh_move(scen, u, chat, logw, J, b, evaluate, grad=None, mpc_step=None):
         acc = mh_accept(scen, J, logw, logw_p, mpc_step)
         extra = dict(u_prop=up)
     else:
-        from .grad import mala_log_q
-        eps = scen["mala_step"]
         g = -b * grad(u, J)
         up = mala_propose(scen, u, g, J, mpc_step)
         chat_p, feas_p = evaluate(up, J)[:2]
         logw_p = log_weights(chat_p, feas_p, b)
         gp = -b * grad(up, J)
-        lq = mala_log_q(u, up, gp, eps) - mala_log_q(up, u, g, eps)
-        inside = np.all(((up >= 0.0) & (up <= 1.0)).reshape(L, -1), axis=1)
+        inside, lq = mala_log_ratio(scen, u, up, g, gp)
         logw_p_eff = np.where(inside[:, None], logw_p, -np.inf)
         acc = mh_accept(scen, J, logw, logw_p_eff, mpc_step, log_q_ratio=lq)
         extra = dict(u_prop=up, g=g, g_prop=gp)

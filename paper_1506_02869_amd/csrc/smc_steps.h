@@ -189,22 +189,42 @@ __device__ __forceinline__ void propose_at(int64_t e, const R* __restrict__ u,
     up[e] = to_real<R>(r);
 }
 
-// ---- Langevin proposal: u' = u + (eps^2 / 2) g + eps xi, g = coef * gsum --
+// ---- the Langevin move in logit coordinates theta = logit(u) -------------
+// The logit map takes the control box (0, 1)^D one-to-one onto R^D, so no
+// proposal leaves the box.  Carried to theta, the tempered target gains the
+// Jacobian prod u (1 - u) of u = logistic(theta), and its log-gradient in
+// theta is g u (1 - u) + 1 - 2 u with g = coef * gsum the gradient in u
 // (gsum: the adjoint's gradient summed over the wind samples; coef =
-// -beta_J / M makes g the drift of the tempered fuel + time target)
+// -beta_J / M).  eps is a standard deviation in logit units.
+__device__ __forceinline__ double logit_of(double u) { return log(u) - log1p(-u); }
+
+__device__ __forceinline__ double logistic_of(double t) {
+    const double e = exp(-fabs(t));
+    return t >= 0.0 ? 1.0 / (1.0 + e) : e / (1.0 + e);
+}
+
+// (eps^2 / 2) times that log-gradient at u
+__device__ __forceinline__ double mala_drift_at(double u, double g, double eps) {
+    return 0.5 * eps * eps * (g * u * (1.0 - u) + 1.0 - 2.0 * u);
+}
+
+// ---- Langevin proposal: u' = logistic(logit(u) + drift + eps xi) ----------
 template <typename R>
 __device__ __forceinline__ void mala_propose_at(int64_t e, const R* __restrict__ u,
                                                 const double* __restrict__ gsum, double coef,
                                                 double eps, const Stream& s, R* __restrict__ up) {
     double z0, z1;
     normal_pair(draw(s, (uint32_t)e), z0, z1);
-    const double g = coef * gsum[e];
-    up[e] = to_real<R>((double)u[e] + 0.5 * eps * eps * g + eps * z0);
+    const double a = (double)u[e];
+    up[e] = to_real<R>(logistic_of(logit_of(a) + mala_drift_at(a, coef * gsum[e], eps) + eps * z0));
 }
 
-// ---- Langevin decision of particle p: reject a proposal outside the box or
-// violating; accept one if the current particle violates; otherwise accept
-// iff log U < sum_i logw' - sum_i logw + log q(u | u') - log q(u' | u) -----
+// ---- Langevin decision of particle p: reject a proposal on a face of the
+// box (u' rounded to 0 or 1 in the storage precision, where the carried
+// target vanishes) or violating; accept one if the current particle
+// violates; otherwise accept iff log U < sum_i logw' - sum_i logw
+// + log q(theta | theta') - log q(theta' | theta) + log J(u') - log J(u),
+// with theta, theta' the logits of the stored controls --------------------
 template <typename R>
 __device__ __forceinline__ int mala_decide_at(int p, int N, int D, const R* __restrict__ u,
                                               const R* __restrict__ up,
@@ -216,15 +236,19 @@ __device__ __forceinline__ int mala_decide_at(int p, int N, int D, const R* __re
     const int64_t base = (int64_t)p * N * D;
     const int64_t n = (int64_t)N * D;
     bool inside = true;
-    double fwd = 0.0, bwd = 0.0;
-    const double h = 0.5 * eps * eps;
+    double fwd = 0.0, bwd = 0.0, ljac = 0.0;
     for (int64_t e = 0; e < n; ++e) {
         const double a = (double)u[base + e], b = (double)up[base + e];
-        if (!(b >= 0.0 && b <= 1.0)) inside = false;
-        const double d1 = b - a - h * coef * g[base + e];      // u' given u
-        const double d2 = a - b - h * coef * gp_[base + e];    // u given u'
+        if (!(b > 0.0 && b < 1.0)) {
+            inside = false;
+            break;
+        }
+        const double ta = logit_of(a), tb = logit_of(b);
+        const double d1 = tb - ta - mala_drift_at(a, coef * g[base + e], eps);    // theta' | theta
+        const double d2 = ta - tb - mala_drift_at(b, coef * gp_[base + e], eps);  // theta | theta'
         fwd += d1 * d1;
         bwd += d2 * d2;
+        ljac += (log(b) + log1p(-b)) - (log(a) + log1p(-a));
     }
     double s_new = 0.0, s_old = 0.0;
     for (int i = 0; i < N; ++i) {
@@ -233,7 +257,7 @@ __device__ __forceinline__ int mala_decide_at(int p, int N, int D, const R* __re
     }
     if (!inside || s_new == -INFINITY) return 0;
     if (s_old == -INFINITY) return 1;
-    const double lq = (fwd - bwd) / (2.0 * eps * eps);   // log q(u|u') - log q(u'|u)
+    const double lq = (fwd - bwd) / (2.0 * eps * eps) + ljac;
     const Words4 w = draw(s, (uint32_t)p);
     return log(uniform01(w.w0, w.w1)) < (s_new - s_old) + lq ? 1 : 0;
 }

@@ -29,7 +29,9 @@ units (angles in radians).  Field list, in the order the C ABI takes them:
                dep spd, alpha_time, alpha_noise),
     time_norm, noise_alt, popdense[ny_p, nx_p] float32 or None,
     precision (0 fp64, 1 fp32), move (0 jitter, 1 rwmh, 2 mala),
-    kappa, sigma_move, mala_step, seed,
+    kappa, sigma_move, mala_step (standard deviation of the Langevin proposal
+    in logit coordinates: the time step h = 1e-2 of the differentiable
+    workload gives sqrt(h) = 0.1), seed,
     states[N, 6] (x, y, z, v, chi, m), k_active[N], wind_mean[2], mpc_step
 """
 from __future__ import annotations
@@ -119,7 +121,7 @@ def make_scenario(name: str, *, n_arr: int, n_dep: int, box, grid, H: int,
                   seed: int = 0, dep_spacing: int | None = None,
                   alpha_time: float = 0.2, alpha_noise: float = 0.0,
                   noise_alt: float = 2000.0, pop_n=None, kappa: float = 1.0,
-                  sigma_move: float = 0.02, mala_step: float = 1e-2,
+                  sigma_move: float = 0.02, mala_step: float = 0.1,
                   mpc_step: int = 0, wind_model: str = "se",
                   wind_tcorr: float = 1800.0) -> dict:
     rng = np.random.default_rng(seed)

@@ -67,8 +67,7 @@ def test_mala_kernels_match_oracle(lib):
     l1 = osmc.log_weights(chat, f1, beta)
     l2 = osmc.log_weights(chat2, f2, beta)
     gp = -beta * Gp / s["M"]
-    lq = og.mala_log_q(u, ref_up, gp, s["mala_step"]) - og.mala_log_q(ref_up, u, g, s["mala_step"])
-    inside = np.all(((ref_up >= 0) & (ref_up <= 1)).reshape(P, -1), axis=1)
+    inside, lq = osmc.mala_log_ratio(s, u, ref_up, g, gp)
     acc_ref = osmc.mh_accept(s, J, l1, np.where(inside[:, None], l2, -np.inf), mpc_step=step,
                              log_q_ratio=lq)
     acc = empty((P,), torch.int32)

@@ -54,14 +54,24 @@ def test_gradient_matches_central_differences(case):
     assert checked >= 24 and skipped <= 8
 
 
-def test_mala_log_q_is_gaussian():
+def test_mala_log_q_is_gaussian_in_logit_coordinates():
     rng = np.random.default_rng(2)
     a, b = rng.uniform(size=(5, 2, 3, 3)), rng.uniform(size=(5, 2, 3, 3))
-    g = np.zeros_like(a)
-    # symmetric without drift
-    assert np.allclose(og.mala_log_q(a, b, g, 0.1), og.mala_log_q(b, a, g, 0.1))
+    # logit and logistic are inverse maps of (0, 1) and R
+    assert np.allclose(og.logistic(og.logit(a)), a, rtol=0, atol=1e-15)
+    t = np.array([-800.0, -40.0, -1.0, 0.0, 2.5, 40.0, 800.0])
+    assert np.allclose(og.logistic(t), 1.0 / (1.0 + np.exp(-np.clip(t, -700, 700))))
+    # the u-gradient that makes the carried target flat: the drift vanishes
+    g_flat = -(1.0 - 2.0 * a) / (a * (1.0 - a))
+    assert np.allclose(og.mala_drift(a, g_flat, 0.3), 0.0, atol=1e-12)
+    # a Gaussian density in theta, symmetric when both drifts vanish
+    gb = -(1.0 - 2.0 * b) / (b * (1.0 - b))
+    assert np.allclose(og.mala_log_q(a, b, gb, 0.1), og.mala_log_q(b, a, g_flat, 0.1))
     ga = rng.normal(size=a.shape)
     eps = 0.05
-    mean = a + 0.5 * eps * eps * ga
-    ref = -np.sum(((b - mean) ** 2).reshape(5, -1), axis=1) / (2 * eps * eps)
+    ta, tb = np.log(a / (1 - a)), np.log(b / (1 - b))
+    mean = ta + 0.5 * eps * eps * (ga * a * (1 - a) + 1 - 2 * a)
+    ref = -np.sum(((tb - mean) ** 2).reshape(5, -1), axis=1) / (2 * eps * eps)
     assert np.allclose(og.mala_log_q(b, a, ga, eps), ref)
+    # log |du/dtheta| = sum log u (1 - u)
+    assert np.allclose(og.log_jacobian(a), np.log(a * (1 - a)).reshape(5, -1).sum(1))

@@ -23,19 +23,25 @@ L_CHAINS = 4000
 N, S = 1, 2                      # D = 6 coordinates
 
 
-def _toy():
+def _toy(near_face=False):
     rng = np.random.default_rng(11)
-    target = rng.uniform(0.35, 0.65, (N, S, 3))
-    A = rng.uniform(60.0, 140.0, (N, S, 3))
+    if near_face:
+        # 6 standard deviations from the face u = 0: mass beyond it < 1e-9
+        target = rng.uniform(0.09, 0.11, (N, S, 3))
+        A = rng.uniform(450.0, 550.0, (N, S, 3))
+    else:
+        target = rng.uniform(0.35, 0.65, (N, S, 3))
+        A = rng.uniform(60.0, 140.0, (N, S, 3))
     return target, A
 
 
-def _run(move, steps, eps=None, sigma=None, q_reversed=False, monkeypatch=None):
-    target, A = _toy()
+def _run(move, steps, eps=None, sigma=None, q_reversed=False, jac_dropped=False,
+         near_face=False, monkeypatch=None):
+    target, A = _toy(near_face)
     s = mini(N=N, S=S, L=L_CHAINS)
     s.update(move=move, seed=21, kappa=1.0,
              sigma_move=0.02 if sigma is None else sigma,
-             mala_step=0.03 if eps is None else eps)
+             mala_step=0.1 if eps is None else eps)
     J = 0
     b = smc.beta(s, J)           # 8: a fixed temperature for every step
 
@@ -51,6 +57,8 @@ def _run(move, steps, eps=None, sigma=None, q_reversed=False, monkeypatch=None):
         real = og.mala_log_q
         monkeypatch.setattr(og, "mala_log_q",
                             lambda u_to, u_from, g_from, e: -real(u_to, u_from, g_from, e))
+    if jac_dropped:
+        monkeypatch.setattr(og, "log_jacobian", lambda u: np.zeros(u.shape[0]))
     sd = 1.0 / np.sqrt(b * A)
     rng = np.random.default_rng(5)
     # start 3 standard deviations off the target mean, at the target's spread
@@ -87,6 +95,49 @@ def test_move_leaves_gaussian_target_stationary(move, steps):
     assert 0.05 < acc < 0.99, acc
     assert mean_se < MEAN_SE_MAX, mean_se
     assert var_rel < VAR_REL_MAX, var_rel
+
+
+def test_langevin_move_is_stationary_near_a_face():
+    u, target, sd, acc = _run(2, 150, near_face=True)
+    mean_se, var_rel = _stationarity_error(u, target, sd)
+    assert 0.05 < acc < 0.99, acc
+    assert mean_se < MEAN_SE_MAX, mean_se
+    assert var_rel < VAR_REL_MAX, var_rel
+
+
+def test_dropped_jacobian_breaks_stationarity(monkeypatch):
+    """Without the Jacobian of the logit map the chain targets
+    exp(-beta c) / (u (1 - u)) instead: near the face u = 0 its mean moves
+    towards the face by var * (1 - 2u) / (u (1 - u)), about 9 Monte Carlo
+    standard errors here."""
+    u, target, sd, acc = _run(2, 150, jac_dropped=True, near_face=True,
+                              monkeypatch=monkeypatch)
+    mean_se, var_rel = _stationarity_error(u, target, sd)
+    assert mean_se >= MEAN_SE_MAX or var_rel >= VAR_REL_MAX, (mean_se, var_rel)
+
+
+def test_langevin_drift_is_the_log_gradient_in_logit_coordinates():
+    """(eps^2 / 2) d/dtheta [log pi(logistic(theta)) + log |du/dtheta|] by
+    central differences equals the oracle's drift, for a target with a known
+    gradient in u."""
+    rng = np.random.default_rng(3)
+    u = rng.uniform(0.02, 0.98, (4, 1, 2, 3))
+    c = rng.normal(size=u.shape)
+
+    def log_target_theta(t):
+        uu = og.logistic(t)
+        return np.sum(np.sin(3.0 * uu) * c) + np.sum(np.log(uu) + np.log1p(-uu))
+
+    g = 3.0 * np.cos(3.0 * u) * c            # gradient in u of sum sin(3u) c
+    eps, h = 0.2, 1e-6
+    t = og.logit(u)
+    fd = np.zeros_like(u)
+    for idx in np.ndindex(u.shape):
+        tp, tm = t.copy(), t.copy()
+        tp[idx] += h
+        tm[idx] -= h
+        fd[idx] = (log_target_theta(tp) - log_target_theta(tm)) / (2 * h)
+    assert np.allclose(og.mala_drift(u, g, eps), 0.5 * eps * eps * fd, rtol=1e-6, atol=1e-9)
 
 
 def test_reversed_langevin_ratio_breaks_stationarity(monkeypatch):
