@@ -1,7 +1,7 @@
 """Throughput of one SMC-MPC update on one MI355X, with the rollout kernel's
 roofline fraction and the CPU oracle timed beside it.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5]
                 [--no-cpu-baseline] [--cpu-particles P]
 
 A step is one MPC update: the whole hot path (particle init, K_smc wind
@@ -36,6 +36,17 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 # aircraft; the table is in the design notes.
 FLOPS_PER_AIRCRAFT_STEP = 170
 FLOPS_PER_PAIR_TEST = 10
+# The same list split by what the wind changes: the wind only moves an
+# aircraft horizontally, so the speed, climb, bank, drag, thrust, fuel,
+# mass, altitude, heading, unary checks and the altitude and speed elements
+# (80) are the same in every wind sample of a particle; the horizontal wind
+# lookup, horizontal update, geometry and horizontal cost elements (90) are
+# per sample.  A pair test is a vertical part (3: difference, abs, compare)
+# and a horizontal part (7).
+FLOPS_WIND_INDEPENDENT = 80
+FLOPS_WIND_DEPENDENT = 90
+FLOPS_PAIR_VERTICAL = 3
+FLOPS_PAIR_HORIZONTAL = 7
 # Adjoint of the fuel + time cost: one primal step plus one reverse step per
 # (particle, aircraft, wind sample, step); the recomputation from checkpoints
 # is overhead and not counted.
@@ -91,15 +102,54 @@ def traffic_for(kernel_src: tuple, workload: str, kind: str = "rollout"):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(scen, particles: int):
+# --- the CPU oracle as a baseline ---------------------------------------------
+# It runs in a child process started before this process touches the GPU:
+# the child forks one worker per host core for the rollouts.
+
+_SHARD = {}
+
+
+def _rollout_shard(u):
+    """One worker's share of an oracle rollout pass (BLAS on one thread)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import rollout as oro
+    with threadpool_limits(limits=1):
+        r = oro.rollout(_SHARD["scen"], u, _SHARD["W"])
+    return r["cost"], r["feas"], r["steps"]
+
+
+def host_cpu():
+    """Host cores this process may use (the box's share, at most 16 for one
+    GPU), nproc, and the CPU model."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return min(avail, 16), os.cpu_count() or 1, model
+
+
+def cpu_baseline(scen, particles: int, workers: int):
     """The oracle, as it stands, on a bounded sample of the same workload:
-    `particles` particles, 2 SMC iterations, all wind samples, aircraft and
-    steps; one host thread (BLAS pinned to 1 thread)."""
+    `particles` particles, 2 SMC iterations over all wind samples, aircraft
+    and steps, the wind factor and fields included; every rollout pass is
+    split by particles over `workers` forked processes (one host core each),
+    the factor and fields use the BLAS library on the same cores."""
+    import multiprocessing as mp
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import synth
-    from oracle import rollout as oro
     from oracle import smc as osmc
     from oracle import wind as owind
 
@@ -111,26 +161,55 @@ def cpu_baseline(scen, particles: int):
         s = synth.shrink(s, move=1)
         note = ", random-walk moves in place of MALA"
     steps = 0
-
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
+    fork = mp.get_context("fork")
+    _SHARD["scen"] = s
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=workers):
         Lfac = owind.kron_factor(s["box"], s["grid"], s["wind_sigma"], s["wind_ell"],
                                  s["wind_nugget"])
 
-        def evaluate(u, J):
-            nonlocal steps
-            W = owind.sample_field(s, J, s["mpc_step"], Lfac)
-            r = oro.rollout(s, u, W)
-            steps += r["steps"]
-            return osmc.expected_cost(r["cost"], r["feas"])
+    def evaluate(u, J):
+        nonlocal steps
+        with threadpool_limits(limits=workers):
+            _SHARD["W"] = owind.sample_field(s, J, s["mpc_step"], Lfac)
+        shards = [x for x in np.array_split(u, workers) if len(x)]
+        with fork.Pool(len(shards)) as pool:
+            parts = pool.map(_rollout_shard, shards)
+        steps += sum(p[2] for p in parts)
+        cost = np.concatenate([p[0] for p in parts])
+        feas = np.concatenate([p[1] for p in parts])
+        return osmc.expected_cost(cost, feas)
 
-        osmc.run_smc(s, evaluate, s["L"], s["K"], s["N"], s["S"])
-        dt = time.perf_counter() - t0
-    return {"value": steps / dt, "unit": "aircraft-steps/s", "cores": 1, "kind": "oracle",
+    osmc.run_smc(s, evaluate, s["L"], s["K"], s["N"], s["S"])
+    dt = time.perf_counter() - t0
+    return {"value": steps / dt, "unit": "aircraft-steps/s", "cores": workers, "kind": "oracle",
             "sample": (f"oracle smc loop on {particles} particles x {s['M']} wind samples x "
                        f"{s['N']} aircraft x {s['H']} steps, 2 SMC iterations "
-                       f"({steps} aircraft-steps in {dt:.1f} s, wind factor included{note})"),
+                       f"({steps} aircraft-steps in {dt:.1f} s; wind factor and fields "
+                       f"included; rollouts split by particles over {workers} processes{note})"),
             "seconds": round(dt, 2)}
+
+
+def cpu_baseline_child(args):
+    """--cpu-baseline-only: print the baseline's JSON (no GPU use)."""
+    import synth
+    key = WORKLOADS[args.workload][1]
+    workers, nproc, model = host_cpu()
+    out = cpu_baseline(getattr(synth, key)(), args.cpu_particles, workers)
+    out.update(nproc=nproc, cpu_model=model)
+    print(json.dumps(out), flush=True)
+
+
+def run_cpu_baseline(args):
+    """The baseline in a child process (it forks workers, which a process
+    holding the GPU should not)."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only",
+           "--workload", args.workload, "--cpu-particles", str(args.cpu_particles)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"cpu baseline failed: {r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def bench_batch(args, desc):
@@ -316,11 +395,14 @@ def rolling(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-particles", type=int, default=256)
+    ap.add_argument("--cpu-particles", type=int, default=None,
+                    help="particles of the CPU baseline's sample (default: 32 for c5, "
+                         "64 for c4, 256 otherwise)")
+    ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="batched workload: autotune the persistent rollout's launch shape first")
@@ -346,6 +428,20 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.cpu_particles is None:
+        args.cpu_particles = {"c5": 32, "c4": 64}.get(args.workload, 256)
+    if args.cpu_baseline_only:
+        return cpu_baseline_child(args)
+    desc, key = WORKLOADS[args.workload]
+    ar1 = args.wind == "ar1"
+    # the CPU oracle first, in a child process, before this process uses the GPU
+    cpu = None
+    single = not (args.compare_moves or args.rolling > 0 or key == "c3")
+    if single and not args.no_cpu_baseline and not ar1:
+        cpu = run_cpu_baseline(args)
+        print(f"bench {args.workload}: cpu baseline {cpu['value']:.4g} aircraft-steps/s on "
+              f"{cpu['cores']} cores ({cpu['seconds']} s)", file=sys.stderr, flush=True)
+
     import numpy as np
     import torch
 
@@ -362,8 +458,6 @@ def main():
         return compare_moves(args)
     if args.rolling > 0:
         return rolling(args)
-    desc, key = WORKLOADS[args.workload]
-    ar1 = args.wind == "ar1"
     if ar1 and key not in ("c1", "c2"):
         print("--wind ar1: the time-correlated wind runs in the single-scenario form with up "
               "to 20 aircraft and random-walk or jitter moves (workloads c1, c2)", file=sys.stderr)
@@ -400,23 +494,21 @@ def main():
     def note(msg):
         print(f"bench {args.workload}: {msg}", file=sys.stderr, flush=True)
 
-    # one instrumented update: work count and per-kernel event timings
-    _, info0 = one(info=True)
-    note(f"instrumented update {info0['ms_total']:.1f} ms")
     for _ in range(args.warmup):
         one()
     torch.cuda.synchronize()
+    # every timed update is instrumented: per-kernel durations from device
+    # events on the stream the kernels run on, and the work counts
+    nsteps = max(args.steps, 1)
+    infos = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        one()
+    for _ in range(nsteps):
+        infos.append(one(info=True)[1])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / max(args.steps, 1)
-    note(f"{args.steps} timed updates, {ms_step:.1f} ms each")
-    # per-kernel timings over instrumented updates (event pairs on the stream
-    # the kernels run on); the last one's outputs are also the cost check's
-    infos = [one(info=True)[1] for _ in range(max(1, min(args.steps, 3)))]
-    torch.cuda.synchronize()
+    ms_step = (t1 - t0) * 1e3 / nsteps
+    note(f"{nsteps} timed updates, {ms_step:.1f} ms each")
+    info0 = infos[0]
     aircraft_steps = info0["aircraft_steps"]
     value = aircraft_steps / (ms_step * 1e-3)
 
@@ -426,25 +518,45 @@ def main():
     ms_wind = sum(i["ms_wind"] for i in infos) / n_wind
     as_per_launch = aircraft_steps / info0["rollout_launches"]
     pt_per_launch = info0["pair_tests"] / info0["rollout_launches"]
+    ph_per_launch = info0["pair_tests_h"] / info0["rollout_launches"]
     N = scen["N"]
-    flops_launch = (as_per_launch * FLOPS_PER_AIRCRAFT_STEP
-                    + pt_per_launch * FLOPS_PER_PAIR_TEST)
-    achieved = flops_launch / (ms_roll * 1e-3) / 1e12
     fp64 = scen["precision"] == 0
+    # the rollout layout the library picks (world-per-lane up to 20 aircraft,
+    # particle-per-wave above in FP32, aircraft-per-lane otherwise)
+    layout = 2 if N <= 20 else (3 if not fp64 else 1)
+    if layout == 3:
+        # the wind-independent part of a step once per particle, the
+        # wind-dependent part per world; vertical pair tests once per
+        # particle, horizontal ones per world for pairs within sep_v
+        flops_launch = (as_per_launch * FLOPS_WIND_DEPENDENT
+                        + as_per_launch / scen["M"] * FLOPS_WIND_INDEPENDENT
+                        + pt_per_launch / scen["M"] * FLOPS_PAIR_VERTICAL
+                        + ph_per_launch * FLOPS_PAIR_HORIZONTAL)
+    else:
+        flops_launch = (as_per_launch * FLOPS_PER_AIRCRAFT_STEP
+                        + pt_per_launch * FLOPS_PER_PAIR_TEST)
+    achieved = flops_launch / (ms_roll * 1e-3) / 1e12
     peak = PEAK_FP64_VECTOR_TFLOPS if fp64 else PEAK_FP32_VECTOR_TFLOPS
-    world_lane = N <= 20   # the library picks the world-per-lane rollout up to 20 aircraft
-    kname, ksrc = ((
-        "k_rollout_wm", ("kernels_rollout_wm.hip", "rollout_wm_body.inc", "rollout_math.h"))
-        if world_lane else ("k_rollout", ("kernels_rollout.hip", "rollout_math.h")))
+    world_lane = layout == 2
+    kname, ksrc = {
+        2: ("k_rollout_wm", ("kernels_rollout_wm.hip", "rollout_wm_body.inc", "rollout_math.h")),
+        3: ("k_rollout_pw", ("kernels_rollout_pw.hip", "rollout_math.h")),
+        1: ("k_rollout", ("kernels_rollout.hip", "rollout_math.h"))}[layout]
     if ar1:
         kname = "k_rollout_wm_tv"
     roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 3),
             "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": traffic_for(ksrc, args.workload) if world_lane and not ar1 else None,
+            "traffic": traffic_for(ksrc, args.workload) if not ar1 else None,
             "ms_per_launch": round(ms_roll, 4),
             "aircraft_steps_per_launch": int(as_per_launch),
             "pair_tests_per_launch": int(pt_per_launch),
-            "flops_per_launch": flops_launch}
+            "horizontal_pair_tests_per_launch": int(ph_per_launch),
+            "flops_per_launch": flops_launch,
+            # the same launch priced at the whole per-step operation list for
+            # every world (170 per aircraft-step, 10 per pair test)
+            "survey_unit_tflops": round((as_per_launch * FLOPS_PER_AIRCRAFT_STEP
+                                         + pt_per_launch * FLOPS_PER_PAIR_TEST)
+                                        / (ms_roll * 1e-3) / 1e12, 3)}
     G = int(np.prod(scen["grid"]))
     # triangular factor x 2M columns; under the time-correlated wind the
     # horizontal factor (nx ny rows) x 2 H M nz columns
@@ -491,9 +603,6 @@ def main():
                  "rel_err": rel, "within_1e-3": bool(rel <= 1e-3),
                  "oracle_feasible": bool(rf.all()), "status": int(status.cpu()[0])}
 
-    cpu = None
-    if not args.no_cpu_baseline and not ar1:
-        cpu = cpu_baseline(scen, args.cpu_particles)
 
     out = {"metric": METRIC, "value": value, "unit": "aircraft-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -507,7 +616,8 @@ def main():
            "roofline": roof, "cpu_baseline": cpu, "wind_gemm_roofline": wind_roof,
            "adjoint_roofline": grad_roof, "cost_check": check,
            "step_info": {k: info0[k] for k in ("feasible_frac", "ess_min", "best_particle",
-                                              "ms_total", "accept_rate")}}
+                                              "ms_total", "accept_rate")},
+           "status": int(status.cpu()[0])}
     print(json.dumps(out), flush=True)
 
 

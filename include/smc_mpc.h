@@ -172,6 +172,10 @@ typedef struct {
     int32_t wind_launches;    /* wind GEMM launches in the update               */
     double ms_grad;           /* summed duration of the adjoint launches (MALA) */
     int32_t grad_launches;    /* adjoint launches in the update (MALA: 2 K)     */
+    int64_t pair_tests_h;     /* pair tests that reached the horizontal distance
+                               * comparison (= pair_tests except in the
+                               * particle-per-wave rollout, which compares only
+                               * pairs within the vertical separation)          */
 } smc_step_info;
 
 /* Create a context: validates the scenario, factors the wind covariance

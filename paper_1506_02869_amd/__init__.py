@@ -72,7 +72,7 @@ class StepInfo(C.Structure):
                 ("ms_total", C.c_double), ("ms_rollout", C.c_double),
                 ("ms_wind", C.c_double), ("rollout_launches", C.c_int32),
                 ("wind_launches", C.c_int32), ("ms_grad", C.c_double),
-                ("grad_launches", C.c_int32)]
+                ("grad_launches", C.c_int32), ("pair_tests_h", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

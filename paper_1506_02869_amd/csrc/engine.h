@@ -62,6 +62,9 @@ struct RolloutArrays {
     double* cost;             // [M][P][N]
     uint8_t* feas;            // [M][P][N]
     unsigned long long* steps;  // [2 kStepSlots] or null: aircraft-steps, pair tests
+    // [kStepSlots] or null: pair tests that reached the horizontal comparison
+    // (particle-per-wave layout: pairs within the vertical separation)
+    unsigned long long* steps_h = nullptr;
 };
 
 // Control box: physical control c = lo[c] + normalised * sp[c].

@@ -126,6 +126,9 @@ k_rollout(const RolloutParams p, const RolloutArrays a, int wpb) {
             vc = (R)p.ctrl_lo[1] + ubase[s * 3 + 1] * (R)p.ctrl_span[1];
             zdot = (R)p.ctrl_lo[2] + ubase[s * 3 + 2] * (R)p.ctrl_span[2];
             k_end = ((s + 1) * H + S - 1) / S;
+            // FP32: heading back into [-pi, pi) at each segment start (its
+            // rounding stays that of an angle near pi)
+            if constexpr (sizeof(R) == 4) chi = wrap_angle<R>(chi);
         }
         // airspeed ramps to vc by the segment's end: 1 / (steps remaining)
         inv_rem = Ops<R>::rcp((R)(k_end - k));

@@ -73,7 +73,7 @@ __device__ __forceinline__ void pw_aircraft(
     const float* __restrict__ rec, const __amdgpu_buffer_rsrc_t wrs, int s_z, int s_y, int s_x,
     int vbase, int M, int i, uint64_t actk, float zn_lane, VX& x, VX& y, VX& acc,
     const v32f& xlo, const v32f& ylo, uint32_t done0, uint32_t& done, uint32_t& bad,
-    uint32_t& sepbad, uint32_t& sepbad_lo) {
+    uint32_t& sepbad, uint32_t& sepbad_lo, int& nhor) {
     typedef Ops<float> O;
     const RollConst<float>& q = p.cf;
     const int ii = HI ? i - 32 : i;
@@ -167,6 +167,7 @@ __device__ __forceinline__ void pw_aircraft(
     // is within sep_v (a uniform candidate mask)
     const uint64_t vclose = __ballot(m_abs(zn_lane - zn) < q.sep_v);
     const uint64_t cand = vclose & actk & ((1ull << i) - 1ull);
+    nhor += __popcll(cand);   // uniform: horizontal tests of this aircraft
     uint32_t c_lo = (uint32_t)cand;
     while (c_lo) {
         const int jj = __builtin_ctz(c_lo);
@@ -262,7 +263,7 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
         accb[i] = 0.f;
     }
     uint32_t done_lo = 0u, done_hi = 0u, bad_lo = 0u, bad_hi = 0u, sep_lo = 0u, sep_hi = 0u;
-    int nsim = 0, npair = 0;
+    int nsim = 0, npair = 0, nhor = 0;
 
     // field of this world's sample in the sample-interleaved layout
     // Wt[g][m][c]: the corner (ix, iy, iz) of lane m sits at byte
@@ -344,7 +345,10 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
                 r4[2] = make_float4(na, pj[A_CFUEL] * fuel, __uint_as_float(fl), 0.f);
             }
             zn_lane = zn;
-            if (act) { zj = zn; vj = vn; chij = chin; burnj = burnj + fuel; }
+            // the heading is kept in [-pi, pi) (it enters only through sin,
+            // cos and wrapped differences), so its rounding stays that of an
+            // angle near pi however far the aircraft turns
+            if (act) { zj = zn; vj = vn; chij = wrap_angle<float>(chin); burnj = burnj + fuel; }
             wave_sync();   // records visible to every lane
         }
 
@@ -353,13 +357,13 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
         for (int i = 0; i < nlo; ++i) {
             if (!((actk >> i) & 1ull)) continue;                    // uniform
             pw_aircraft<false>(p, a, par, recw, wrs, s_z, s_y, s_x, vbase, M, i, actk, zn_lane,
-                               xa, ya, acca, xa, ya, d0lo, done_lo, bad_lo, sep_lo, sep_lo);
+                               xa, ya, acca, xa, ya, d0lo, done_lo, bad_lo, sep_lo, sep_lo, nhor);
         }
         if (NMAX > 32) {
             for (int i = 32; i < N; ++i) {
                 if (!((actk >> i) & 1ull)) continue;                // uniform
                 pw_aircraft<true>(p, a, par, recw, wrs, s_z, s_y, s_x, vbase, M, i, actk, zn_lane,
-                                  xb, yb, accb, xa, ya, d0hi, done_hi, bad_hi, sep_hi, sep_lo);
+                                  xb, yb, accb, xa, ya, d0hi, done_hi, bad_hi, sep_hi, sep_lo, nhor);
             }
         }
         {   // aircraft simulated this step and pair tests with both present
@@ -393,6 +397,12 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
             if (cnt) atomicAdd(&a.steps[slot], (unsigned long long)cnt);
             if (cp) atomicAdd(&a.steps[kStepSlots + slot], (unsigned long long)cp);
         }
+    }
+    if (a.steps_h) {   // nhor is wave-uniform: one count per valid lane (world)
+        const unsigned long long nv = (unsigned long long)__popcll(__ballot(valid));
+        if (lane == 0 && nhor && nv)
+            atomicAdd(&a.steps_h[(unsigned)(wave & (kStepSlots - 1))],
+                      (unsigned long long)nhor * nv);
     }
 }
 

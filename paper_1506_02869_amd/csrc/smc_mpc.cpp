@@ -276,6 +276,9 @@ RolloutArrays rollout_arrays(smc_ctx* c, const void* u, const void* W, const dou
     a.cost = cost;
     a.feas = feas;
     a.steps = steps;
+    // the context's own counters carry a third region for the horizontal
+    // pair tests; a caller's counter buffer (kernel-level entry) does not
+    a.steps_h = (steps && steps == c->d_steps) ? steps + 2 * kStepSlots : nullptr;
     return a;
 }
 
@@ -368,7 +371,7 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     rp.P = L;
     unsigned long long* steps = info ? c->d_steps : nullptr;
     if (info) {
-        HIP_OK(c, hipMemsetAsync(c->d_steps, 0, sizeof(unsigned long long) * 2 * kStepSlots, st));
+        HIP_OK(c, hipMemsetAsync(c->d_steps, 0, sizeof(unsigned long long) * 3 * kStepSlots, st));
         HIP_OK(c, hipEventRecord(c->ev0, st));
     }
     void* u = c->d_u;
@@ -485,8 +488,8 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     HIP_OK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     int32_t best[2];
     HIP_OK(c, hipMemcpy(best, c->d_best, sizeof best, hipMemcpyDeviceToHost));
-    std::vector<unsigned long long> cnt(2 * kStepSlots);
-    HIP_OK(c, hipMemcpy(cnt.data(), c->d_steps, sizeof(unsigned long long) * 2 * kStepSlots,
+    std::vector<unsigned long long> cnt(3 * kStepSlots);
+    HIP_OK(c, hipMemcpy(cnt.data(), c->d_steps, sizeof(unsigned long long) * 3 * kStepSlots,
                         hipMemcpyDeviceToHost));
     std::vector<uint8_t> fe((size_t)L * N);
     HIP_OK(c, hipMemcpy(fe.data(), c->d_feaspn, fe.size(), hipMemcpyDeviceToHost));
@@ -499,8 +502,12 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     HIP_OK(c, hipStreamSynchronize(st));
     long nf = 0;
     for (uint8_t f : fe) nf += f;
-    unsigned long long tot = 0, totp = 0;
-    for (int q = 0; q < kStepSlots; ++q) { tot += cnt[q]; totp += cnt[kStepSlots + q]; }
+    unsigned long long tot = 0, totp = 0, toth = 0;
+    for (int q = 0; q < kStepSlots; ++q) {
+        tot += cnt[q];
+        totp += cnt[kStepSlots + q];
+        toth += cnt[2 * kStepSlots + q];
+    }
     info->iterations = c->K;
     info->best_particle = best[0];
     info->feasible_frac = (double)nf / (double)fe.size();
@@ -508,6 +515,9 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     info->ess_min = *std::min_element(ess.begin(), ess.end());
     info->aircraft_steps = (int64_t)tot;
     info->pair_tests = (int64_t)totp;
+    // every layout but the particle-per-wave one tests all pairs horizontally
+    info->pair_tests_h = rollout_layout(c) == 3 && c->wind_model == SMC_WIND_SE ? (int64_t)toth
+                                                                                 : (int64_t)totp;
     info->ms_total = ms;
     double ms_r = 0.0, ms_w = 0.0, ms_g = 0.0;
     const bool grad = c->move == SMC_MOVE_MALA;
@@ -868,7 +878,7 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         (st = dalloc_t(c, &c->d_anc, N * L)) || (st = dalloc_t(c, &c->d_U, N)) ||
         (st = dalloc_t(c, &c->d_scan, N * L)) || (st = dalloc_t(c, &c->d_ess, N)) ||
         (st = dalloc_t(c, &c->d_flags, L)) || (st = dalloc_t(c, &c->d_best, 2)) ||
-        (st = dalloc_t(c, &c->d_status, 1)) || (st = dalloc_t(c, &c->d_steps, 2 * kStepSlots)) ||
+        (st = dalloc_t(c, &c->d_status, 1)) || (st = dalloc_t(c, &c->d_steps, 3 * kStepSlots)) ||
         (st = dalloc_t(c, &c->d_states, N * 6)) || (st = dalloc_t(c, &c->d_kact, N)) ||
         (st = dalloc_t(c, &c->d_ctrl_out, N * D)) || (st = dalloc_t(c, &c->d_cost_out, 1 + N)) ||
         (st = dalloc_t(c, &c->d_plant_states, N * 6)) || (st = dalloc_t(c, &c->d_plant_i32, 2 * N)) ||
