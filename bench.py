@@ -68,6 +68,11 @@ WORKLOADS = {
            "FP32 rollout and adjoint with FP64 weights, scan and gradient sums, MALA moves "
            "(step 1e-2) driven by the adjoint of the fuel + time cost, checkpoint every "
            "25 steps", "c4"),
+    "paper": ("the paper's timing experiment shape: 10 aircraft (8 arrivals, 2 departures "
+              "released 4 steps apart), 80x80x6 km, H=6 dt=10 s, per-step (thrust, flight-path "
+              "angle, bank) controls, wind 2x2x2 M=709, L=10240, K=100, literal weighting over "
+              "SampleSchedule(J)+1 passes at iteration J, FP32 rollout with FP64 weights and scan, "
+              "jitter moves", "paper_table"),
     "c5": ("large form: 40 aircraft (24 arrivals, 16 departures, 780 pairs), 150x150x10 km, "
            "H=180 dt=5 s, S=12, fuel + time + noise (256x256 lognormal population below "
            "2 km), wind 64x64x8 (G=32768) M=128, L=65536, K=60, FP32 rollout "
@@ -138,10 +143,11 @@ def host_cpu():
     return min(avail, 16), os.cpu_count() or 1, model
 
 
-def cpu_baseline(scen, particles: int, workers: int):
+def cpu_baseline(scen, particles: int, workers: int, iters: int = 2):
     """The oracle, as it stands, on a bounded sample of the same workload:
-    `particles` particles, 2 SMC iterations over all wind samples, aircraft
-    and steps, the wind factor and fields included; every rollout pass is
+    `particles` particles, `iters` SMC iterations over all wind samples (or
+    the iteration's passes), aircraft and steps, the wind factor and fields
+    included; every rollout pass is
     split by particles over `workers` forked processes (one host core each),
     the factor and fields use the BLAS library on the same cores."""
     import multiprocessing as mp
@@ -153,7 +159,7 @@ def cpu_baseline(scen, particles: int, workers: int):
     from oracle import smc as osmc
     from oracle import wind as owind
 
-    s = synth.shrink(scen, L=particles, K=2)
+    s = synth.shrink(scen, L=particles, K=iters)
     note = ""
     if s["move"] == 2:
         # the oracle's Langevin move needs its autograd gradient; the baseline
@@ -165,26 +171,31 @@ def cpu_baseline(scen, particles: int, workers: int):
     _SHARD["scen"] = s
     t0 = time.perf_counter()
     with threadpool_limits(limits=workers):
-        Lfac = owind.kron_factor(s["box"], s["grid"], s["wind_sigma"], s["wind_ell"],
-                                 s["wind_nugget"])
+        Lfac = owind.factor(s)
+    product = osmc.product_weighting(s)
 
     def evaluate(u, J):
         nonlocal steps
         with threadpool_limits(limits=workers):
-            _SHARD["W"] = owind.sample_field(s, J, s["mpc_step"], Lfac)
+            W = owind.sample_field(s, J, s["mpc_step"], Lfac)
+        # the literal weighting rolls out the iteration's first passes only
+        _SHARD["W"] = W[:osmc.inner_samples(J)] if product else W
         shards = [x for x in np.array_split(u, workers) if len(x)]
         with fork.Pool(len(shards)) as pool:
             parts = pool.map(_rollout_shard, shards)
         steps += sum(p[2] for p in parts)
         cost = np.concatenate([p[0] for p in parts])
         feas = np.concatenate([p[1] for p in parts])
-        return osmc.expected_cost(cost, feas)
+        chat, fe = osmc.expected_cost(cost, feas)
+        if product:
+            return chat, fe, osmc.product_log_weights(cost, feas)
+        return chat, fe
 
     osmc.run_smc(s, evaluate, s["L"], s["K"], s["N"], s["S"])
     dt = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "aircraft-steps/s", "cores": workers, "kind": "oracle",
             "sample": (f"oracle smc loop on {particles} particles x {s['M']} wind samples x "
-                       f"{s['N']} aircraft x {s['H']} steps, 2 SMC iterations "
+                       f"{s['N']} aircraft x {s['H']} steps, {iters} SMC iterations "
                        f"({steps} aircraft-steps in {dt:.1f} s; wind factor and fields "
                        f"included; rollouts split by particles over {workers} processes{note})"),
             "seconds": round(dt, 2)}
@@ -195,7 +206,8 @@ def cpu_baseline_child(args):
     import synth
     key = WORKLOADS[args.workload][1]
     workers, nproc, model = host_cpu()
-    out = cpu_baseline(getattr(synth, key)(), args.cpu_particles, workers)
+    iters = 10 if key == "paper_table" else 2
+    out = cpu_baseline(getattr(synth, key)(), args.cpu_particles, workers, iters)
     out.update(nproc=nproc, cpu_model=model)
     print(json.dumps(out), flush=True)
 
@@ -401,7 +413,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-particles", type=int, default=None,
                     help="particles of the CPU baseline's sample (default: 32 for c5, "
-                         "64 for c4, 256 otherwise)")
+                         "64 for c4, 2048 for paper, 256 otherwise)")
     ap.add_argument("--cpu-baseline-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--autotune", action="store_true",
@@ -429,7 +441,7 @@ def main():
         sys.exit(2)
 
     if args.cpu_particles is None:
-        args.cpu_particles = {"c5": 32, "c4": 64}.get(args.workload, 256)
+        args.cpu_particles = {"c5": 32, "c4": 64, "paper": 2048}.get(args.workload, 256)
     if args.cpu_baseline_only:
         return cpu_baseline_child(args)
     desc, key = WORKLOADS[args.workload]
@@ -472,10 +484,11 @@ def main():
         desc += (AR1_DESC)
     scen = getattr(synth, key)(**({"wind_model": "ar1"} if ar1 else {}))
     product = args.weighting == "product"
-    if product:
+    if product and scen.get("weighting", 0) != 1:
         scen["weighting"] = 1
         desc += ("; the paper's literal weighting: SampleSchedule(J) + 1 passes at iteration J "
                  "(one wind sample each), log W = sum log(1 - cost)")
+    product = scen.get("weighting", 0) == 1
     torch.cuda.set_device(0)
     ctx = smc.smc_mpc_init(scen)
     dev = torch.device("cuda")
@@ -618,6 +631,13 @@ def main():
            "step_info": {k: info0[k] for k in ("feasible_frac", "ess_min", "best_particle",
                                               "ms_total", "accept_rate")},
            "status": int(status.cpu()[0])}
+    if key == "paper_table":
+        # the paper's own timing (Table comp_sense, best thread layout), on
+        # its hardware and traffic: context, not a target
+        out["paper_context"] = {
+            "seconds_per_update": 56.0, "hardware": "NVIDIA GeForce GTX 580, mostly FP64",
+            "workload": "10 aircraft, H=6, dt=10 s, L=10240, 100 iterations of "
+                        "SampleSchedule(J) passes, 8-point wind grid (Gatwick traffic)"}
     print(json.dumps(out), flush=True)
 
 

@@ -61,6 +61,11 @@ enum { SMC_WIND_SE = 0, SMC_WIND_EXP_AR1 = 1 };
  * n_wind samples) or the paper's literal product over SampleSchedule(J) + 1
  * passes. */
 enum { SMC_WEIGHT_TEMPERED = 0, SMC_WEIGHT_PRODUCT = 1 };
+/* Control parametrisation: the kinematic segment controls (heading rate,
+ * airspeed reached at the segment's end, climb rate), or the paper's own
+ * per-step thrust, flight-path angle and bank (Sec. "Trajectory Planning and
+ * Disturbance Realisations", eq. hor; Sec. "Particles"). */
+enum { SMC_CONTROLS_KINEMATIC = 0, SMC_CONTROLS_PAPER = 1 };
 
 #define SMC_AC_NPAR 9   /* aircraft parameters per aircraft, see smc_scenario */
 #define SMC_COST_NW 9   /* cost weights, see smc_scenario */
@@ -128,6 +133,18 @@ enum { SMC_WEIGHT_TEMPERED = 0, SMC_WEIGHT_PRODUCT = 1 };
  *  a violation; c_hat is the mean over the passes.  Needs n_wind >=
  *  SampleSchedule(n_iters - 1) + 1, the static wind model and a move other
  *  than SMC_MOVE_MALA; not in the batched form.
+ *  control_model SMC_CONTROLS_KINEMATIC: segment s of n_segments holds
+ *  (heading rate [rad/s], airspeed [m/s], climb rate [m/s]) for the steps
+ *  floor(k n_segments / horizon) = s.  SMC_CONTROLS_PAPER: step k has its own
+ *  control set k (n_segments >= horizon_max, so D = 3 N horizon per
+ *  particle), (thrust as a fraction of the aircraft's T_max, flight-path
+ *  angle gamma [rad], bank phi [rad]) with ctrl_lo/ctrl_hi bounding those
+ *  three (thrust fraction >= 0, |angles| < pi/2); v' = v + dt ((T - D)/m
+ *  - g sin gamma), chi' = chi + dt L sin(phi) / (m v), L = m g cos(gamma) /
+ *  cos(phi), z' = z + dt v sin(gamma), fuel dt eta(v) T; the departure
+ *  altitude band grows at v_max sin(max |gamma bound|).  Limits:
+ *  n_aircraft <= 20 (world-per-lane rollout), static wind model, move not
+ *  SMC_MOVE_MALA, no smc_plant_step, not in the batched form.
  */
 typedef struct {
     int32_t n_aircraft, n_segments, horizon_max, n_particles, n_wind, n_iters;
@@ -153,6 +170,7 @@ typedef struct {
     int32_t wind_model;                         /* SMC_WIND_* */
     double wind_beta, wind_gamma, wind_tcorr;   /* SMC_WIND_EXP_AR1 only */
     int32_t weighting;                          /* SMC_WEIGHT_* */
+    int32_t control_model;                      /* SMC_CONTROLS_* */
 } smc_scenario;
 
 /* Diagnostics of one MPC update (optional output).  When requested, device
@@ -191,7 +209,8 @@ smc_status smc_mpc_init(const smc_scenario* scenario, smc_ctx** out);
  *  k_active[N]: step at which the aircraft enters the horizon (0 = now);
  *     < 0 or >= horizon: not in the problem.
  *  wind_mean[2]: nominal wind (east, north) added to every field sample.
- *  horizon: 1..horizon_max steps.
+ *  horizon: 1..horizon_max steps, at least n_segments with the kinematic
+ *     controls (no empty segment); any with the paper's per-step controls.
  *  controls_out[N x S x 3]: physical controls of the chosen particle.
  *  exp_cost_out[1 + N]: its total and per-aircraft expected cost (mean over
  *     the wind samples of the last pass; 0 best, 1 worst per aircraft).

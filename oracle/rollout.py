@@ -29,6 +29,14 @@ Paper passages followed:
     fuel; Sec. "Noise Pollution Reduction": the altitude-weighted population
     noise term.
 
+The paper's own control parametrisation (control_model 1, Sec.
+"Trajectory Planning and Disturbance Realisations", eq. (hor) and Sec.
+"Particles"): every step k has its own controls, thrust T (a fraction of
+T_max), flight-path angle gamma and bank angle phi; v' = v + dt ((T - D)/m -
+g sin gamma), chi' = chi + dt L sin(phi) / (m v) with the lift of the
+coordinated turn L = m g cos(gamma) / cos(phi), z' = z + dt v sin(gamma),
+m' = m - dt eta(v) T.
+
 Build-specific readings (all listed in the design notes): costs are
 minimised, c = 1 - J per element, so the best cost is 0; a time-to-go term is
 added; the flow field is chi_hat = pi + 2 atan2(y, x) with remaining arc
@@ -106,6 +114,16 @@ def time_element(scen, x, y, v):
     return np.where(kind == 0, t_arr, t_dep)
 
 
+def climb_rate_bound(scen):
+    """Largest climb or descent rate the controls allow [m/s]: the climb-rate
+    bound of the kinematic controls, or v_max sin(gamma_bound) for the
+    paper's flight-path-angle control."""
+    lo, hi = scen["ctrl_lo"], scen["ctrl_hi"]
+    if scen.get("control_model", 0) == 1:
+        return scen["env"][3] * math.sin(max(abs(lo[1]), abs(hi[1])))
+    return max(abs(lo[2]), abs(hi[2]))
+
+
 def step_cost(scen, j, x, y, z, v, chi, z_act):
     """Per-step cost (0 best, 1 worst) at a new state, for every aircraft.
 
@@ -118,7 +136,7 @@ def step_cost(scen, j, x, y, z, v, chi, z_act):
     vmin, vmax = scen["env"][2], scen["env"][3]
     beta_f = scen["landing"][4]
     theta_F, Zt, vD, dtma = (scen["targets"][:, c] for c in range(4))
-    zdot_max = max(abs(scen["ctrl_lo"][2]), abs(scen["ctrl_hi"][2]))
+    zdot_max = climb_rate_bound(scen)
     dt = scen["dt"]
 
     theta = np.arctan2(y, x)
@@ -198,33 +216,48 @@ def rollout(scen, u_norm, W, states=None, k_active=None, horizon=None,
     track = [np.stack([x, y, z, v, chi, mass], axis=-1)] if record else None
     pres_log = [] if record else None
 
+    paper_controls = scen.get("control_model", 0) == 1
+    if paper_controls and S < H:
+        raise ValueError("the per-step controls need a control set for every step (S >= H)")
     for k in range(H):
-        s = (k * S) // H
-        k_end = ((s + 1) * H + S - 1) // S        # first step of segment s+1
-        chidot = u[:, None, :, s, 0]
-        vc = u[:, None, :, s, 1]
-        zdot = u[:, None, :, s, 2]
         present = active & (k >= kact) & ~done
         steps += int(present.sum())
-
         Wk = W[k] if W.ndim == 4 else W           # per-step fields (paper's model)
         wxy = _wind.trilinear(Wk, m_idx, scen["box"], scen["grid"], x, y, z)
-        gamma = np.arcsin(zdot / v)               # climb angle from climb rate
-        phi = np.arctan(v * chidot / G0)          # bank for the heading rate
         rho = isa_density(z)
         qd = 0.5 * rho * v * v
-        CL = mass * G0 / (qd * Sw * np.cos(phi))  # lift balances weight in turn
-        CD = cd0 + cd2 * CL * CL
-        D = qd * Sw * CD
-        vn = v + (vc - v) / (k_end - k)           # ramp to vc by segment end
-        T = mass * (vn - v) / dt + D + mass * G0 * np.sin(gamma)
         eta = cf1 * (1.0 + v / cf2)
-        fuel = dt * eta * np.maximum(T, 0.0)
+        if paper_controls:
+            # thrust, flight-path angle and bank of step k (eq. hor)
+            T = np.broadcast_to(u[:, None, :, k, 0] * tmax, shape)
+            gamma = np.broadcast_to(u[:, None, :, k, 1], shape)
+            phi = np.broadcast_to(u[:, None, :, k, 2], shape)
+            lift = mass * G0 * np.cos(gamma) / np.cos(phi)   # coordinated turn
+            CL = lift / (qd * Sw)
+            CD = cd0 + cd2 * CL * CL
+            D = qd * Sw * CD
+            vn = v + dt * ((T - D) / mass - G0 * np.sin(gamma))
+            chin = chi + dt * lift * np.sin(phi) / (mass * v)
+            fuel = dt * eta * T
+        else:
+            s = (k * S) // H
+            k_end = ((s + 1) * H + S - 1) // S    # first step of segment s+1
+            chidot = u[:, None, :, s, 0]
+            vc = u[:, None, :, s, 1]
+            zdot = u[:, None, :, s, 2]
+            gamma = np.arcsin(zdot / v)           # climb angle from climb rate
+            phi = np.arctan(v * chidot / G0)      # bank for the heading rate
+            CL = mass * G0 / (qd * Sw * np.cos(phi))  # lift balances weight in turn
+            CD = cd0 + cd2 * CL * CL
+            D = qd * Sw * CD
+            vn = v + (vc - v) / (k_end - k)       # ramp to vc by segment end
+            T = mass * (vn - v) / dt + D + mass * G0 * np.sin(gamma)
+            fuel = dt * eta * np.maximum(T, 0.0)
+            chin = chi + dt * chidot
 
         xn = x + dt * (v * np.cos(chi) * np.cos(gamma) + wxy[..., 0])
         yn = y + dt * (v * np.sin(chi) * np.cos(gamma) + wxy[..., 1])
         zn = z + dt * v * np.sin(gamma)
-        chin = chi + dt * chidot
         mn = mass - fuel
 
         viol = ((T > tmax) | (np.abs(phi) >= phi_max) | (np.abs(gamma) > gamma_max)

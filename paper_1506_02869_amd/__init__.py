@@ -60,7 +60,7 @@ class Scenario(C.Structure):
         ("kappa", C.c_double), ("sigma_move", C.c_double), ("mala_step", C.c_double),
         ("seed", C.c_uint64), ("scenario_id", C.c_int32),
         ("wind_model", C.c_int32), ("wind_beta", C.c_double), ("wind_gamma", C.c_double),
-        ("wind_tcorr", C.c_double), ("weighting", C.c_int32),
+        ("wind_tcorr", C.c_double), ("weighting", C.c_int32), ("control_model", C.c_int32),
     ]
 
 
@@ -357,6 +357,7 @@ def make_scenario_struct(s: dict):
     sc.wind_gamma = float(s.get("wind_gamma", 0.0))
     sc.wind_tcorr = float(s.get("wind_tcorr", 0.0))
     sc.weighting = int(s.get("weighting", 0))
+    sc.control_model = int(s.get("control_model", 0))
     return sc, keep
 
 

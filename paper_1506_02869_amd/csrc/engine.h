@@ -36,6 +36,7 @@ struct RolloutParams {
     int N, S, H, P, M, G;
     int nx, ny, nz;
     int use_noise, pop_nx, pop_ny;
+    int control_model;      // 0 kinematic segment controls, 1 the paper's per-step (T, gamma, phi)
     double half_wx, half_wy, inv_hx, inv_hy, inv_hz;
     double pop_inv_hx, pop_inv_hy;
     double dt, sep_h2, sep_v;

@@ -59,6 +59,7 @@ k_rollout_wm_batch(const BatchScen* __restrict__ tab, const BatchItem* __restric
         const int64_t world = (int64_t)item->world0 + lane;
         const unsigned slot = (unsigned)it;
         constexpr bool kTV = false;
+        constexpr bool kPC = false;
 #include "rollout_wm_body.inc"
     }
 }

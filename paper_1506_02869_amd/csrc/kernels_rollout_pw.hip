@@ -37,11 +37,16 @@ namespace smc {
 
 namespace {
 
+// one float per aircraft of the world, in two register vectors of at most
+// 32 (aircraft 0..31 and 32..NMAX-1), each indexed at a uniform index
 typedef float v32f __attribute__((ext_vector_type(32)));
 template <int NB> struct PwHalf { typedef float t __attribute__((ext_vector_type(NB))); };
+template <int NMAX>
+constexpr int pw_nb() { return NMAX <= 32 ? 8 : NMAX - 32; }
 
 constexpr int kPwWaves = 4;     // wavefronts per workgroup (independent)
-constexpr int kPwRec = 16;      // floats of an aircraft-step record
+constexpr int kXcds = 8;        // accelerator complex dies; workgroups are dealt to them in turn
+constexpr int kPwRec = 12;      // floats of an aircraft-step record
 constexpr int kPwPar = 24;      // floats of an aircraft parameter row
 
 // record fields (phase 1 -> phase 2)
@@ -55,54 +60,82 @@ enum : int {
 };
 constexpr uint32_t F_VIOL = 1u, F_LANDOK = 2u, F_DEP = 4u;
 
-template <int NMAX>
-constexpr int pw_nb() { return NMAX <= 32 ? 8 : NMAX - 32; }
 // waves per SIMD the register budget is set for: the world state takes
-// 3 NMAX VGPRs (x, y and the cost sum of every aircraft)
+// 2 NMAX VGPRs (x and y of every aircraft), the cost sums NMAX x 64 floats
+// of LDS per wave
 template <int NMAX>
 constexpr int pw_waves() { return NMAX <= 48 ? 2 : 1; }
 
 }  // namespace
 
+typedef float F2 __attribute__((ext_vector_type(2)));
+
+// The wind lookup of one aircraft in every world of the wave, issued one
+// aircraft ahead of its use so that the loads overlap the previous
+// aircraft's arithmetic: the position, the cell fractions and the eight
+// corners (x, y components) of this lane's sample.
+struct PwTap {
+    float xi, yi, tx, ty, tz;
+    F2 c[8];
+};
+
+// Issue the lookup of aircraft i (its position before this step's update;
+// the altitude cell and fraction come from its phase-1 record); x, y: the
+// half holding aircraft i, at index ii.
+template <typename V>
+__device__ __forceinline__ PwTap pw_issue(const RollConst<float>& q, const float* __restrict__ rec,
+                                          const __amdgpu_buffer_rsrc_t wrs, int s_z, int s_y,
+                                          int s_x, int vbase, int M, int i, int ii, const V& x,
+                                          const V& y) {
+    PwTap t;
+    t.xi = x[ii];
+    t.yi = y[ii];
+    const float2 zc = *reinterpret_cast<const float2*>(rec + i * kPwRec + 4);   // cell, fraction
+    const float fx = clampr(m_fma(t.xi, q.inv_hx, q.ox), 0.f, q.fnx1);
+    const float fy = clampr(m_fma(t.yi, q.inv_hy, q.oy), 0.f, q.fny1);
+    const float flx = m_floor(clampr(fx, 0.f, q.fnx2));
+    const float fly = m_floor(clampr(fy, 0.f, q.fny2));
+    t.tx = fx - flx;
+    t.ty = fy - fly;
+    t.tz = zc.y;
+    const int g = (int)m_fma(m_fma(flx, q.fny, fly), q.fnz, zc.x);
+    const int vo = g * (M * 8) + vbase;
+    const int off[8] = {0, s_z, s_y, s_y + s_z, s_x, s_x + s_z, s_x + s_y, s_x + s_y + s_z};
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        t.c[c] = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, off[c], 0));
+    return t;
+}
+
 // One aircraft of phase 2 in every world of the wave (aircraft i, index ii
-// = i - 32 HI into the upper halves).  x, y, acc: this half's vectors;
-// xlo, ylo: the lower halves (pair partners below 32); masks per half.
+// = i - 32 HI into the upper halves).  x, y: this half's vectors; xlo,
+// ylo: the lower halves (pair partners below 32); masks per half; accl:
+// this lane's cost sums in LDS, aircraft i at accl[i * 64].
+// The vectors are written once each, unconditionally, at a uniform index
+// (values chosen by selects), so that no vector is carried through a
+// divergent branch.
 template <bool HI, typename VX>
 __device__ __forceinline__ void pw_aircraft(
     const RolloutParams& p, const RolloutArrays& a, const float* __restrict__ par,
-    const float* __restrict__ rec, const __amdgpu_buffer_rsrc_t wrs, int s_z, int s_y, int s_x,
-    int vbase, int M, int i, uint64_t actk, float zn_lane, VX& x, VX& y, VX& acc,
-    const v32f& xlo, const v32f& ylo, uint32_t done0, uint32_t& done, uint32_t& bad,
-    uint32_t& sepbad, uint32_t& sepbad_lo, int& nhor) {
+    const float* __restrict__ rec, const PwTap& w, int i, uint64_t actk, float zn_lane, VX& x,
+    VX& y, float* __restrict__ accl, const v32f& xlo, const v32f& ylo, uint32_t done0,
+    uint32_t& done, uint32_t& bad, uint32_t& sepbad, uint32_t& sepbad_lo, int& nhor) {
     typedef Ops<float> O;
     const RollConst<float>& q = p.cf;
     const int ii = HI ? i - 32 : i;
     const uint32_t bit = 1u << ii;
     const float4* r4 = reinterpret_cast<const float4*>(rec + i * kPwRec);
     const float4 ra = r4[0], rb = r4[1], rc = r4[2];
-    // wave-uniform flags of the record, moved to a scalar register so that
-    // the arrival / departure choice is a uniform branch
+    // wave-uniform parts of the record moved to scalar registers: the
+    // arrival / departure choice and the noise weight are uniform branches
     const uint32_t flags = __builtin_amdgcn_readfirstlane(__float_as_uint(rc.z));
+    const float na = uniform_real(rc.x);
     const bool wasdone = (done0 & bit) != 0u;
-    const float xi = x[ii], yi = y[ii];
+    const float xi = w.xi, yi = w.yi, tx = w.tx, ty = w.ty, tz = w.tz;
 
     // trilinear wind of this world's sample at (x, y, z)
-    const float fx = clampr(m_fma(xi, q.inv_hx, q.ox), 0.f, q.fnx1);
-    const float fy = clampr(m_fma(yi, q.inv_hy, q.oy), 0.f, q.fny1);
-    const float flx = m_floor(clampr(fx, 0.f, q.fnx2));
-    const float fly = m_floor(clampr(fy, 0.f, q.fny2));
-    const float tx = fx - flx, ty = fy - fly, tz = rb.y;
-    const int g = (int)m_fma(m_fma(flx, q.fny, fly), q.fnz, rb.x);
-    const int vo = g * (M * 8) + vbase;
-    typedef float F2 __attribute__((ext_vector_type(2)));
-    const F2 c000 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, 0, 0));
-    const F2 c001 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_z, 0));
-    const F2 c010 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_y, 0));
-    const F2 c011 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_y + s_z, 0));
-    const F2 c100 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_x, 0));
-    const F2 c101 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_x + s_z, 0));
-    const F2 c110 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_x + s_y, 0));
-    const F2 c111 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, s_x + s_y + s_z, 0));
+    const F2 c000 = w.c[0], c001 = w.c[1], c010 = w.c[2], c011 = w.c[3];
+    const F2 c100 = w.c[4], c101 = w.c[5], c110 = w.c[6], c111 = w.c[7];
     const float a00x = c000.x + tz * (c001.x - c000.x), a00y = c000.y + tz * (c001.y - c000.y);
     const float a01x = c010.x + tz * (c011.x - c010.x), a01y = c010.y + tz * (c011.y - c010.y);
     const float a10x = c100.x + tz * (c101.x - c100.x), a10y = c100.y + tz * (c101.y - c100.y);
@@ -137,7 +170,7 @@ __device__ __forceinline__ void pw_aircraft(
         const float tt = m_min(m_max(pi_[A_DTMA] - r, 0.f) * rb.w, 1.f);
         cst = q.c_brg * brg + rb.z + q.a_time * tt;
     }
-    if (p.use_noise) {
+    if (p.use_noise && na != 0.f) {   // uniform: below the noise altitude
         const float fpx = clampr(m_fma(xn, q.pop_inv_hx, q.pop_ox), 0.f, q.fpnx1);
         const float fpy = clampr(m_fma(yn, q.pop_inv_hy, q.pop_oy), 0.f, q.fpny1);
         const int px = min((int)fpx, p.pop_nx - 2), py = min((int)fpy, p.pop_ny - 2);
@@ -149,17 +182,15 @@ __device__ __forceinline__ void pw_aircraft(
         const F2 p1 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(prs, po, p.pop_nx * 4, 0));
         const float pd = (1.f - ux) * (1.f - uy) * p0.x + ux * (1.f - uy) * p0.y +
                          (1.f - ux) * uy * p1.x + ux * uy * p1.y;
-        if (!landed) cst += rc.x * pd;
+        cst += landed ? 0.f : na * pd;
     }
-    const float ai = acc[ii];
-    acc[ii] = wasdone ? ai : ai + (cst + rc.y);
-    if (landed) done |= bit;
-    if (flags & F_VIOL) {     // uniform: a unary violation at this step
-        if (!wasdone) bad |= bit;
-    }
-    // parked from the step after landing on
+    accl[i * 64] += wasdone ? 0.f : cst + rc.y;
+    done |= landed ? bit : 0u;
+    bad |= ((flags & F_VIOL) != 0u && !wasdone) ? bit : 0u;
+    // parked from the step after landing on (far away in x, distinct per
+    // aircraft; y keeps moving, finite and unused)
     const float xs = wasdone ? (float)kGoneX + (float)kGoneDX * (float)i : xn;
-    const float ys = wasdone ? yi : yn;
+    const float ys = yn;
     x[ii] = xs;
     y[ii] = ys;
 
@@ -192,6 +223,36 @@ __device__ __forceinline__ void pw_aircraft(
     }
 }
 
+// Phase 2 over the active aircraft of one half (bits of `todo`, aircraft
+// index base + bit), the wind lookup of the next aircraft issued before
+// this one's arithmetic.
+template <bool HI, typename VX>
+__device__ __forceinline__ void pw_half(
+    const RolloutParams& p, const RolloutArrays& a, const float* __restrict__ par,
+    const float* __restrict__ rec, const __amdgpu_buffer_rsrc_t wrs, int s_z, int s_y, int s_x,
+    int vbase, int M, uint32_t todo, uint64_t actk, float zn_lane, VX& x, VX& y,
+    float* __restrict__ accl,
+    const v32f& xlo, const v32f& ylo, uint32_t done0, uint32_t& done, uint32_t& bad,
+    uint32_t& sepbad, uint32_t& sepbad_lo, int& nhor) {
+    if (!todo) return;
+    const int base = HI ? 32 : 0;
+    int ii = __builtin_ctz(todo);
+    PwTap cur = pw_issue(p.cf, rec, wrs, s_z, s_y, s_x, vbase, M, base + ii, ii, x, y);
+    while (true) {                                                 // uniform
+        todo &= todo - 1u;
+        // the next aircraft's lookup (after the last one, a repeat of this
+        // one's, unused): issued unconditionally so that it stays ahead of
+        // this aircraft's arithmetic
+        const int inext = todo ? __builtin_ctz(todo) : ii;
+        const PwTap nxt = pw_issue(p.cf, rec, wrs, s_z, s_y, s_x, vbase, M, base + inext, inext, x, y);
+        pw_aircraft<HI>(p, a, par, rec, cur, base + ii, actk, zn_lane, x, y, accl, xlo, ylo, done0,
+                        done, bad, sepbad, sepbad_lo, nhor);
+        if (!todo) break;
+        ii = inext;
+        cur = nxt;
+    }
+}
+
 template <int NMAX>
 __global__ void __launch_bounds__(64 * kPwWaves, pw_waves<NMAX>())
 k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restrict__ acR,
@@ -200,14 +261,33 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
     typedef Ops<float> O;
     __shared__ __attribute__((aligned(16))) float par[NMAX * kPwPar];
     __shared__ __attribute__((aligned(16))) float recs[kPwWaves * NMAX * kPwRec];
+    // per-world cost sums [wave][aircraft][lane] (LDS, so that the sum of
+    // the aircraft at a uniform index needs no register indexing)
+    __shared__ float accs[kPwWaves * NMAX * 64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int N = p.N, S = p.S, H = p.H, M = p.M;
     const int nmb = (M + 63) >> 6;                      // 64-sample blocks per particle
-    const int64_t wave = (int64_t)blockIdx.x * kPwWaves + wv;
-    const int64_t nwave = (int64_t)p.P * nmb;
-    const bool wvalid = wave < nwave;
-    const int l = wvalid ? (int)(wave / nmb) : 0;
-    const int m = (wvalid ? (int)(wave % nmb) : 0) * 64 + lane;
+    // workgroup -> (sample block, particles): workgroups go to the eight
+    // XCDs in turn, so when the blocks divide 8, every XCD keeps to one block
+    // of samples (its L2 holds that block's fields) and the workgroup's
+    // waves take consecutive particles; otherwise waves run in (particle,
+    // block) order
+    int mb;
+    int64_t l64;
+    if ((kXcds % nmb) == 0) {
+        const int xcd = (int)(blockIdx.x % kXcds);
+        const int64_t slot = blockIdx.x / kXcds;
+        mb = xcd % nmb;
+        l64 = ((slot * (kXcds / nmb) + xcd / nmb) * kPwWaves) + wv;
+    } else {
+        const int64_t wave = (int64_t)blockIdx.x * kPwWaves + wv;
+        mb = (int)(wave % nmb);
+        l64 = wave / nmb;
+    }
+    const int64_t wave = l64 * nmb + mb;                // counter slot
+    const bool wvalid = l64 < p.P;
+    const int l = wvalid ? (int)l64 : 0;
+    const int m = (wvalid ? mb : 0) * 64 + lane;
     const bool valid = wvalid && m < M;
     const RollConst<float>& q = p.cf;
 
@@ -246,21 +326,22 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
 
     // phase-2 state: one world per lane, all aircraft; aircraft i < 32 in
     // the lower halves, i >= 32 in the upper ones
-    v32f xa, ya, acca;
-    vBf xb, yb, accb;
+    v32f xa, ya;
+    vBf xb, yb;
+    float* accl = accs + wv * NMAX * 64 + lane;
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) accl[i * 64] = 0.f;
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
         const int ic = i < N ? i : 0;
         xa[i] = (float)a.states[6 * ic];
         ya[i] = (float)a.states[6 * ic + 1];
-        acca[i] = 0.f;
     }
 #pragma unroll
     for (int i = 0; i < pw_nb<NMAX>(); ++i) {
         const int ic = i + 32 < N ? i + 32 : 0;
         xb[i] = (float)a.states[6 * ic];
         yb[i] = (float)a.states[6 * ic + 1];
-        accb[i] = 0.f;
     }
     uint32_t done_lo = 0u, done_hi = 0u, bad_lo = 0u, bad_hi = 0u, sep_lo = 0u, sep_hi = 0u;
     int nsim = 0, npair = 0, nhor = 0;
@@ -274,7 +355,6 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
     // lanes past the last sample (M not a multiple of 64) read sample M - 1
     // and write nothing
     const int vbase = (m < M ? m : M - 1) * 8;
-    const int nlo = N < 32 ? N : 32;
 
     int s_cur = -1, k_end = 0;
     for (int k = 0; k < H; ++k) {
@@ -352,20 +432,15 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
             wave_sync();   // records visible to every lane
         }
 
-        // ---- phase 2: every world runs the aircraft in turn ----
+        // ---- phase 2: every world runs the active aircraft in turn, the
+        // wind lookup of the next one issued before this one's arithmetic ----
         const uint32_t d0lo = done_lo, d0hi = done_hi;
-        for (int i = 0; i < nlo; ++i) {
-            if (!((actk >> i) & 1ull)) continue;                    // uniform
-            pw_aircraft<false>(p, a, par, recw, wrs, s_z, s_y, s_x, vbase, M, i, actk, zn_lane,
-                               xa, ya, acca, xa, ya, d0lo, done_lo, bad_lo, sep_lo, sep_lo, nhor);
-        }
-        if (NMAX > 32) {
-            for (int i = 32; i < N; ++i) {
-                if (!((actk >> i) & 1ull)) continue;                // uniform
-                pw_aircraft<true>(p, a, par, recw, wrs, s_z, s_y, s_x, vbase, M, i, actk, zn_lane,
-                                  xb, yb, accb, xa, ya, d0hi, done_hi, bad_hi, sep_hi, sep_lo, nhor);
-            }
-        }
+        pw_half<false>(p, a, par, recw, wrs, s_z, s_y, s_x, vbase, M, (uint32_t)actk, actk,
+                       zn_lane, xa, ya, accl, xa, ya, d0lo, done_lo, bad_lo, sep_lo, sep_lo, nhor);
+        if (NMAX > 32)
+            pw_half<true>(p, a, par, recw, wrs, s_z, s_y, s_x, vbase, M, (uint32_t)(actk >> 32),
+                          actk, zn_lane, xb, yb, accl, xa, ya, d0hi, done_hi, bad_hi, sep_hi,
+                          sep_lo, nhor);
         {   // aircraft simulated this step and pair tests with both present
             const uint64_t pres = actk & ~(((uint64_t)d0hi << 32) | d0lo);
             const int np = __popcll(pres);
@@ -378,7 +453,7 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
         const uint64_t badm = ((uint64_t)(bad_hi | sep_hi) << 32) | (bad_lo | sep_lo);
         for (int i = 0; i < N; ++i) {
             const int k0 = a.k_active[i];
-            const float ai = i < 32 ? acca[i] : accb[(i - 32) & (pw_nb<NMAX>() - 1)];
+            const float ai = accl[i * 64];
             const double cost = (k0 >= 0 && k0 < H) ? (double)ai / (double)(H - k0) : 0.0;
             const int64_t o = ((int64_t)m * p.P + l) * N + i;
             a.cost[o] = cost;
@@ -411,8 +486,16 @@ bool rollout_pw_supported(int N, int prec) { return prec == 1 && N >= 1 && N <= 
 template <int NMAX>
 static hipError_t launch_pw_n(const RolloutParams& p, const RolloutArrays& a, const void* acR,
                               const void* Wt, hipStream_t st) {
-    const int64_t nwave = (int64_t)p.P * ((p.M + 63) / 64);
-    const int64_t blocks = (nwave + kPwWaves - 1) / kPwWaves;
+    const int nmb = (p.M + 63) / 64;
+    int64_t blocks;
+    if ((kXcds % nmb) == 0) {
+        // whole rounds of the eight XCDs: each holds ceil(P / (4 * 8 / nmb))
+        // workgroups of 4 particles of its sample block
+        const int64_t per_round = (int64_t)kPwWaves * (kXcds / nmb);
+        blocks = (((int64_t)p.P + per_round - 1) / per_round) * kXcds;
+    } else {
+        blocks = ((int64_t)p.P * nmb + kPwWaves - 1) / kPwWaves;
+    }
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_rollout_pw<NMAX>), dim3((unsigned)blocks), dim3(64 * kPwWaves), 0, st,
                        p, a, (const float*)acR, (const float*)Wt);

@@ -19,10 +19,14 @@
 
 namespace smc {
 
-template <typename R, int NMAX>
+// PC: the paper's per-step thrust / flight-path angle / bank controls (Sec.
+// "Trajectory Planning and Disturbance Realisations", eq. hor) in place of
+// the kinematic segment controls.
+template <typename R, int NMAX, bool PC>
 __global__ void __launch_bounds__(256, (wm_waves<R, NMAX>()))
 k_rollout_wm(const RolloutParams p, const RolloutArrays a, const R* __restrict__ acR) {
     constexpr bool kTV = false;
+    constexpr bool kPC = PC;
     extern __shared__ unsigned char smem_raw[];
     R* uc = reinterpret_cast<R*>(smem_raw);   // [N][3][blockDim.x]
     const int tid = threadIdx.x;
@@ -42,8 +46,12 @@ static hipError_t launch_wm_n(const RolloutParams& p, const RolloutArrays& a, co
     const int64_t nworld = (int64_t)p.P * p.M;
     const unsigned blocks = (unsigned)((nworld + block - 1) / block);
     const size_t lds = (size_t)NMAX * 3 * block * sizeof(R);
-    hipLaunchKernelGGL((k_rollout_wm<R, NMAX>), dim3(blocks), dim3(block), lds, st, p, a,
-                       (const R*)acR);
+    if (p.control_model == 1)
+        hipLaunchKernelGGL((k_rollout_wm<R, NMAX, true>), dim3(blocks), dim3(block), lds, st, p,
+                           a, (const R*)acR);
+    else
+        hipLaunchKernelGGL((k_rollout_wm<R, NMAX, false>), dim3(blocks), dim3(block), lds, st, p,
+                           a, (const R*)acR);
     return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@ template <typename R, int NMAX>
 __global__ void __launch_bounds__(256, (wm_waves<R, NMAX>()))
 k_rollout_wm_tv(const RolloutParams p, const RolloutArrays a, const R* __restrict__ acR) {
     constexpr bool kTV = true;
+    constexpr bool kPC = false;
     extern __shared__ unsigned char smem_raw[];
     R* uc = reinterpret_cast<R*>(smem_raw);   // [N][3][blockDim.x]
     const int tid = threadIdx.x;

@@ -196,6 +196,24 @@ smc_status validate(const smc_scenario* s) {
         if ((double)s->horizon_max * s->n_wind * G * 2 * rbytes >= 2147483648.0)
             return fail(nullptr, SMC_EINVAL, "time-correlated wind: the fields of all steps must take below 2^31 bytes");
     }
+    if (s->control_model != SMC_CONTROLS_KINEMATIC && s->control_model != SMC_CONTROLS_PAPER)
+        return fail(nullptr, SMC_EINVAL, "control_model must be SMC_CONTROLS_KINEMATIC or SMC_CONTROLS_PAPER");
+    if (s->control_model == SMC_CONTROLS_PAPER) {
+        if (s->n_segments < s->horizon_max)
+            return fail(nullptr, SMC_EINVAL, "the paper's controls need n_segments >= horizon_max (one control set per step)");
+        if (s->n_aircraft > kWorldLaneMaxN)
+            return fail(nullptr, SMC_EINVAL, "the paper's controls support at most %d aircraft", kWorldLaneMaxN);
+        if (s->wind_model != SMC_WIND_SE)
+            return fail(nullptr, SMC_EINVAL, "the paper's controls take the static wind model");
+        if (s->move == SMC_MOVE_MALA)
+            return fail(nullptr, SMC_EINVAL, "the paper's controls do not support the gradient move");
+        if (!(s->ctrl_lo[0] >= 0) || !(s->ctrl_lo[1] > -1.5707963267948966) ||
+            !(s->ctrl_hi[1] < 1.5707963267948966) || !(s->ctrl_lo[2] > -1.5707963267948966) ||
+            !(s->ctrl_hi[2] < 1.5707963267948966))
+            return fail(nullptr, SMC_EINVAL, "the paper's controls: thrust fraction >= 0 and |angles| < pi/2");
+    } else if (!(s->ctrl_lo[1] > 0)) {
+        return fail(nullptr, SMC_EINVAL, "airspeed control must be > 0");
+    }
     if (!(s->sep_h >= 0) || !(s->sep_v >= 0)) return fail(nullptr, SMC_EINVAL, "separations must be >= 0");
     if (!s->kind || !s->aircraft || !s->targets)
         return fail(nullptr, SMC_EINVAL, "kind, aircraft and targets are required");
@@ -209,7 +227,6 @@ smc_status validate(const smc_scenario* s) {
             return fail(nullptr, SMC_EINVAL, "aircraft[%d]: angle limits must be in (0, pi/2)", i);
         if (!(s->env[2] > 0)) return fail(nullptr, SMC_EINVAL, "v_min must be > 0");
     }
-    if (!(s->ctrl_lo[1] > 0)) return fail(nullptr, SMC_EINVAL, "airspeed control must be > 0");
     if (!(s->time_norm > 0) || !(s->noise_alt > 0))
         return fail(nullptr, SMC_EINVAL, "time_norm and noise_alt must be > 0");
     if (s->popdense && (s->pop_n[0] < 2 || s->pop_n[1] < 2))
@@ -287,6 +304,7 @@ RolloutArrays rollout_arrays(smc_ctx* c, const void* u, const void* W, const dou
 // sample-interleaved layout the wave's lanes read), aircraft-per-lane
 // otherwise; or the layout asked for.
 int rollout_layout(const smc_ctx* c) {
+    if (c->rp.control_model == SMC_CONTROLS_PAPER) return 2;
     if (c->layout != 0) return c->layout;
     if (rollout_wm_supported(c->N)) return 2;
     return rollout_pw_supported(c->N, c->prec) ? 3 : 1;
@@ -309,7 +327,9 @@ hipError_t do_rollout(smc_ctx* c, const RolloutParams& rp, const RolloutArrays& 
 smc_status check_horizon(smc_ctx* c, int32_t horizon) {
     if (horizon < 1 || horizon > c->Hmax)
         return fail(c, SMC_EINVAL, "horizon %d outside [1, %d]", horizon, c->Hmax);
-    if (horizon < c->S)
+    // kinematic segments must not be empty; the paper's per-step controls
+    // take control set k at step k whatever the horizon
+    if (c->rp.control_model == SMC_CONTROLS_KINEMATIC && horizon < c->S)
         return fail(c, SMC_EINVAL, "horizon %d shorter than n_segments %d", horizon, c->S);
     return SMC_OK;
 }
@@ -653,7 +673,12 @@ void fill_rollout_params(const smc_scenario* s, RolloutParams& rp) {
     rp.p_vs = s->landing[3]; rp.beta_f = s->landing[4];
     for (int a = 0; a < 9; ++a) rp.w[a] = s->cost_w[a];
     rp.time_norm = s->time_norm; rp.noise_alt = s->noise_alt;
-    rp.zdot_max = std::max(std::fabs(s->ctrl_lo[2]), std::fabs(s->ctrl_hi[2]));
+    rp.control_model = s->control_model;
+    // bound of the climb rate (departure altitude band): the climb-rate
+    // control's, or v_max sin(gamma bound) for the flight-path angle
+    rp.zdot_max = s->control_model == SMC_CONTROLS_PAPER
+                      ? s->env[3] * std::sin(std::max(std::fabs(s->ctrl_lo[1]), std::fabs(s->ctrl_hi[1])))
+                      : std::max(std::fabs(s->ctrl_lo[2]), std::fabs(s->ctrl_hi[2]));
     fill_rollout_consts(rp);
 }
 
@@ -987,6 +1012,8 @@ smc_status smc_plant_step(smc_ctx* c, int64_t mpc_step, int32_t plant_iter, cons
     if (plant_iter < 0) return fail(c, SMC_EINVAL, "plant_iter must be >= 0");
     if (c->wind_model != SMC_WIND_SE)
         return fail(c, SMC_EINVAL, "smc_plant_step: static wind model only");
+    if (c->rp.control_model != SMC_CONTROLS_KINEMATIC)
+        return fail(c, SMC_EINVAL, "smc_plant_step: kinematic controls only");
     hipStream_t st = c->stream;
     const int N = c->N;
     HIP_OK(c, hipMemcpyAsync(c->d_states, states, sizeof(double) * N * 6, hipMemcpyHostToDevice, st));
@@ -1261,6 +1288,8 @@ smc_status smc_set_rollout_layout(smc_ctx* c, int32_t layout) {
     if (!c || layout < 0 || layout > 3) return fail(c, SMC_EINVAL, "smc_set_rollout_layout: bad arguments");
     if (layout == 2 && !rollout_wm_supported(c->N))
         return fail(c, SMC_EINVAL, "world-per-lane rollout supports at most %d aircraft", kWorldLaneMaxN);
+    if (c->rp.control_model == SMC_CONTROLS_PAPER && layout != 0 && layout != 2)
+        return fail(c, SMC_EINVAL, "the paper's controls run the world-per-lane rollout only");
     if (layout == 3 && !rollout_pw_supported(c->N, c->prec))
         return fail(c, SMC_EINVAL, "particle-per-wave rollout: FP32 contexts only");
     if ((layout == 1 || layout == 3) && c->wind_model != SMC_WIND_SE)

@@ -29,6 +29,8 @@ units (angles in radians).  Field list, in the order the C ABI takes them:
                dep spd, alpha_time, alpha_noise),
     time_norm, noise_alt, popdense[ny_p, nx_p] float32 or None,
     precision (0 fp64, 1 fp32), move (0 jitter, 1 rwmh, 2 mala),
+    control_model (0 kinematic segment controls, 1 the paper's per-step
+    thrust fraction / flight-path angle / bank, S = H),
     kappa, sigma_move, mala_step (standard deviation of the Langevin proposal
     in logit coordinates: the time step h = 1e-2 of the differentiable
     workload gives sqrt(h) = 0.1), seed,
@@ -54,6 +56,7 @@ MIX_WEIGHTS = (0.25, 0.65, 0.10, 0.40, 0.10, 0.25, 0.25)
 PRECISION = {"fp64": 0, "fp32": 1}
 MOVES = {"jitter": 0, "rwmh": 1, "mala": 2}
 WIND_MODELS = {"se": 0, "ar1": 1}   # static squared-exponential; the paper's time recursion
+CONTROL_MODELS = {"kinematic": 0, "paper": 1}
 
 
 def _aircraft_params(rng: np.random.Generator, n: int) -> np.ndarray:
@@ -123,7 +126,7 @@ def make_scenario(name: str, *, n_arr: int, n_dep: int, box, grid, H: int,
                   noise_alt: float = 2000.0, pop_n=None, kappa: float = 1.0,
                   sigma_move: float = 0.02, mala_step: float = 0.1,
                   mpc_step: int = 0, wind_model: str = "se",
-                  wind_tcorr: float = 1800.0) -> dict:
+                  wind_tcorr: float = 1800.0, controls: str = "kinematic") -> dict:
     rng = np.random.default_rng(seed)
     box = tuple(float(b) for b in box)
     N = n_arr + n_dep
@@ -148,8 +151,16 @@ def make_scenario(name: str, *, n_arr: int, n_dep: int, box, grid, H: int,
         X = rng.lognormal(mean=0.0, sigma=1.5, size=(pop_n[1], pop_n[0]))
         q90 = math.exp(1.5 * 1.2815515655446004)
         popdense = np.minimum(X / q90, 1.0).astype(np.float32)
-    ctrl_lo = np.array([-3.0 * DEG, 110.0, -15.0])
-    ctrl_hi = np.array([3.0 * DEG, 250.0, 15.0])
+    if controls == "paper":
+        # the paper's per-step controls: thrust (fraction of T_max, up to
+        # about twice the cruise drag), flight-path angle, bank; one control
+        # set per step
+        S = H
+        ctrl_lo = np.array([0.0, -6.0 * DEG, -25.0 * DEG])
+        ctrl_hi = np.array([0.5, 6.0 * DEG, 25.0 * DEG])
+    else:
+        ctrl_lo = np.array([-3.0 * DEG, 110.0, -15.0])
+        ctrl_hi = np.array([3.0 * DEG, 250.0, 15.0])
     env = np.array([0.0, box[2], 110.0, 250.0])
     landing = np.array([8000.0, 6.0 * DEG, 15.0 * DEG, 130.0, 3.0 * DEG])
     cost_w = np.array(list(MIX_WEIGHTS) + [alpha_time, alpha_noise])
@@ -170,6 +181,7 @@ def make_scenario(name: str, *, n_arr: int, n_dep: int, box, grid, H: int,
         # 1): beta, gamma [1/m] as quoted there, G_t [s] a stated choice
         wind_model=WIND_MODELS[wind_model], wind_beta=1.6e-6, wind_gamma=1.5e-5,
         wind_tcorr=float(wind_tcorr),
+        control_model=CONTROL_MODELS[controls],
     )
 
 
@@ -237,6 +249,25 @@ def c5(seed: int = 0, **kw) -> dict:
                 alpha_noise=0.1, noise_alt=2000.0, pop_n=(256, 256), seed=seed)
     args.update(kw)
     return make_scenario("C5", **args)
+
+
+def paper_table(seed: int = 0, **kw) -> dict:
+    """The shape of the paper's timing experiment (Sec. "Simulation Setup",
+    Table comp_sense): 10 aircraft (8 arrivals, 2 departures released 4
+    steps apart), horizon 6 steps of dt = 10 s with the paper's per-step
+    (thrust, flight-path angle, bank) controls, a 2 x 2 x 2 wind grid,
+    10240 particles, 100 SMC iterations weighted literally over
+    SampleSchedule(J) + 1 wind passes (M = SampleSchedule(99) + 1 = 710),
+    in a 80 x 80 x 6 km terminal area."""
+    K = kw.pop("K", 100)
+    M = int(math.floor(3.0 + 5.0 * math.exp(0.05 * (K - 1)))) + 1
+    args = dict(n_arr=8, n_dep=2, box=(80e3, 80e3, 6e3), grid=(2, 2, 2), H=6, dt=10.0,
+                S=6, M=M, L=10240, K=K, precision="fp32", controls="paper", seed=seed,
+                dep_spacing=4)
+    args.update(kw)
+    s = make_scenario("PAPER", **args)
+    s["weighting"] = 1
+    return s
 
 
 def shrink(scen: dict, **kw) -> dict:
