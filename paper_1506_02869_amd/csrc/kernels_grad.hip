@@ -18,6 +18,10 @@
 namespace smc {
 
 constexpr int GR_CK = 25;        // checkpoint interval [steps]
+constexpr int GR_IN = 5;         // inner checkpoint interval within a segment [steps]
+constexpr int GR_NIN = GR_CK / GR_IN;
+static_assert(GR_CK % GR_IN == 0, "inner blocks tile a segment");
+constexpr int GR_BLOCK = 256;    // lanes per workgroup
 constexpr int GR_MAXSEG = 16;    // horizons up to 400 steps
 constexpr int GR_MAXS = 16;      // control segments
 
@@ -279,6 +283,67 @@ __device__ __forceinline__ void flush_segment(const GradParams& gp, int s, const
     }
 }
 
+// One step of the reverse sweep at step k: recompute the step's
+// intermediates from its start state, add the time element's derivative at
+// the new state (unless the step lands) and the fuel's, and carry the
+// adjoint (ax, ay, az, av, achi, aB) of the state back over the step, adding
+// the step's share of the segment's control gradient to gc.
+template <typename R>
+__device__ __forceinline__ void grad_reverse_step(const typename V2<R>::t* Wm,
+                                                  const RolloutParams& p, const AcConst& ac, int k,
+                                                  int k_land, R x0, R y0, R z0, R v0, R chi0,
+                                                  R B0, R cd, R vc, R zd, R ir, R kt, R& ax,
+                                                  R& ay, R& az, R& av, R& achi, R& aB, R* gc) {
+    const R dt = (R)p.dt;
+    StepFwd<R> o;
+    step_forward<R>(Wm, p, ac, x0, y0, z0, v0, chi0, B0, cd, vc, zd, ir, o);
+    const R xn = x0 + dt * (v0 * o.cc * o.cg + o.wx);
+    const R yn = y0 + dt * (v0 * o.sc * o.cg + o.wy);
+    // time element at the new state (counted unless this step lands)
+    if (k < k_land) {
+        R dx, dy, dv;
+        time_elem<R>(p, ac, xn, yn, o.vn, &dx, &dy, &dv);
+        ax += kt * dx; ay += kt * dy; av += kt * dv;
+    }
+    // fuel f = dt eta max(T, 0)
+    R df_dv = 0, df_dvc = 0, df_dzd = 0, df_dcd = 0, df_dz = 0, df_dm = 0;
+    if (o.T > (R)0) {
+        const R g0 = (R)kG0;
+        const R A0 = o.qd * (R)ac.Sw;
+        const R dD_dA0 = (R)ac.cd0 - (R)ac.cd2 * o.CL * o.CL;
+        const R dD_dK = (R)2 * (R)ac.cd2 * o.CL;
+        const R inv_dt = (R)(1.0 / p.dt);
+        const R dT_dv = -o.mass * ir * inv_dt + dD_dA0 * ((R)2 * A0 * Ops<R>::rcp(v0)) +
+                        dD_dK * o.mass * g0 * (o.tphi * Ops<R>::rcp(o.icphi)) * (cd * (R)(1.0 / kG0)) -
+                        o.mass * g0 * o.sg * Ops<R>::rcp(v0);
+        const R dT_dvc = o.mass * ir * inv_dt;
+        const R dT_dzd = o.mass * g0 * Ops<R>::rcp(v0);
+        const R dT_dcd = dD_dK * o.mass * g0 * (o.tphi * Ops<R>::rcp(o.icphi)) * (v0 * (R)(1.0 / kG0));
+        const R dT_dz = dD_dA0 * (A0 * Ops<R>::rcp(o.rho)) * o.drho_dz;
+        const R dT_dm = (o.vn - v0) * inv_dt + dD_dK * g0 * o.icphi + g0 * o.sg;
+        const R dt_eta = dt * o.eta;
+        df_dv = dt * (R)(ac.cf1 / ac.cf2) * o.T + dt_eta * dT_dv;
+        df_dvc = dt_eta * dT_dvc;
+        df_dzd = dt_eta * dT_dzd;
+        df_dcd = dt_eta * dT_dcd;
+        df_dz = dt_eta * dT_dz;
+        df_dm = dt_eta * dT_dm;
+    }
+    const R icg = Ops<R>::rcp(o.cg);
+    // adjoints of the step's inputs
+    const R nx_ = ax * ((R)1 + dt * o.dwx[0]) + ay * dt * o.dwy[0];
+    const R ny_ = ax * dt * o.dwx[1] + ay * ((R)1 + dt * o.dwy[1]);
+    const R nz_ = az + ax * dt * o.dwx[2] + ay * dt * o.dwy[2] + aB * df_dz;
+    const R nchi = achi + ax * dt * (-v0 * o.sc * o.cg) + ay * dt * (v0 * o.cc * o.cg);
+    const R nv = av * ((R)1 - ir) + ax * dt * o.cc * icg + ay * dt * o.sc * icg + aB * df_dv;
+    const R nB = aB - aB * df_dm;
+    gc[0] += achi * dt + aB * df_dcd;
+    gc[1] += av * ir + aB * df_dvc;
+    gc[2] += ax * dt * o.cc * (-o.sg * icg) + ay * dt * o.sc * (-o.sg * icg) + az * dt +
+             aB * df_dzd;
+    ax = nx_; ay = ny_; az = nz_; achi = nchi; av = nv; aB = nB;
+}
+
 // Adjoint of the fuel + time cost of one (particle, aircraft, wind sample)
 // per lane.  The step loops run over absolute steps, the same for every lane
 // of a wave (a lane takes part in the steps k0 <= k <= its last step), so the
@@ -287,7 +352,7 @@ __device__ __forceinline__ void flush_segment(const GradParams& gp, int s, const
 // segment's gradient is summed over its steps in three registers and reduced
 // over the wind samples when the reverse sweep leaves the segment.
 template <typename R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_rollout_grad(const GradParams gp, const R* __restrict__ u,
+__global__ void __launch_bounds__(GR_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_rollout_grad(const GradParams gp, const R* __restrict__ u,
                                                       const R* __restrict__ W,
                                                       const double* __restrict__ states,
                                                       const int32_t* __restrict__ k_active,
@@ -318,7 +383,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     const R* ub = u + ((int64_t)l * N + i) * S * 3;
     const double lo[3] = {p.ctrl_lo[0], p.ctrl_lo[1], p.ctrl_lo[2]};
     const double sp[3] = {p.ctrl_span[0], p.ctrl_span[1], p.ctrl_span[2]};
-    const R dt = (R)p.dt;
 
     // forward sweep: checkpoints at every GR_CK-th step and the landing step
     R ck[GR_MAXSEG][6];
@@ -345,7 +409,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         }
     }
 
-    // reverse sweep, segment by segment from the last
+    // reverse sweep, segment by segment from the last.  Two levels of
+    // recomputation keep the tape in registers: a pass over the segment
+    // from its checkpoint stores the state every GR_IN steps in LDS (this
+    // lane's column), then each block of GR_IN steps, from the last, is
+    // recomputed into a tape indexed at compile time and swept backwards.
+    __shared__ R ick[GR_NIN][6][GR_BLOCK];
+    const int tl = threadIdx.x;
     const int k_last = min(k_land, H - 1);
     const int nsteps = H - k0;
     const double wf = ac.arr ? p.w[2] : p.w[4];
@@ -354,19 +424,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     const R kt = (R)(p.w[7] / (double)nsteps);
     R ax = 0, ay = 0, az = 0, av = 0, achi = 0, aB = kf;
     R gc[3] = {(R)0, (R)0, (R)0};
-    R tx_[GR_CK], ty_[GR_CK], tz_[GR_CK], tv_[GR_CK], tchi_[GR_CK], tB_[GR_CK];
     const int nseg = (H + GR_CK - 1) / GR_CK;
     int s_grad = S - 1;      // segment whose gradient gc holds
     s_cur = -1;
     for (int j = nseg - 1; j >= 0; --j) {
         const int ka = j * GR_CK;
         const int kb = min(H, ka + GR_CK) - 1;
-        {   // the segment's step-start states from its checkpoint
+        {   // inner checkpoints: the state at the start of each block
             R x1 = ck[j][0], y1 = ck[j][1], z1 = ck[j][2], v1 = ck[j][3], chi1 = ck[j][4],
               B1 = ck[j][5];
             for (int k = ka; k <= kb; ++k) {
-                const int q = k - ka;
-                tx_[q] = x1; ty_[q] = y1; tz_[q] = z1; tv_[q] = v1; tchi_[q] = chi1; tB_[q] = B1;
+                if (((k - ka) % GR_IN) == 0) {
+                    R* c = &ick[(k - ka) / GR_IN][0][tl];
+                    c[0] = x1; c[GR_BLOCK] = y1; c[2 * GR_BLOCK] = z1; c[3 * GR_BLOCK] = v1;
+                    c[4 * GR_BLOCK] = chi1; c[5 * GR_BLOCK] = B1;
+                }
                 if (k == kb) break;
                 const int s = (k * S) / H;
                 if (s != s_cur) {
@@ -379,70 +451,52 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                                   Ops<R>::rcp((R)(k_end - k)));
             }
         }
-        for (int k = kb; k >= ka; --k) {
-            const int q = k - ka;
-            const int s = (k * S) / H;
-            if (s != s_grad) {   // wave-uniform: the reverse sweep leaves segment s_grad
-                flush_segment<R>(gp, s_grad, gc, sp, m, grp, ngrp, l, i, out);
-                gc[0] = gc[1] = gc[2] = (R)0;
-                s_grad = s;
+        for (int b = (kb - ka) / GR_IN; b >= 0; --b) {
+            const int kc = ka + b * GR_IN;           // first step of the block
+            const int kd = min(kb, kc + GR_IN - 1);  // last step of the block
+            R tx_[GR_IN], ty_[GR_IN], tz_[GR_IN], tv_[GR_IN], tchi_[GR_IN], tB_[GR_IN];
+            {   // the block's step-start states (the tape)
+                const R* c = &ick[b][0][tl];
+                R x1 = c[0], y1 = c[GR_BLOCK], z1 = c[2 * GR_BLOCK], v1 = c[3 * GR_BLOCK],
+                  chi1 = c[4 * GR_BLOCK], B1 = c[5 * GR_BLOCK];
+#pragma unroll
+                for (int q = 0; q < GR_IN; ++q) {
+                    const int k = kc + q;
+                    tx_[q] = x1; ty_[q] = y1; tz_[q] = z1; tv_[q] = v1; tchi_[q] = chi1; tB_[q] = B1;
+                    if (k >= kd) continue;           // uniform
+                    const int s = (k * S) / H;
+                    if (s != s_cur) {
+                        s_cur = s;
+                        k_end = ((s + 1) * H + S - 1) / S;
+                        seg_controls<R>(ub, s, lo, sp, cd, vc, zd);
+                    }
+                    if (active && k >= k0 && k <= k_last)
+                        step_state<R>(Wm, p, ac, x1, y1, z1, v1, chi1, B1, cd, vc, zd,
+                                      Ops<R>::rcp((R)(k_end - k)));
+                }
             }
-            if (s != s_cur) {
-                s_cur = s;
-                k_end = ((s + 1) * H + S - 1) / S;
-                seg_controls<R>(ub, s, lo, sp, cd, vc, zd);
+#pragma unroll
+            for (int q = GR_IN - 1; q >= 0; --q) {
+                const int k = kc + q;
+                if (k > kd) continue;                // uniform
+                const int s = (k * S) / H;
+                if (s != s_grad) {   // wave-uniform: the reverse sweep leaves segment s_grad
+                    flush_segment<R>(gp, s_grad, gc, sp, m, grp, ngrp, l, i, out);
+                    gc[0] = gc[1] = gc[2] = (R)0;
+                    s_grad = s;
+                }
+                if (s != s_cur) {
+                    s_cur = s;
+                    k_end = ((s + 1) * H + S - 1) / S;
+                    seg_controls<R>(ub, s, lo, sp, cd, vc, zd);
+                }
+                if (!(active && k >= k0 && k <= k_last)) continue;
+                const R x0 = tx_[q], y0 = ty_[q], z0 = tz_[q], v0 = tv_[q], chi0 = tchi_[q],
+                        B0 = tB_[q];
+                grad_reverse_step<R>(Wm, p, ac, k, k_land, x0, y0, z0, v0, chi0, B0, cd, vc, zd,
+                                     Ops<R>::rcp((R)(k_end - k)), kt, ax, ay, az, av, achi, aB,
+                                     gc);
             }
-            if (!(active && k >= k0 && k <= k_last)) continue;
-            const R x0 = tx_[q], y0 = ty_[q], z0 = tz_[q], v0 = tv_[q], chi0 = tchi_[q],
-                    B0 = tB_[q];
-            const R ir = Ops<R>::rcp((R)(k_end - k));
-            StepFwd<R> o;
-            step_forward<R>(Wm, p, ac, x0, y0, z0, v0, chi0, B0, cd, vc, zd, ir, o);
-            const R xn = x0 + dt * (v0 * o.cc * o.cg + o.wx);
-            const R yn = y0 + dt * (v0 * o.sc * o.cg + o.wy);
-            // time element at the new state (counted unless this step lands)
-            if (k < k_land) {
-                R dx, dy, dv;
-                time_elem<R>(p, ac, xn, yn, o.vn, &dx, &dy, &dv);
-                ax += kt * dx; ay += kt * dy; av += kt * dv;
-            }
-            // fuel f = dt eta max(T, 0)
-            R df_dv = 0, df_dvc = 0, df_dzd = 0, df_dcd = 0, df_dz = 0, df_dm = 0;
-            if (o.T > (R)0) {
-                const R g0 = (R)kG0;
-                const R A0 = o.qd * (R)ac.Sw;
-                const R dD_dA0 = (R)ac.cd0 - (R)ac.cd2 * o.CL * o.CL;
-                const R dD_dK = (R)2 * (R)ac.cd2 * o.CL;
-                const R inv_dt = (R)(1.0 / p.dt);
-                const R dT_dv = -o.mass * ir * inv_dt + dD_dA0 * ((R)2 * A0 * Ops<R>::rcp(v0)) +
-                                dD_dK * o.mass * g0 * (o.tphi * Ops<R>::rcp(o.icphi)) * (cd * (R)(1.0 / kG0)) -
-                                o.mass * g0 * o.sg * Ops<R>::rcp(v0);
-                const R dT_dvc = o.mass * ir * inv_dt;
-                const R dT_dzd = o.mass * g0 * Ops<R>::rcp(v0);
-                const R dT_dcd = dD_dK * o.mass * g0 * (o.tphi * Ops<R>::rcp(o.icphi)) * (v0 * (R)(1.0 / kG0));
-                const R dT_dz = dD_dA0 * (A0 * Ops<R>::rcp(o.rho)) * o.drho_dz;
-                const R dT_dm = (o.vn - v0) * inv_dt + dD_dK * g0 * o.icphi + g0 * o.sg;
-                const R dt_eta = dt * o.eta;
-                df_dv = dt * (R)(ac.cf1 / ac.cf2) * o.T + dt_eta * dT_dv;
-                df_dvc = dt_eta * dT_dvc;
-                df_dzd = dt_eta * dT_dzd;
-                df_dcd = dt_eta * dT_dcd;
-                df_dz = dt_eta * dT_dz;
-                df_dm = dt_eta * dT_dm;
-            }
-            const R icg = Ops<R>::rcp(o.cg);
-            // adjoints of the step's inputs
-            const R nx_ = ax * ((R)1 + dt * o.dwx[0]) + ay * dt * o.dwy[0];
-            const R ny_ = ax * dt * o.dwx[1] + ay * ((R)1 + dt * o.dwy[1]);
-            const R nz_ = az + ax * dt * o.dwx[2] + ay * dt * o.dwy[2] + aB * df_dz;
-            const R nchi = achi + ax * dt * (-v0 * o.sc * o.cg) + ay * dt * (v0 * o.cc * o.cg);
-            const R nv = av * ((R)1 - ir) + ax * dt * o.cc * icg + ay * dt * o.sc * icg + aB * df_dv;
-            const R nB = aB - aB * df_dm;
-            gc[0] += achi * dt + aB * df_dcd;
-            gc[1] += av * ir + aB * df_dvc;
-            gc[2] += ax * dt * o.cc * (-o.sg * icg) + ay * dt * o.sc * (-o.sg * icg) + az * dt +
-                     aB * df_dzd;
-            ax = nx_; ay = ny_; az = nz_; achi = nchi; av = nv; aB = nB;
         }
     }
     flush_segment<R>(gp, s_grad, gc, sp, m, grp, ngrp, l, i, out);
@@ -522,14 +576,14 @@ hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u,
     gp.Mp = grad_lanes_per_group(rp.M);
     gp.chunks = gp.Mp > 64 ? gp.Mp / 64 : 1;
     const int64_t lanes = (int64_t)rp.P * rp.N * gp.Mp;
-    const unsigned blocks = (unsigned)((lanes + 255) / 256);
+    const unsigned blocks = (unsigned)((lanes + GR_BLOCK - 1) / GR_BLOCK);
     double* dst = gp.chunks > 1 ? partial : grad_out;
     if (prec == 0)
-        hipLaunchKernelGGL(k_rollout_grad<double>, dim3(blocks), dim3(256), 0, st, gp,
+        hipLaunchKernelGGL(k_rollout_grad<double>, dim3(blocks), dim3(GR_BLOCK), 0, st, gp,
                            (const double*)u, (const double*)Wt, states, k_active, acpar, targets,
                            kind, dst);
     else
-        hipLaunchKernelGGL(k_rollout_grad<float>, dim3(blocks), dim3(256), 0, st, gp,
+        hipLaunchKernelGGL(k_rollout_grad<float>, dim3(blocks), dim3(GR_BLOCK), 0, st, gp,
                            (const float*)u, (const float*)Wt, states, k_active, acpar, targets,
                            kind, dst);
     hipError_t e = hipGetLastError();
