@@ -211,8 +211,8 @@ smc_status smc_k_mala_accept(smc_ctx* ctx, int32_t P, void* u, const void* u_pro
                              int32_t* accepted, void* stream);
 
 /* Rollout kernel layout used by every pass of this context:
- *  0 automatic (world-per-lane for N <= 20; above, particle-per-wave in
- *    FP32 and aircraft-per-lane in FP64),
+ *  0 automatic (world-per-lane for N <= 20; above, particle tile in FP32
+ *    and aircraft-per-lane in FP64),
  *  1 aircraft-per-lane: one lane per (particle, sample, aircraft), the world's
  *    aircraft in consecutive lanes of a wavefront, positions exchanged in LDS;
  *  2 world-per-lane: one lane per (particle, sample) holding all N aircraft
@@ -224,6 +224,10 @@ smc_status smc_k_mala_accept(smc_ctx* ctx, int32_t P, void* u, const void* u_pro
  *    get the horizontal test (exact: the altitudes do not depend on the
  *    wind).  Uses the context's workspace for a sample-interleaved copy of
  *    the fields, so calls on one context must run in stream order.
+ *  4 particle tile (FP32, N <= 64; the automatic choice above 20 aircraft
+ *    in FP32): a wavefront holds 4 particles x 16 wind samples, a
+ *    workgroup one block of 16 samples, so that the wind lookups of the
+ *    workgroups on one XCD stay in one block of the fields; otherwise as 3.
  * All compute the same rollout; SMC_EINVAL for an unsupported choice. */
 smc_status smc_set_rollout_layout(smc_ctx* ctx, int32_t layout);
 

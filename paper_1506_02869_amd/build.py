@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libsmc_mpc.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels_rng.hip", "kernels_wind.hip", "kernels_rollout.hip", "kernels_rollout_pw.hip",
+SOURCES = ["kernels_rng.hip", "kernels_wind.hip", "kernels_rollout.hip", "kernels_rollout_pw.hip", "kernels_rollout_pt.hip",
            "kernels_rollout_wm.hip", "kernels_rollout_wm_tv.hip", "kernels_rollout_batch.hip",
            "kernels_grad.hip",
            "kernels_smc.hip", "kernels_batch.hip", "kernels_plant.hip", "smc_mpc.cpp",

@@ -165,6 +165,11 @@ bool rollout_wm_supported(int N);
 bool rollout_pw_supported(int N, int prec);
 hipError_t launch_rollout_pw(const RolloutParams& p, const RolloutArrays& a, const void* acR,
                              const void* Wt, hipStream_t st);
+// Particle-tile rollout (FP32, N <= 64): a wave holds 4 particles x 16 wind
+// samples; the same fields layout as the particle-per-wave rollout.
+bool rollout_pt_supported(int N, int prec);
+hipError_t launch_rollout_pt(const RolloutParams& p, const RolloutArrays& a, const void* acR,
+                             const void* Wt, hipStream_t st);
 // W[M][G][2] -> Wt[G][M][2] (pairs of reals), coalesced through LDS tiles.
 hipError_t launch_wind_transpose(int prec, const void* W, int M, int G, void* Wt, hipStream_t st);
 // acR: [N][kAcR] real: wing area, C_D0, C_D2, dt C_f1, dt C_f1 / C_f2,

@@ -31,81 +31,9 @@
 // (1 - alpha_time - alpha_noise) w_fuel fuel_k / (dt T_max eta(v_max)), so
 // the element sum over the steps divided by their number is the fuel
 // element plus the mean of the other elements.
-#include "rollout_math.h"
+#include "rollout_pw_common.h"
 
 namespace smc {
-
-namespace {
-
-// one float per aircraft of the world, in two register vectors of at most
-// 32 (aircraft 0..31 and 32..NMAX-1), each indexed at a uniform index
-typedef float v32f __attribute__((ext_vector_type(32)));
-template <int NB> struct PwHalf { typedef float t __attribute__((ext_vector_type(NB))); };
-template <int NMAX>
-constexpr int pw_nb() { return NMAX <= 32 ? 8 : NMAX - 32; }
-
-constexpr int kPwWaves = 4;     // wavefronts per workgroup (independent)
-constexpr int kXcds = 8;        // accelerator complex dies; workgroups are dealt to them in turn
-constexpr int kPwRec = 12;      // floats of an aircraft-step record
-constexpr int kPwPar = 24;      // floats of an aircraft parameter row
-
-// record fields (phase 1 -> phase 2)
-enum : int {
-    R_VX = 0, R_VY, R_ZN, R_CHIN, R_GZ, R_TZ, R_UDEP, R_IVT, R_NA, R_FUEL, R_FLAGS
-};
-// parameter row fields (LDS, whole workgroup)
-enum : int {
-    A_SW = 0, A_CD0, A_CD2, A_CF, A_CFV, A_TMAX, A_MEMP, A_TPHI, A_SGAM, A_THF, A_ZT, A_VD,
-    A_DTMA, A_CSPD, A_CFUEL, A_M0, A_D0, A_Z0, A_V0, A_CHI0, A_K0
-};
-constexpr uint32_t F_VIOL = 1u, F_LANDOK = 2u, F_DEP = 4u;
-
-// waves per SIMD the register budget is set for: the world state takes
-// 2 NMAX VGPRs (x and y of every aircraft), the cost sums NMAX x 64 floats
-// of LDS per wave
-template <int NMAX>
-constexpr int pw_waves() { return NMAX <= 48 ? 2 : 1; }
-
-}  // namespace
-
-typedef float F2 __attribute__((ext_vector_type(2)));
-
-// The wind lookup of one aircraft in every world of the wave, issued one
-// aircraft ahead of its use so that the loads overlap the previous
-// aircraft's arithmetic: the position, the cell fractions and the eight
-// corners (x, y components) of this lane's sample.
-struct PwTap {
-    float xi, yi, tx, ty, tz;
-    F2 c[8];
-};
-
-// Issue the lookup of aircraft i (its position before this step's update;
-// the altitude cell and fraction come from its phase-1 record); x, y: the
-// half holding aircraft i, at index ii.
-template <typename V>
-__device__ __forceinline__ PwTap pw_issue(const RollConst<float>& q, const float* __restrict__ rec,
-                                          const __amdgpu_buffer_rsrc_t wrs, int s_z, int s_y,
-                                          int s_x, int vbase, int M, int i, int ii, const V& x,
-                                          const V& y) {
-    PwTap t;
-    t.xi = x[ii];
-    t.yi = y[ii];
-    const float2 zc = *reinterpret_cast<const float2*>(rec + i * kPwRec + 4);   // cell, fraction
-    const float fx = clampr(m_fma(t.xi, q.inv_hx, q.ox), 0.f, q.fnx1);
-    const float fy = clampr(m_fma(t.yi, q.inv_hy, q.oy), 0.f, q.fny1);
-    const float flx = m_floor(clampr(fx, 0.f, q.fnx2));
-    const float fly = m_floor(clampr(fy, 0.f, q.fny2));
-    t.tx = fx - flx;
-    t.ty = fy - fly;
-    t.tz = zc.y;
-    const int g = (int)m_fma(m_fma(flx, q.fny, fly), q.fnz, zc.x);
-    const int vo = g * (M * 8) + vbase;
-    const int off[8] = {0, s_z, s_y, s_y + s_z, s_x, s_x + s_z, s_x + s_y, s_x + s_y + s_z};
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-        t.c[c] = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(wrs, vo, off[c], 0));
-    return t;
-}
 
 // One aircraft of phase 2 in every world of the wave (aircraft i, index ii
 // = i - 32 HI into the upper halves).  x, y: this half's vectors; xlo,
@@ -119,7 +47,8 @@ __device__ __forceinline__ void pw_aircraft(
     const RolloutParams& p, const RolloutArrays& a, const float* __restrict__ par,
     const float* __restrict__ rec, const PwTap& w, int i, uint64_t actk, float zn_lane, VX& x,
     VX& y, float* __restrict__ accl, const v32f& xlo, const v32f& ylo, uint32_t done0,
-    uint32_t& done, uint32_t& bad, uint32_t& sepbad, uint32_t& sepbad_lo, int& nhor) {
+    uint32_t& done, uint32_t& bad, uint32_t& sepbad, uint32_t& sepbad_lo, int& nhor,
+    PwNoise& noise) {
     typedef Ops<float> O;
     const RollConst<float>& q = p.cf;
     const int ii = HI ? i - 32 : i;
@@ -170,19 +99,20 @@ __device__ __forceinline__ void pw_aircraft(
         const float tt = m_min(m_max(pi_[A_DTMA] - r, 0.f) * rb.w, 1.f);
         cst = q.c_brg * brg + rb.z + q.a_time * tt;
     }
+    noise.i = -1;
     if (p.use_noise && na != 0.f) {   // uniform: below the noise altitude
         const float fpx = clampr(m_fma(xn, q.pop_inv_hx, q.pop_ox), 0.f, q.fpnx1);
         const float fpy = clampr(m_fma(yn, q.pop_inv_hy, q.pop_oy), 0.f, q.fpny1);
         const int px = min((int)fpx, p.pop_nx - 2), py = min((int)fpy, p.pop_ny - 2);
-        const float ux = fpx - (float)px, uy = fpy - (float)py;
+        noise.ux = fpx - (float)px;
+        noise.uy = fpy - (float)py;
         const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
             (void*)a.pop, (short)0, p.pop_nx * p.pop_ny * 4, 0x00020000);
         const int po = (py * p.pop_nx + px) * 4;
-        const F2 p0 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(prs, po, 0, 0));
-        const F2 p1 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(prs, po, p.pop_nx * 4, 0));
-        const float pd = (1.f - ux) * (1.f - uy) * p0.x + ux * (1.f - uy) * p0.y +
-                         (1.f - ux) * uy * p1.x + ux * uy * p1.y;
-        cst += landed ? 0.f : na * pd;
+        noise.p0 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(prs, po, 0, 0));
+        noise.p1 = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(prs, po, p.pop_nx * 4, 0));
+        noise.w = (landed | wasdone) ? 0.f : na;
+        noise.i = i;
     }
     accl[i * 64] += wasdone ? 0.f : cst + rc.y;
     done |= landed ? bit : 0u;
@@ -237,20 +167,33 @@ __device__ __forceinline__ void pw_half(
     if (!todo) return;
     const int base = HI ? 32 : 0;
     int ii = __builtin_ctz(todo);
-    PwTap cur = pw_issue(p.cf, rec, wrs, s_z, s_y, s_x, vbase, M, base + ii, ii, x, y);
-    while (true) {                                                 // uniform
-        todo &= todo - 1u;
-        // the next aircraft's lookup (after the last one, a repeat of this
-        // one's, unused): issued unconditionally so that it stays ahead of
-        // this aircraft's arithmetic
-        const int inext = todo ? __builtin_ctz(todo) : ii;
-        const PwTap nxt = pw_issue(p.cf, rec, wrs, s_z, s_y, s_x, vbase, M, base + inext, inext, x, y);
-        pw_aircraft<HI>(p, a, par, rec, cur, base + ii, actk, zn_lane, x, y, accl, xlo, ylo, done0,
-                        done, bad, sepbad, sepbad_lo, nhor);
-        if (!todo) break;
-        ii = inext;
-        cur = nxt;
+    // two lookups alternate (the loop body twice), so that no lookup in
+    // flight is copied from register to register
+    PwTap ta = pw_issue(p.cf, rec, wrs, s_z, s_y, s_x, vbase, M, base + ii, ii, x, y), tb;
+    PwNoise pend;
+    pend.i = -1;
+    // one aircraft: first the previous aircraft's population lookup (issued
+    // after this aircraft's wind lookup, so waiting for it waits for nothing
+    // still needed later), then the next aircraft's wind lookup (after the
+    // last aircraft a repeat of this one's, unused), issued unconditionally
+    // so that it stays ahead of this aircraft's arithmetic
+#define PW_ONE(CUR, NXT)                                                                    \
+    {                                                                                       \
+        todo &= todo - 1u;                                                                  \
+        pw_noise_add(pend, accl);                                                           \
+        const int inext = todo ? __builtin_ctz(todo) : ii;                                  \
+        NXT = pw_issue(p.cf, rec, wrs, s_z, s_y, s_x, vbase, M, base + inext, inext, x, y); \
+        pw_aircraft<HI>(p, a, par, rec, CUR, base + ii, actk, zn_lane, x, y, accl, xlo, ylo,  \
+                        done0, done, bad, sepbad, sepbad_lo, nhor, pend);                   \
+        if (!todo) break;                                                                   \
+        ii = inext;                                                                         \
     }
+    while (true) {                                                 // uniform
+        PW_ONE(ta, tb)
+        PW_ONE(tb, ta)
+    }
+#undef PW_ONE
+    pw_noise_add(pend, accl);
 }
 
 template <int NMAX>
@@ -258,7 +201,6 @@ __global__ void __launch_bounds__(64 * kPwWaves, pw_waves<NMAX>())
 k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restrict__ acR,
              const float* __restrict__ Wt) {
     typedef typename PwHalf<pw_nb<NMAX>()>::t vBf;
-    typedef Ops<float> O;
     __shared__ __attribute__((aligned(16))) float par[NMAX * kPwPar];
     __shared__ __attribute__((aligned(16))) float recs[kPwWaves * NMAX * kPwRec];
     // per-world cost sums [wave][aircraft][lane] (LDS, so that the sum of
@@ -269,16 +211,20 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
     const int nmb = (M + 63) >> 6;                      // 64-sample blocks per particle
     // workgroup -> (sample block, particles): workgroups go to the eight
     // XCDs in turn, so when the blocks divide 8, every XCD keeps to one block
-    // of samples (its L2 holds that block's fields) and the workgroup's
-    // waves take consecutive particles; otherwise waves run in (particle,
-    // block) order
+    // of samples and to one contiguous range of particles, which it works
+    // through in order: the workgroups resident on an XCD at a time hold
+    // neighbouring particles, which after resampling (ancestors in
+    // non-decreasing order) fly similar tracks through the same cells of the
+    // fields, so their wind lookups share the XCD's L2; otherwise waves run
+    // in (particle, block) order
     int mb;
     int64_t l64;
     if ((kXcds % nmb) == 0) {
         const int xcd = (int)(blockIdx.x % kXcds);
         const int64_t slot = blockIdx.x / kXcds;
+        const int64_t per_xcd = gridDim.x / kXcds;               // workgroups per XCD
         mb = xcd % nmb;
-        l64 = ((slot * (kXcds / nmb) + xcd / nmb) * kPwWaves) + wv;
+        l64 = (((int64_t)(xcd / nmb) * per_xcd + slot) * kPwWaves) + wv;
     } else {
         const int64_t wave = (int64_t)blockIdx.x * kPwWaves + wv;
         mb = (int)(wave % nmb);
@@ -291,37 +237,18 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
     const bool valid = wvalid && m < M;
     const RollConst<float>& q = p.cf;
 
-    // per-aircraft parameters for the workgroup (host constants from acR,
-    // the initial state and the fuel element's per-step coefficient)
-    if (tid < N) {
-        const int i = tid;
-        const float* c = acR + kAcR * i;
-        float* r = par + i * kPwPar;
-#pragma unroll
-        for (int f = 0; f < 14; ++f) r[f] = c[f];
-        const double* ac = a.acpar + 9 * i;
-        const double wf = a.kind[i] == 0 ? p.w[2] : p.w[4];
-        r[A_CFUEL] = (float)((1.0 - p.w[7] - p.w[8]) * wf /
-                             (p.dt * ac[5] * (ac[3] * (1.0 + p.vmax / ac[4]))));
-        const double* st = a.states + 6 * i;
-        r[A_M0] = (float)st[5];
-        r[A_D0] = fabsf(c[10] - (float)st[2]);
-        r[A_Z0] = (float)st[2];
-        r[A_V0] = (float)st[3];
-        r[A_CHI0] = (float)st[4];
-        r[A_K0] = __int_as_float(a.k_active[i]);
-    }
+    // per-aircraft parameters for the workgroup
+    pw_fill_par(p, a, acR, par, tid);
     __syncthreads();
 
     // phase-1 lane state: aircraft j = lane (j < N), wind-independent
     const int j = lane < N ? lane : N - 1;
     const float* pj = par + j * kPwPar;
-    float zj = pj[A_Z0], vj = pj[A_V0], chij = pj[A_CHI0], burnj = 0.f;
+    PwAc sj = {pj[A_Z0], pj[A_V0], pj[A_CHI0], 0.f, 0.f, 0.f, 0.f};
     const int k0j = __float_as_int(pj[A_K0]);
     const bool actj = lane < N && k0j >= 0 && k0j < H;
     const bool arrj = a.kind[j] == 0;
     const float* ubj = (const float*)a.u + ((int64_t)l * N + j) * S * 3;
-    float chidot = 0.f, vc = 0.f, zdot = 0.f;
     float* recw = recs + wv * NMAX * kPwRec;
 
     // phase-2 state: one world per lane, all aircraft; aircraft i < 32 in
@@ -361,76 +288,17 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
         if (k == k_end) {   // uniform: the next control segment
             const int s = ++s_cur;
             k_end = ((s + 1) * H + S - 1) / S;
-            chidot = q.lo[0] + ubj[s * 3 + 0] * q.span[0];
-            vc = q.lo[1] + ubj[s * 3 + 1] * q.span[1];
-            zdot = q.lo[2] + ubj[s * 3 + 2] * q.span[2];
+            sj.chidot = q.lo[0] + ubj[s * 3 + 0] * q.span[0];
+            sj.vc = q.lo[1] + ubj[s * 3 + 1] * q.span[1];
+            sj.zdot = q.lo[2] + ubj[s * 3 + 2] * q.span[2];
         }
         // ---- phase 1: aircraft j's wind-independent step (lane j) ----
         const bool act = actj && k >= k0j;
         const uint64_t actk = __ballot(act);
-        float zn_lane;
-        {
-            const float inv_rem = O::rcp((float)(k_end - k));
-            const float sg = zdot * O::rcp(vj);
-            const float cg = O::sqrt(1.f - sg * sg);
-            const float tphi = vj * chidot * q.inv_g;
-            const float inv_cphi = O::sqrt(1.f + tphi * tphi);
-            const float zc = clampr(zj, 0.f, 11000.f);
-            const float rho = q.rho0 * O::pow_pos(1.f - q.isa_c * zc, q.isa_e);
-            const float qS = 0.5f * rho * vj * vj * pj[A_SW];
-            const float mass = pj[A_M0] - burnj;
-            const float CL = O::div(mass * q.g0 * inv_cphi, qS);
-            const float D = qS * (pj[A_CD0] + pj[A_CD2] * CL * CL);
-            const float dv = (vc - vj) * inv_rem;
-            const float vn = vj + dv;
-            const float T = mass * (dv * q.inv_dt + q.g0 * sg) + D;
-            const float fuel = m_fma(vj, pj[A_CFV], pj[A_CF]) * m_max(T, 0.f);
-            float sc, cc;
-            O::sincos(chij, &sc, &cc);
-            const float vcg = vj * cg;
-            const float zn = m_fma(q.dt, zdot, zj);
-            const float chin = m_fma(q.dt, chidot, chij);
-            const float mn = mass - fuel;
-            const bool viol = (T > pj[A_TMAX]) | (m_abs(tphi) >= pj[A_TPHI]) |
-                              (m_abs(sg) > pj[A_SGAM]) | (zn < q.zmin) | (zn > q.zmax) |
-                              (vn < q.vmin) | (vn > q.vmax) | (mn < pj[A_MEMP]);
-            // wind cell along z at the current altitude (shared by the worlds)
-            const float fz = clampr(zj * q.inv_hz, 0.f, q.fnz1);
-            const float flz = m_floor(clampr(fz, 0.f, q.fnz2));
-            const float ivt = q.inv_tnorm * O::rcp(maxr(vn, q.vmin));
-            float udep = 0.f;
-            bool landok = false;
-            if (arrj) {
-                landok = (m_abs(wrap_angle<float>(chin - Consts<float>::pi)) <= q.p_chi) &
-                         (vn <= q.p_vs);
-            } else {
-                const float span = q.zdm_dt * (float)max(k + 1 - k0j, 1);
-                const float sup = pj[A_D0] + span;
-                const float inf = m_max(pj[A_D0] - span, 0.f);
-                const float alt = clampr(O::div(m_abs(pj[A_ZT] - zn) - inf, sup - inf), 0.f, 1.f);
-                udep = q.c_alt * alt + pj[A_CSPD] * m_abs(vn - pj[A_VD]);
-            }
-            float na = 0.f;
-            if (p.use_noise) {
-                const float za = zn * q.inv_Ac;
-                na = q.a_noise * m_max(1.f - za * za, 0.f);
-            }
-            const uint32_t fl = (viol ? F_VIOL : 0u) | (landok ? F_LANDOK : 0u) |
-                                (arrj ? 0u : F_DEP);
-            wave_sync();   // the previous step's records were read
-            if (lane < N) {
-                float4* r4 = reinterpret_cast<float4*>(recw + lane * kPwRec);
-                r4[0] = make_float4(vcg * cc, vcg * sc, zn, chin);
-                r4[1] = make_float4(flz, fz - flz, udep, ivt);
-                r4[2] = make_float4(na, pj[A_CFUEL] * fuel, __uint_as_float(fl), 0.f);
-            }
-            zn_lane = zn;
-            // the heading is kept in [-pi, pi) (it enters only through sin,
-            // cos and wrapped differences), so its rounding stays that of an
-            // angle near pi however far the aircraft turns
-            if (act) { zj = zn; vj = vn; chij = wrap_angle<float>(chin); burnj = burnj + fuel; }
-            wave_sync();   // records visible to every lane
-        }
+        wave_sync();   // the previous step's records were read
+        const float zn_lane = pw_phase1(p, pj, k, k0j, k_end, arrj, act, sj,
+                                        recw + lane * kPwRec, lane < N);
+        wave_sync();   // records visible to every lane
 
         // ---- phase 2: every world runs the active aircraft in turn, the
         // wind lookup of the next one issued before this one's arithmetic ----

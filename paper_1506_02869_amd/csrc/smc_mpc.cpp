@@ -307,7 +307,7 @@ int rollout_layout(const smc_ctx* c) {
     if (c->rp.control_model == SMC_CONTROLS_PAPER) return 2;
     if (c->layout != 0) return c->layout;
     if (rollout_wm_supported(c->N)) return 2;
-    return rollout_pw_supported(c->N, c->prec) ? 3 : 1;
+    return rollout_pt_supported(c->N, c->prec) ? 4 : 1;
 }
 
 hipError_t do_rollout(smc_ctx* c, const RolloutParams& rp, const RolloutArrays& a,
@@ -315,10 +315,12 @@ hipError_t do_rollout(smc_ctx* c, const RolloutParams& rp, const RolloutArrays& 
     if (rp.w_kstride != 0) return launch_rollout_wm_tv(c->prec, rp, a, c->d_acR, st);
     switch (rollout_layout(c)) {
     case 2: return launch_rollout_wm(c->prec, rp, a, c->d_acR, st);
-    case 3: {
+    case 3:
+    case 4: {
         const hipError_t e = launch_wind_transpose(c->prec, a.W, rp.M, rp.G, c->d_Wt, st);
         if (e != hipSuccess) return e;
-        return launch_rollout_pw(rp, a, c->d_acR, c->d_Wt, st);
+        return rollout_layout(c) == 3 ? launch_rollout_pw(rp, a, c->d_acR, c->d_Wt, st)
+                                      : launch_rollout_pt(rp, a, c->d_acR, c->d_Wt, st);
     }
     default: return launch_rollout(c->prec, rp, a, st);
     }
@@ -535,8 +537,10 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     info->ess_min = *std::min_element(ess.begin(), ess.end());
     info->aircraft_steps = (int64_t)tot;
     info->pair_tests = (int64_t)totp;
-    // every layout but the particle-per-wave one tests all pairs horizontally
-    info->pair_tests_h = rollout_layout(c) == 3 && c->wind_model == SMC_WIND_SE ? (int64_t)toth
+    // the layouts whose lanes are the samples of particles test only pairs
+    // within the vertical separation horizontally, the others all pairs
+    const int lay = rollout_layout(c);
+    info->pair_tests_h = (lay == 3 || lay == 4) && c->wind_model == SMC_WIND_SE ? (int64_t)toth
                                                                                  : (int64_t)totp;
     info->ms_total = ms;
     double ms_r = 0.0, ms_w = 0.0, ms_g = 0.0;
@@ -1285,14 +1289,15 @@ smc_status smc_k_mala_accept(smc_ctx* c, int32_t P, void* u, const void* u_prop,
 }
 
 smc_status smc_set_rollout_layout(smc_ctx* c, int32_t layout) {
-    if (!c || layout < 0 || layout > 3) return fail(c, SMC_EINVAL, "smc_set_rollout_layout: bad arguments");
+    if (!c || layout < 0 || layout > 4) return fail(c, SMC_EINVAL, "smc_set_rollout_layout: bad arguments");
     if (layout == 2 && !rollout_wm_supported(c->N))
         return fail(c, SMC_EINVAL, "world-per-lane rollout supports at most %d aircraft", kWorldLaneMaxN);
     if (c->rp.control_model == SMC_CONTROLS_PAPER && layout != 0 && layout != 2)
         return fail(c, SMC_EINVAL, "the paper's controls run the world-per-lane rollout only");
-    if (layout == 3 && !rollout_pw_supported(c->N, c->prec))
-        return fail(c, SMC_EINVAL, "particle-per-wave rollout: FP32 contexts only");
-    if ((layout == 1 || layout == 3) && c->wind_model != SMC_WIND_SE)
+    if ((layout == 3 && !rollout_pw_supported(c->N, c->prec)) ||
+        (layout == 4 && !rollout_pt_supported(c->N, c->prec)))
+        return fail(c, SMC_EINVAL, "particle-per-wave and particle-tile rollouts: FP32 contexts only");
+    if ((layout == 1 || layout == 3 || layout == 4) && c->wind_model != SMC_WIND_SE)
         return fail(c, SMC_EINVAL, "time-correlated wind runs the world-per-lane rollout only");
     c->layout = layout;
     return SMC_OK;

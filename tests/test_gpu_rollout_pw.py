@@ -1,7 +1,9 @@
-"""GPU parity of the particle-per-wave rollout (layout 3, FP32): the lanes
-of a wave are wind samples of one particle, the wind-independent part of
-every aircraft's step is computed once per particle, and only pairs inside
-the vertical separation get the horizontal test.  Element-wise against the
+"""GPU parity of the rollouts whose lanes are wind samples of particles
+(FP32): particle-per-wave (layout 3, 64 samples of one particle per wave)
+and the particle tile (layout 4, 4 particles x 16 samples per wave).  The
+wind-independent part of every aircraft's step is computed once per
+particle, and only pairs inside the vertical separation get the horizontal
+test.  Element-wise against the
 FP64 oracle (2e-5 relative per world, feasibility exact away from
 thresholds), with the simulated aircraft-steps and pair-test counts exact."""
 import numpy as np
@@ -12,12 +14,13 @@ from tests.test_gpu_kernels import _compare_rollout, _rollout_case
 
 pytestmark = pytest.mark.gpu
 
-PW = 3
+LAYOUTS = [3, 4]
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("N,M", [(1, 3), (2, 70), (7, 3), (16, 64), (21, 3), (24, 70), (32, 3),
                                  (33, 5), (40, 70), (41, 3), (48, 128), (49, 3), (63, 5), (64, 66)])
-def test_rollout_pw_aircraft_counts(lib, N, M):
+def test_rollout_pw_aircraft_counts(lib, N, M, layout):
     """One to 64 aircraft (both vector halves, every register bucket), one or
     two blocks of 64 samples with a ragged tail, mixed kinds and activation
     steps, inactive aircraft."""
@@ -29,7 +32,7 @@ def test_rollout_pw_aircraft_counts(lib, N, M):
     k_act = s["k_active"].copy()
     k_act[rng.uniform(size=N) < 0.2] = -1
     ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=11, seed=N, horizon=27, k_active=k_act,
-                                            layout=PW)
+                                            layout=layout)
     n_near = _compare_rollout(gc, gf, ref, 1)
     assert steps == ref["steps"]
     # a wind-independent margin (thrust, bank, climb, speed, altitude, mass)
@@ -38,8 +41,9 @@ def test_rollout_pw_aircraft_counts(lib, N, M):
     assert n_near <= 0.02 * 11 * M + 2 * M
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("N", [12, 33, 40, 41, 64])
-def test_rollout_pw_close_traffic_separation(lib, N):
+def test_rollout_pw_close_traffic_separation(lib, N, layout):
     """Aircraft packed inside one separation cell at altitudes within a few
     hundred metres: many pairs pass the vertical test and many horizontal
     tests fire, in both vector halves."""
@@ -54,14 +58,15 @@ def test_rollout_pw_close_traffic_separation(lib, N):
     st[:, 4] = rng.uniform(-3, 3, N)
     st[:, 5] = 60e3
     ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=9, states=st, k_active=np.zeros(N, np.int32),
-                                            layout=PW)
+                                            layout=layout)
     n_near = _compare_rollout(gc, gf, ref, 1)
     assert steps == ref["steps"]
     assert n_near <= 0.02 * 9 * 66 + 2 * 66
     assert (~ref["feas"]).mean() > 0.2
 
 
-def test_rollout_pw_landed_aircraft_leave_the_airspace(lib):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_rollout_pw_landed_aircraft_leave_the_airspace(lib, layout):
     """Arrivals queued on the final approach land one after the other at one
     altitude: a landed aircraft is parked and never conflicts again."""
     n, H = 4, 40
@@ -77,22 +82,24 @@ def test_rollout_pw_landed_aircraft_leave_the_airspace(lib):
     st[:, 4] = np.pi
     st[:, 5] = 60e3
     ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=64, states=st,
-                                            k_active=np.zeros(n, np.int32), layout=PW)
+                                            k_active=np.zeros(n, np.int32), layout=layout)
     _compare_rollout(gc, gf, ref, 1)
     assert steps == ref["steps"] < 64 * 2 * n * H
     assert ref["feas"].all() and gf.all()
 
 
-def test_rollout_pw_noise_term(lib):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_rollout_pw_noise_term(lib, layout):
     s = synth.shrink(synth.c5(), M=3, H=30, S=3, grid=(8, 8, 4))
-    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=6, layout=PW)
+    ctx, gc, gf, steps, ref = _rollout_case(lib, s, P=6, layout=layout)
     n_near = _compare_rollout(gc, gf, ref, 1)
     assert steps == ref["steps"]
     assert n_near <= 0.02 * 6 * 3 * 40 + 2 * 3
 
 
-def test_rollout_pw_refused_in_fp64(lib):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_rollout_pw_refused_in_fp64(lib, layout):
     s = synth.shrink(synth.c5(precision="fp64"), M=2, H=20, S=2, grid=(4, 4, 3), L=4)
     ctx = lib.smc_mpc_init(s)
     with pytest.raises(lib.SmcError):
-        lib.smc_set_rollout_layout(ctx, PW)
+        lib.smc_set_rollout_layout(ctx, layout)
