@@ -76,7 +76,7 @@ WORKLOADS = {
     "c5": ("large form: 40 aircraft (24 arrivals, 16 departures, 780 pairs), 150x150x10 km, "
            "H=180 dt=5 s, S=12, fuel + time + noise (256x256 lognormal population below "
            "2 km), wind 64x64x8 (G=32768) M=128, L=65536, K=60, FP32 rollout "
-           "(aircraft-per-lane) with FP64 weights and scan, jitter moves", "c5"),
+           "(particle tile) with FP64 weights and scan, jitter moves", "c5"),
 }
 
 
@@ -535,9 +535,9 @@ def main():
     N = scen["N"]
     fp64 = scen["precision"] == 0
     # the rollout layout the library picks (world-per-lane up to 20 aircraft,
-    # particle-per-wave above in FP32, aircraft-per-lane otherwise)
-    layout = 2 if N <= 20 else (3 if not fp64 else 1)
-    if layout == 3:
+    # the particle tile above in FP32, aircraft-per-lane otherwise)
+    layout = 2 if N <= 20 else (4 if not fp64 else 1)
+    if layout in (3, 4):
         # the wind-independent part of a step once per particle, the
         # wind-dependent part per world; vertical pair tests once per
         # particle, horizontal ones per world for pairs within sep_v
@@ -553,7 +553,8 @@ def main():
     world_lane = layout == 2
     kname, ksrc = {
         2: ("k_rollout_wm", ("kernels_rollout_wm.hip", "rollout_wm_body.inc", "rollout_math.h")),
-        3: ("k_rollout_pw", ("kernels_rollout_pw.hip", "rollout_math.h")),
+        3: ("k_rollout_pw", ("kernels_rollout_pw.hip", "rollout_pw_common.h", "rollout_math.h")),
+        4: ("k_rollout_pt", ("kernels_rollout_pt.hip", "rollout_pw_common.h", "rollout_math.h")),
         1: ("k_rollout", ("kernels_rollout.hip", "rollout_math.h"))}[layout]
     if ar1:
         kname = "k_rollout_wm_tv"

@@ -159,19 +159,31 @@ hipError_t launch_wind_gemm(int prec, const void* Lfac, const void* Z,
 hipError_t launch_rollout(int prec, const RolloutParams& p,
                           const RolloutArrays& a, hipStream_t st);
 bool rollout_wm_supported(int N);
+// Sample-blocked fields for the rollouts whose lanes are wind samples: the
+// samples split into blocks of B, block b holds Wt[b][g][B][2] (pairs of
+// reals), so the samples of one grid point inside a block are contiguous
+// and one block's fields are one contiguous range (the last block is
+// padded to B samples).  B = M gives the plain sample-interleaved
+// [G][M][2] layout.
+constexpr int kWtBlockPw = 64;   // particle-per-wave rollout
+constexpr int kWtBlockPt = 16;   // particle tile
+__host__ __device__ inline int64_t wt_elems(int M, int G, int B) {
+    return (int64_t)((M + B - 1) / B) * B * G;
+}
 // Particle-per-wave rollout (FP32, N <= 64): the 64 lanes of a wave are 64
-// wind samples of one particle; Wt holds the fields sample-interleaved,
-// [G][M][2] (launch_wind_transpose).
+// wind samples of one particle; Wt: the fields in blocks of kWtBlockPw.
 bool rollout_pw_supported(int N, int prec);
 hipError_t launch_rollout_pw(const RolloutParams& p, const RolloutArrays& a, const void* acR,
                              const void* Wt, hipStream_t st);
 // Particle-tile rollout (FP32, N <= 64): a wave holds 4 particles x 16 wind
-// samples; the same fields layout as the particle-per-wave rollout.
+// samples; Wt: the fields in blocks of kWtBlockPt.
 bool rollout_pt_supported(int N, int prec);
 hipError_t launch_rollout_pt(const RolloutParams& p, const RolloutArrays& a, const void* acR,
                              const void* Wt, hipStream_t st);
-// W[M][G][2] -> Wt[G][M][2] (pairs of reals), coalesced through LDS tiles.
-hipError_t launch_wind_transpose(int prec, const void* W, int M, int G, void* Wt, hipStream_t st);
+// W[M][G][2] -> the sample-blocked Wt with blocks of B samples (pairs of
+// reals), coalesced through LDS tiles.
+hipError_t launch_wind_transpose(int prec, const void* W, int M, int G, int B, void* Wt,
+                                 hipStream_t st);
 // acR: [N][kAcR] real: wing area, C_D0, C_D2, dt C_f1, dt C_f1 / C_f2,
 // T_max, empty mass, tan(phi_max), sin(gamma_max), theta_F, Z, v_D, D_TMA,
 // (1 - alpha_time - alpha_noise) w_speed / speed span, kind (0 arrival,

@@ -502,11 +502,11 @@ __global__ void __launch_bounds__(GR_BLOCK) __attribute__((amdgpu_waves_per_eu(2
     flush_segment<R>(gp, s_grad, gc, sp, m, grp, ngrp, l, i, out);
 }
 
-// W[m][g] -> Wt[g][m] (pairs of reals), one 32 x 32 tile per workgroup
-// through LDS so that both the reads and the writes are coalesced.
+// W[m][g] -> Wt[m / B][g][m % B] (pairs of reals), one 32 x 32 tile per
+// workgroup through LDS so that both the reads and the writes are coalesced.
 template <typename R>
 __global__ void __launch_bounds__(256) k_wind_transpose(const typename V2<R>::t* __restrict__ W,
-                                                        int M, int G,
+                                                        int M, int G, int B,
                                                         typename V2<R>::t* __restrict__ Wt) {
     typedef typename V2<R>::t R2;
     __shared__ R2 tile[32][33];
@@ -519,7 +519,7 @@ __global__ void __launch_bounds__(256) k_wind_transpose(const typename V2<R>::t*
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int g = g0 + r, m = m0 + tx;
-        if (m < M && g < G) Wt[(int64_t)g * M + m] = tile[tx][r];
+        if (m < M && g < G) Wt[((int64_t)(m / B) * G + g) * B + m % B] = tile[tx][r];
     }
 }
 
@@ -550,14 +550,16 @@ bool grad_supported(int H, int S) {
     return S <= GR_MAXS && (H + GR_CK - 1) / GR_CK <= GR_MAXSEG;
 }
 
-hipError_t launch_wind_transpose(int prec, const void* W, int M, int G, void* Wt, hipStream_t st) {
+hipError_t launch_wind_transpose(int prec, const void* W, int M, int G, int B, void* Wt,
+                                 hipStream_t st) {
     if (M <= 0 || G <= 0) return hipSuccess;
+    if (B <= 0) return hipErrorInvalidValue;
     const dim3 tg((unsigned)((G + 31) / 32), (unsigned)((M + 31) / 32));
     if (prec == 0)
-        hipLaunchKernelGGL(k_wind_transpose<double>, tg, dim3(256), 0, st, (const double2*)W, M, G,
+        hipLaunchKernelGGL(k_wind_transpose<double>, tg, dim3(256), 0, st, (const double2*)W, M, G, B,
                            (double2*)Wt);
     else
-        hipLaunchKernelGGL(k_wind_transpose<float>, tg, dim3(256), 0, st, (const float2*)W, M, G,
+        hipLaunchKernelGGL(k_wind_transpose<float>, tg, dim3(256), 0, st, (const float2*)W, M, G, B,
                            (float2*)Wt);
     return hipGetLastError();
 }
@@ -568,7 +570,8 @@ hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u,
                                double* grad_out, hipStream_t st) {
     if (!grad_supported(rp.H, rp.S)) return hipErrorInvalidValue;
     {
-        const hipError_t e = launch_wind_transpose(prec, W, rp.M, rp.G, Wt, st);
+        // one block of all M samples: the plain [G][M] interleaving
+        const hipError_t e = launch_wind_transpose(prec, W, rp.M, rp.G, rp.M, Wt, st);
         if (e != hipSuccess) return e;
     }
     GradParams gp;

@@ -11,15 +11,18 @@
 // from LDS; only pairs inside the vertical separation get the horizontal
 // test (exact: the altitudes do not depend on the wind).  What the tile
 // changes: a workgroup (8 wavefronts up to 40 aircraft, 32 particles; 4
-// above) reads the fields of 16 samples only, so with the
-// blocks of samples dealt one per XCD the lookups of every workgroup on an
-// XCD fall in one block of the fields (G x 16 x 8 bytes: 4.2 MB on a
-// 64 x 64 x 8 grid), which its L2 holds, where 64 samples per wavefront
-// (17 MB per block) missed the L2 on large grids.
+// above) reads the fields of 16 samples only, so with the blocks of samples
+// dealt one per XCD the lookups of every workgroup on an XCD fall in one
+// block of the fields, which its L2 holds (G x 16 x 8 bytes: 4.2 MB on a
+// 64 x 64 x 8 grid), where 64 samples per wavefront (17 MB per block)
+// missed the L2 on large grids.  The fields are stored block by block, so
+// that a block is one contiguous range: interleaving all M samples per grid
+// point would leave an XCD's lines at a stride of 8 M bytes, which crowds
+// them into a fraction of the L2's sets and channels.
 //
 // Vertical candidates: after the four passes of a step, for every particle
 // and aircraft i, the mask of aircraft j < i active at the step with
-// |z_j - z_i| < sep_v (one ballot per aircraft over the particle's pass),
+// |z_j - z_i| < sep_v (each lane compares its aircraft with every other),
 // kept per particle and as the union over the wavefront's four particles
 // (the uniform loop of the pair tests; each lane tests only its particle's
 // candidates).
@@ -31,6 +34,7 @@ namespace {
 
 constexpr int kPtP = 4;         // particles per wavefront
 constexpr int kPtS = 16;        // wind samples per particle in a wavefront
+static_assert(kPtS == kWtBlockPt, "the fields come in blocks of one wavefront's samples");
 
 // waves per SIMD the register budget is set for (as the particle-per-wave
 // layout: x and y of every aircraft in registers, cost sums in LDS)
@@ -91,7 +95,7 @@ __device__ __forceinline__ void pt_aircraft(
         const float ratio = tha > 1e-4f ? tha * O::rcp(maxr(O::sin(tha), 1e-6f))
                                         : 1.f + tha * tha * (1.f / 6.f);
         const float s_arc = r * ratio;
-        const float beta = O::atan2(zn, s_arc);
+        const float beta = O::atan2_xpos(zn, s_arc);                 // s_arc >= 0
         landed = !wasdone & (r <= q.p_run) & (beta <= q.p_beta) & (tha <= q.p_chi) &
                  ((flags & F_LANDOK) != 0u);
         const float hdg = m_abs(wrap_angle<float>(chin - (Consts<float>::pi + 2.f * theta)));
@@ -130,30 +134,35 @@ __device__ __forceinline__ void pt_aircraft(
     y[ii] = ys;
 
     // separation against the aircraft already moved this step that are
-    // vertical candidates of the lane's particle
+    // vertical candidates of the lane's particle: every lane tests the
+    // wave's union of candidates and keeps a mask of the horizontal
+    // conflicts, restricted to its own particle's candidates at the end.
+    // d2 < sep_h2 is read off the sign of the rounded difference, which
+    // is negative exactly then (a difference of finite floats rounds to
+    // zero only when they are equal, and keeps its sign otherwise).
     nhor += __popcll(mine);
-    uint32_t c_lo = (uint32_t)cand;
-    while (c_lo) {
+    uint32_t c_lo = (uint32_t)cand, h_lo = 0u;
+    while (c_lo) {                                                  // uniform
         const int jj = __builtin_ctz(c_lo);
         c_lo &= c_lo - 1u;
         const float dx = xs - xlo[jj], dy = ys - ylo[jj];
-        const bool hit = ((mine >> jj) & 1ull) && dx * dx + dy * dy < q.sep_h2;
-        if (__builtin_expect(__ballot(hit) != 0ull, 0)) {
-            if (hit) { sepbad |= bit; sepbad_lo |= 1u << jj; }
-        }
+        h_lo |= (__float_as_uint(dx * dx + dy * dy - q.sep_h2) >> 31) << jj;
     }
+    h_lo &= (uint32_t)mine;
     if (HI) {
-        uint32_t c_hi = (uint32_t)(cand >> 32);
-        while (c_hi) {
+        uint32_t c_hi = (uint32_t)(cand >> 32), h_hi = 0u;
+        while (c_hi) {                                              // uniform
             const int jj = __builtin_ctz(c_hi);
             c_hi &= c_hi - 1u;
             const float dx = xs - x[jj], dy = ys - y[jj];
-            const bool hit = ((mine >> (jj + 32)) & 1ull) && dx * dx + dy * dy < q.sep_h2;
-            if (__builtin_expect(__ballot(hit) != 0ull, 0)) {
-                if (hit) sepbad |= bit | (1u << jj);
-            }
+            h_hi |= (__float_as_uint(dx * dx + dy * dy - q.sep_h2) >> 31) << jj;
         }
+        h_hi &= (uint32_t)(mine >> 32);
+        sepbad |= (h_lo | h_hi) != 0u ? bit | h_hi : 0u;
+    } else {
+        sepbad |= h_lo != 0u ? bit : 0u;
     }
+    sepbad_lo |= h_lo;
 }
 
 // Phase 2 over the active aircraft of one half (bits of `todo`, aircraft
@@ -165,13 +174,13 @@ __device__ __forceinline__ void pt_half(
     const RolloutParams& p, const RolloutArrays& a, const float* __restrict__ par,
     const float* __restrict__ rec, const uint64_t* __restrict__ cm,
     const uint64_t* __restrict__ cu, uint64_t depm, const __amdgpu_buffer_rsrc_t wrs, int s_z,
-    int s_y, int s_x, int vbase, int M, uint32_t todo, VX& x, VX& y, float* __restrict__ accl,
+    int s_y, int s_x, int vbase, int bw, uint32_t todo, VX& x, VX& y, float* __restrict__ accl,
     const v32f& xlo, const v32f& ylo, uint32_t done0, uint32_t& done, uint32_t& bad,
     uint32_t& sepbad, uint32_t& sepbad_lo, int& nhor) {
     if (!todo) return;
     const int base = HI ? 32 : 0;
     int ii = __builtin_ctz(todo);
-    PwTap ta = pw_issue(p.cf, rec, wrs, s_z, s_y, s_x, vbase, M, base + ii, ii, x, y), tb;
+    PwTap ta = pw_issue<kPwRec>(p.cf, rec, wrs, s_z, s_y, s_x, vbase, bw, base + ii, ii, x, y), tb;
     PwNoise pend;
     pend.i = -1;
 #define PT_ONE(CUR, NXT)                                                                     \
@@ -179,7 +188,7 @@ __device__ __forceinline__ void pt_half(
         todo &= todo - 1u;                                                                   \
         pw_noise_add(pend, accl);                                                            \
         const int inext = todo ? __builtin_ctz(todo) : ii;                                   \
-        NXT = pw_issue(p.cf, rec, wrs, s_z, s_y, s_x, vbase, M, base + inext, inext, x, y);  \
+        NXT = pw_issue<kPwRec>(p.cf, rec, wrs, s_z, s_y, s_x, vbase, bw, base + inext, inext, x, y);  \
         const int i = base + ii;                                                             \
         const uint64_t un = __builtin_amdgcn_readfirstlane((uint32_t)cu[i]) |                \
                             ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(cu[i] >> 32)) << 32); \
@@ -285,14 +294,15 @@ k_rollout_pt(const RolloutParams p, const RolloutArrays a, const float* __restri
     uint32_t done_lo = 0u, done_hi = 0u, bad_lo = 0u, bad_hi = 0u, sep_lo = 0u, sep_hi = 0u;
     int nsim = 0, npair = 0, nhor = 0;
 
-    // fields in the sample-interleaved layout Wt[g][m][c]: the corner
-    // (ix, iy, iz) of sample m sits at byte (g M + m) 8, the other corners
-    // at uniform offsets; lanes past the last sample read sample M - 1 and
-    // write nothing
+    // fields in blocks of kPtS samples, Wt[b][g][kPtS][c]: the corner
+    // (ix, iy, iz) of sample m = b kPtS + t sits at byte ((b G + g) kPtS +
+    // t) 8, the other corners at uniform offsets; lanes past the last
+    // sample read sample M - 1 and write nothing
     const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)Wt, (short)0, p.G * M * 8, 0x00020000);
-    const int s_z = M * 8, s_y = p.nz * M * 8, s_x = p.ny * p.nz * M * 8;
-    const int vbase = (m < M ? m : M - 1) * 8;
+        (void*)Wt, (short)0, (int)wt_elems(M, p.G, kPtS) * 8, 0x00020000);
+    const int s_z = kPtS * 8, s_y = p.nz * kPtS * 8, s_x = p.ny * p.nz * kPtS * 8;
+    const int mc = m < M ? m : M - 1;
+    const int vbase = ((mc / kPtS) * p.G * kPtS + mc % kPtS) * 8;
 
     int s_cur = -1, k_end = 0;
     for (int k = 0; k < H; ++k) {
@@ -316,8 +326,9 @@ k_rollout_pt(const RolloutParams p, const RolloutArrays a, const float* __restri
         for (int r = 0; r < kPtP; ++r) {
             const float zr = pw_phase1(p, pj, k, k0j, k_end, arrj, act, s1[r],
                                        recw + (r * NMAX + lane) * kPwRec, lane < N);
-            // lane i receives the mask of aircraft j < i, active at this step,
-            // with |z_j - z_i| < sep_v
+            // lane i's mask of aircraft j < i, active at this step, with
+            // |z_j - z_i| < sep_v: every lane compares its altitude with
+            // aircraft i's in turn and sets bit i (|z_j - z_i| is symmetric)
             uint32_t mlo = 0u, mhi = 0u;
             uint64_t todo = actk;
             while (todo) {                                          // uniform
@@ -325,25 +336,27 @@ k_rollout_pt(const RolloutParams p, const RolloutArrays a, const float* __restri
                 todo &= todo - 1ull;
                 const float zi = __builtin_bit_cast(
                     float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, zr), i));
-                const uint64_t c = __ballot(m_abs(zr - zi) < q.sep_v) & actk & ((1ull << i) - 1ull);
-                const bool me = lane == i;
-                mlo = me ? (uint32_t)c : mlo;
-                mhi = me ? (uint32_t)(c >> 32) : mhi;
+                // |z_j - z_i| < sep_v from the sign of the difference
+                const uint32_t close = __float_as_uint(m_abs(zr - zi) - q.sep_v) >> 31;
+                if (i < 32) mlo |= close << i;                      // uniform
+                else mhi |= close << (i - 32);
             }
-            const uint64_t mr = ((uint64_t)mhi << 32) | mlo;
+            const uint64_t mr = act ? (((uint64_t)mhi << 32) | mlo) & actk &
+                                          ((1ull << lane) - 1ull)
+                                    : 0ull;
             un |= mr;
-            if (lane < N) cmw[r * NMAX + lane] = act ? mr : 0ull;
+            if (lane < N) cmw[r * NMAX + lane] = mr;
         }
-        if (lane < N) cuw[lane] = act ? un : 0ull;
+        if (lane < N) cuw[lane] = un;
         wave_sync();   // records and masks visible to every lane
 
         // ---- phase 2: every world runs the active aircraft in turn ----
         const uint32_t d0lo = done_lo, d0hi = done_hi;
-        pt_half<false>(p, a, par, recl, cml, cuw, depm, wrs, s_z, s_y, s_x, vbase, M,
+        pt_half<false>(p, a, par, recl, cml, cuw, depm, wrs, s_z, s_y, s_x, vbase, kPtS,
                        (uint32_t)actk, xa, ya, accl, xa, ya, d0lo, done_lo, bad_lo, sep_lo, sep_lo,
                        nhor);
         if (NMAX > 32)
-            pt_half<true>(p, a, par, recl, cml, cuw, depm, wrs, s_z, s_y, s_x, vbase, M,
+            pt_half<true>(p, a, par, recl, cml, cuw, depm, wrs, s_z, s_y, s_x, vbase, kPtS,
                           (uint32_t)(actk >> 32), xb, yb, accl, xa, ya, d0hi, done_hi, bad_hi,
                           sep_hi, sep_lo, nhor);
         {   // aircraft simulated this step and pair tests with both present
@@ -413,7 +426,7 @@ hipError_t launch_rollout_pt(const RolloutParams& p, const RolloutArrays& a, con
                              const void* Wt, hipStream_t st) {
     if (!rollout_pt_supported(p.N, 1) || p.w_kstride != 0) return hipErrorInvalidValue;
     if (p.P <= 0 || p.M <= 0) return hipSuccess;
-    if ((int64_t)p.G * p.M * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    if (wt_elems(p.M, p.G, kPtS) * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     if (p.N <= 32) return launch_pt_n<32>(p, a, acR, Wt, st);
     if (p.N <= 40) return launch_pt_n<40>(p, a, acR, Wt, st);
     if (p.N <= 48) return launch_pt_n<48>(p, a, acR, Wt, st);

@@ -160,7 +160,7 @@ template <bool HI, typename VX>
 __device__ __forceinline__ void pw_half(
     const RolloutParams& p, const RolloutArrays& a, const float* __restrict__ par,
     const float* __restrict__ rec, const __amdgpu_buffer_rsrc_t wrs, int s_z, int s_y, int s_x,
-    int vbase, int M, uint32_t todo, uint64_t actk, float zn_lane, VX& x, VX& y,
+    int vbase, int bw, uint32_t todo, uint64_t actk, float zn_lane, VX& x, VX& y,
     float* __restrict__ accl,
     const v32f& xlo, const v32f& ylo, uint32_t done0, uint32_t& done, uint32_t& bad,
     uint32_t& sepbad, uint32_t& sepbad_lo, int& nhor) {
@@ -169,7 +169,7 @@ __device__ __forceinline__ void pw_half(
     int ii = __builtin_ctz(todo);
     // two lookups alternate (the loop body twice), so that no lookup in
     // flight is copied from register to register
-    PwTap ta = pw_issue(p.cf, rec, wrs, s_z, s_y, s_x, vbase, M, base + ii, ii, x, y), tb;
+    PwTap ta = pw_issue<kPwRec>(p.cf, rec, wrs, s_z, s_y, s_x, vbase, bw, base + ii, ii, x, y), tb;
     PwNoise pend;
     pend.i = -1;
     // one aircraft: first the previous aircraft's population lookup (issued
@@ -182,7 +182,7 @@ __device__ __forceinline__ void pw_half(
         todo &= todo - 1u;                                                                  \
         pw_noise_add(pend, accl);                                                           \
         const int inext = todo ? __builtin_ctz(todo) : ii;                                  \
-        NXT = pw_issue(p.cf, rec, wrs, s_z, s_y, s_x, vbase, M, base + inext, inext, x, y); \
+        NXT = pw_issue<kPwRec>(p.cf, rec, wrs, s_z, s_y, s_x, vbase, bw, base + inext, inext, x, y); \
         pw_aircraft<HI>(p, a, par, rec, CUR, base + ii, actk, zn_lane, x, y, accl, xlo, ylo,  \
                         done0, done, bad, sepbad, sepbad_lo, nhor, pend);                   \
         if (!todo) break;                                                                   \
@@ -273,15 +273,17 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
     uint32_t done_lo = 0u, done_hi = 0u, bad_lo = 0u, bad_hi = 0u, sep_lo = 0u, sep_hi = 0u;
     int nsim = 0, npair = 0, nhor = 0;
 
-    // field of this world's sample in the sample-interleaved layout
-    // Wt[g][m][c]: the corner (ix, iy, iz) of lane m sits at byte
-    // (g M + m) 8, the other corners at uniform offsets
+    // field of this world's sample in blocks of 64 samples,
+    // Wt[b][g][64][c]: the corner (ix, iy, iz) of lane t of block b sits at
+    // byte ((b G + g) 64 + t) 8, the other corners at uniform offsets
+    constexpr int B = kWtBlockPw;
     const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)Wt, (short)0, p.G * M * 8, 0x00020000);
-    const int s_z = M * 8, s_y = p.nz * M * 8, s_x = p.ny * p.nz * M * 8;
+        (void*)Wt, (short)0, (int)wt_elems(M, p.G, B) * 8, 0x00020000);
+    const int s_z = B * 8, s_y = p.nz * B * 8, s_x = p.ny * p.nz * B * 8;
     // lanes past the last sample (M not a multiple of 64) read sample M - 1
     // and write nothing
-    const int vbase = (m < M ? m : M - 1) * 8;
+    const int mc = m < M ? m : M - 1;
+    const int vbase = ((mc / B) * p.G * B + mc % B) * 8;
 
     int s_cur = -1, k_end = 0;
     for (int k = 0; k < H; ++k) {
@@ -303,10 +305,10 @@ k_rollout_pw(const RolloutParams p, const RolloutArrays a, const float* __restri
         // ---- phase 2: every world runs the active aircraft in turn, the
         // wind lookup of the next one issued before this one's arithmetic ----
         const uint32_t d0lo = done_lo, d0hi = done_hi;
-        pw_half<false>(p, a, par, recw, wrs, s_z, s_y, s_x, vbase, M, (uint32_t)actk, actk,
+        pw_half<false>(p, a, par, recw, wrs, s_z, s_y, s_x, vbase, B, (uint32_t)actk, actk,
                        zn_lane, xa, ya, accl, xa, ya, d0lo, done_lo, bad_lo, sep_lo, sep_lo, nhor);
         if (NMAX > 32)
-            pw_half<true>(p, a, par, recw, wrs, s_z, s_y, s_x, vbase, M, (uint32_t)(actk >> 32),
+            pw_half<true>(p, a, par, recw, wrs, s_z, s_y, s_x, vbase, B, (uint32_t)(actk >> 32),
                           actk, zn_lane, xb, yb, accl, xa, ya, d0hi, done_hi, bad_hi, sep_hi,
                           sep_lo, nhor);
         {   // aircraft simulated this step and pair tests with both present
@@ -375,7 +377,7 @@ hipError_t launch_rollout_pw(const RolloutParams& p, const RolloutArrays& a, con
                              const void* Wt, hipStream_t st) {
     if (!rollout_pw_supported(p.N, 1) || p.w_kstride != 0) return hipErrorInvalidValue;
     if (p.P <= 0 || p.M <= 0) return hipSuccess;
-    if ((int64_t)p.G * p.M * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    if (wt_elems(p.M, p.G, kWtBlockPw) * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     if (p.N <= 32) return launch_pw_n<32>(p, a, acR, Wt, st);
     if (p.N <= 40) return launch_pw_n<40>(p, a, acR, Wt, st);
     if (p.N <= 48) return launch_pw_n<48>(p, a, acR, Wt, st);

@@ -54,14 +54,16 @@ template <> struct Ops<double> {
     static __device__ __forceinline__ void sincos(double x, double* s, double* c) { ::sincos(x, s, c); }
     static __device__ __forceinline__ double sin(double x) { return ::sin(x); }
     static __device__ __forceinline__ double atan2(double y, double x) { return ::atan2(y, x); }
+    // atan2 for x >= 0 (the right half-plane)
+    static __device__ __forceinline__ double atan2_xpos(double y, double x) { return ::atan2(y, x); }
 };
 
 // atan(t) for t in [0, 1] as t P(t^2), P of degree 7 fitted by iteratively
 // reweighted least squares toward minimax (max error 4e-8 in exact
 // arithmetic, 1.4e-7 evaluated in FP32); the quadrant follows from the
-// signs and the magnitude order of (x, y).
-__device__ __forceinline__ float fast_atan2(float y, float x) {
-    const float ax = fabsf(x), ay = fabsf(y);
+// signs and the magnitude order of (x, y).  fast_atan2_abs: the angle of
+// (|x|, |y|) in [0, pi/2].
+__device__ __forceinline__ float fast_atan2_abs(float ay, float ax) {
     const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
     const float t = mn * __builtin_amdgcn_rcpf(fmaxf(mx, 1e-30f));
     const float q = t * t;
@@ -73,10 +75,12 @@ __device__ __forceinline__ float fast_atan2(float y, float x) {
     p = fmaf(p, q, 0.1994655877351761f);
     p = fmaf(p, q, -0.33329859375953674f);
     p = fmaf(p, q, 0.9999993443489075f);
-    float a = t * p;
-    a = ay > ax ? 1.57079632679489662f - a : a;
-    a = x < 0.f ? 3.14159265358979324f - a : a;
-    return copysignf(a, y);
+    const float a = t * p;
+    return ay > ax ? 1.57079632679489662f - a : a;
+}
+__device__ __forceinline__ float fast_atan2(float y, float x) {
+    const float a = fast_atan2_abs(fabsf(y), fabsf(x));
+    return copysignf(x < 0.f ? 3.14159265358979324f - a : a, y);
 }
 
 template <> struct Ops<float> {
@@ -92,6 +96,10 @@ template <> struct Ops<float> {
     }
     static __device__ __forceinline__ float sin(float x) { return __sinf(x); }
     static __device__ __forceinline__ float atan2(float y, float x) { return fast_atan2(y, x); }
+    // atan2 for x >= 0 (+0 included): fast_atan2 without the left half-plane
+    static __device__ __forceinline__ float atan2_xpos(float y, float x) {
+        return copysignf(fast_atan2_abs(fabsf(y), x), y);
+    }
 };
 
 template <typename R>

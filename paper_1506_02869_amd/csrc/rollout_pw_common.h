@@ -81,16 +81,18 @@ __device__ __forceinline__ void pw_noise_add(const PwNoise& n, float* __restrict
 
 // Issue the lookup of aircraft i (its position before this step's update;
 // the altitude cell and fraction come from its phase-1 record); x, y: the
-// half holding aircraft i, at index ii.
-template <typename V>
+// half holding aircraft i, at index ii; bw: the samples per block of the
+// fields (grid point g of the lane's block starts at byte vbase + 8 g bw);
+// RS: floats between consecutive aircraft's records.
+template <int RS, typename V>
 __device__ __forceinline__ PwTap pw_issue(const RollConst<float>& q, const float* __restrict__ rec,
                                           const __amdgpu_buffer_rsrc_t wrs, int s_z, int s_y,
-                                          int s_x, int vbase, int M, int i, int ii, const V& x,
+                                          int s_x, int vbase, int bw, int i, int ii, const V& x,
                                           const V& y) {
     PwTap t;
     t.xi = x[ii];
     t.yi = y[ii];
-    const float2 zc = *reinterpret_cast<const float2*>(rec + i * kPwRec + 4);   // cell, fraction
+    const float2 zc = *reinterpret_cast<const float2*>(rec + i * RS + R_GZ);   // cell, fraction
     const float fx = clampr(m_fma(t.xi, q.inv_hx, q.ox), 0.f, q.fnx1);
     const float fy = clampr(m_fma(t.yi, q.inv_hy, q.oy), 0.f, q.fny1);
     const float flx = m_floor(clampr(fx, 0.f, q.fnx2));
@@ -99,7 +101,9 @@ __device__ __forceinline__ PwTap pw_issue(const RollConst<float>& q, const float
     t.ty = fy - fly;
     t.tz = zc.y;
     const int g = (int)m_fma(m_fma(flx, q.fny, fly), q.fnz, zc.x);
-    const int vo = g * (M * 8) + vbase;
+    // (a 24-bit multiply: g < 2^24 and 8 bw < 2^24, the product is a byte
+    // offset inside the fields, below 2^31)
+    const int vo = (int)__umul24((unsigned)g, (unsigned)(bw * 8)) + vbase;
     const int off[8] = {0, s_z, s_y, s_y + s_z, s_x, s_x + s_z, s_x + s_y, s_x + s_y + s_z};
 #pragma unroll
     for (int c = 0; c < 8; ++c)

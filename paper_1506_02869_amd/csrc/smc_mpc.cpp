@@ -56,7 +56,7 @@ struct smc_ctx {
     double *d_acpar = nullptr, *d_targets = nullptr;
     void* d_acR = nullptr;       // [N][kAcR] per-aircraft parameters, real
     int layout = 0;              // rollout layout: 0 auto, 1 aircraft/lane, 2 world/lane,
-                                 // 3 particle/wave
+                                 // 3 particle/wave, 4 particle tile
     int8_t* d_kind = nullptr;
     float* d_pop = nullptr;
     void* d_Lfac = nullptr;
@@ -317,7 +317,9 @@ hipError_t do_rollout(smc_ctx* c, const RolloutParams& rp, const RolloutArrays& 
     case 2: return launch_rollout_wm(c->prec, rp, a, c->d_acR, st);
     case 3:
     case 4: {
-        const hipError_t e = launch_wind_transpose(c->prec, a.W, rp.M, rp.G, c->d_Wt, st);
+        const hipError_t e =
+            launch_wind_transpose(c->prec, a.W, rp.M, rp.G,
+                                  rollout_layout(c) == 3 ? kWtBlockPw : kWtBlockPt, c->d_Wt, st);
         if (e != hipSuccess) return e;
         return rollout_layout(c) == 3 ? launch_rollout_pw(rp, a, c->d_acR, c->d_Wt, st)
                                       : launch_rollout_pt(rp, a, c->d_acR, c->d_Wt, st);
@@ -892,7 +894,7 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     if ((st = dalloc_t(c, &c->d_acpar, N * SMC_AC_NPAR)) || (st = dalloc_t(c, &c->d_targets, N * 4)) ||
         (st = dalloc_t(c, &c->d_kind, N)) ||
         (st = dalloc(c, &c->d_Lfac, G * G * c->rsz)) || (st = dalloc(c, &c->d_Z, G * 2 * Mf * c->rsz)) ||
-        (st = dalloc(c, &c->d_W, Mf * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_Wt, M * G * 2 * c->rsz)) ||
+        (st = dalloc(c, &c->d_W, Mf * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_Wt, wt_elems(M, G, kWtBlockPw) * 2 * c->rsz)) ||
         (st = dalloc(c, &c->d_wpart, std::max<size_t>({part_elems_upto(c),
                                                        c->wind_model == SMC_WIND_EXP_AR1 ? wind_gemm_part_elems(fx, (int)Mf * c->nz) : 0,
                                                        (size_t)1}) *
