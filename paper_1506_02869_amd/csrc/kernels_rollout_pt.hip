@@ -42,7 +42,7 @@ template <int NMAX>
 constexpr int pt_waves() { return NMAX <= 40 ? 2 : 1; }
 // wavefronts per workgroup: a wavefront takes about NMAX x 480 bytes of LDS
 // (records, candidate masks, cost sums), so up to 40 aircraft one
-// workgroup of 8 wavefronts fills a CU (156 KB of 160), above that 4
+// workgroup of 8 wavefronts fills a CU (157 KB of 160), above that 4
 template <int NMAX>
 constexpr int pt_wgw() { return NMAX <= 40 ? 8 : 4; }
 
@@ -213,8 +213,13 @@ k_rollout_pt(const RolloutParams p, const RolloutArrays a, const float* __restri
     constexpr int kPtWaves = pt_wgw<NMAX>();
     constexpr int kPtPart = kPtP * kPtWaves;   // particles per workgroup
     __shared__ __attribute__((aligned(16))) float par[NMAX * kPwPar];
-    __shared__ __attribute__((aligned(16))) float recs[kPtWaves * kPtP * NMAX * kPwRec];
-    __shared__ uint64_t cmask[kPtWaves * kPtP * NMAX];   // per particle
+    // per-particle strides padded so that the four particles' records (and
+    // masks) of one aircraft, read together by the wave, fall in distinct
+    // LDS banks
+    constexpr int kRecStride = NMAX * kPwRec + 4;       // floats
+    constexpr int kMaskStride = NMAX + 1;                // 64-bit words
+    __shared__ __attribute__((aligned(16))) float recs[kPtWaves * kPtP * kRecStride];
+    __shared__ uint64_t cmask[kPtWaves * kPtP * kMaskStride];   // per particle
     __shared__ uint64_t cunion[kPtWaves * NMAX];         // union over the wave's particles
     __shared__ float accs[kPtWaves * NMAX * 64];         // [wave][aircraft][lane]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -266,10 +271,10 @@ k_rollout_pt(const RolloutParams p, const RolloutArrays a, const float* __restri
     uint64_t depm = 0ull;
     for (int i = 0; i < N; ++i)
         if (a.kind[i] != 0) depm |= 1ull << i;
-    float* recw = recs + wv * kPtP * NMAX * kPwRec;          // the wave's records
-    const float* recl = recw + pl * NMAX * kPwRec;           // the lane's particle's
-    uint64_t* cmw = cmask + wv * kPtP * NMAX;
-    const uint64_t* cml = cmw + pl * NMAX;
+    float* recw = recs + wv * kPtP * kRecStride;             // the wave's records
+    const float* recl = recw + pl * kRecStride;              // the lane's particle's
+    uint64_t* cmw = cmask + wv * kPtP * kMaskStride;
+    const uint64_t* cml = cmw + pl * kMaskStride;
     uint64_t* cuw = cunion + wv * NMAX;
 
     // phase-2 state: one world per lane, all aircraft; aircraft i < 32 in
@@ -325,7 +330,7 @@ k_rollout_pt(const RolloutParams p, const RolloutArrays a, const float* __restri
 #pragma unroll
         for (int r = 0; r < kPtP; ++r) {
             const float zr = pw_phase1(p, pj, k, k0j, k_end, arrj, act, s1[r],
-                                       recw + (r * NMAX + lane) * kPwRec, lane < N);
+                                       recw + r * kRecStride + lane * kPwRec, lane < N);
             // lane i's mask of aircraft j < i, active at this step, with
             // |z_j - z_i| < sep_v: every lane compares its altitude with
             // aircraft i's in turn and sets bit i (|z_j - z_i| is symmetric)
@@ -345,7 +350,7 @@ k_rollout_pt(const RolloutParams p, const RolloutArrays a, const float* __restri
                                           ((1ull << lane) - 1ull)
                                     : 0ull;
             un |= mr;
-            if (lane < N) cmw[r * NMAX + lane] = mr;
+            if (lane < N) cmw[r * kMaskStride + lane] = mr;
         }
         if (lane < N) cuw[lane] = un;
         wave_sync();   // records and masks visible to every lane
