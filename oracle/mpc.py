@@ -10,8 +10,10 @@ the problem once it has landed.
 
 Readings (the paper is silent): the applied part is the first control
 segment, ceil(H / S) steps; the plant flies the plan with the rollout's
-arithmetic through one wind field, sample 0 of the fields the optimiser
-would draw for an iteration word it never uses (``plant_iter``); a departure
+arithmetic through one wind sample, sample 0 of the fields the optimiser
+would draw for an iteration word it never uses (``plant_iter``): one static
+field, or under the paper's time-correlated model (Sec. "Wind Model") that
+sample's field of each step; a departure
 leaves the problem once it is outside its exit radius D_TMA; the plant's
 states are exact (no observer).
 """
@@ -40,13 +42,13 @@ def plant_step(scen, controls, states, k_active, n_steps, plant_iter, mpc_step,
     arrival that landed or a departure outside its exit radius leaves the
     problem (k_active -1); event is 1 landed, 2 left through the exit
     radius, 0 otherwise.  An aircraft that has not joined keeps its state."""
-    if int(scen.get("wind_model", 0)) != 0:
-        raise NotImplementedError("plant step: static wind model only")
     H = scen["H"] if horizon is None else int(horizon)
     N = scen["N"]
     lo, hi = scen["ctrl_lo"], scen["ctrl_hi"]
     u = ((np.asarray(controls, dtype=np.float64) - lo) / (hi - lo))[None]
-    W = _wind.sample_field(scen, plant_iter, mpc_step, Lfac)[:1]
+    W = _wind.sample_field(scen, plant_iter, mpc_step, Lfac)
+    # sample 0: its static field, or its field of every step [H, 1, G, 2]
+    W = W[:, :1] if W.ndim == 4 else W[:1]
     r = _rollout.rollout(scen, u, W, states, k_active, H, record=True)
     track, present = r["track"][:, 0, 0], r["present"][:, 0, 0]     # [H+1, N, 6], [H, N]
     is_arr = scen["kind"] == 0
@@ -74,8 +76,7 @@ def rolling_window(scen, n_updates, plant_iter=None, Lfac=None):
     plant step, k_active, events)."""
     plant_iter = scen["K"] + 1 if plant_iter is None else plant_iter
     if Lfac is None:
-        Lfac = _wind.kron_factor(scen["box"], scen["grid"], scen["wind_sigma"],
-                                 scen["wind_ell"], scen["wind_nugget"])
+        Lfac = _wind.factor(scen)
     states = np.array(scen["states"], dtype=np.float64)
     kact = np.array(scen["k_active"], dtype=np.int32)
     n = applied_steps(scen)

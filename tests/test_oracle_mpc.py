@@ -92,3 +92,50 @@ def test_departure_leaves_through_the_exit_radius():
                                     plant_iter=9, mpc_step=0)
     assert list(ev) == [2] and list(k_new) == [-1]
     assert math.hypot(new[0, 0], new[0, 1]) >= dtma
+
+
+def test_straight_level_flight_closed_form_time_correlated_wind():
+    """The same closed form holds under the paper's time-correlated wind
+    model (Sec. "Wind Model") when the air is still (sigma 0, no mean)."""
+    s = _still_air(0, 2, wind_model="ar1")
+    st = np.array([[20e3, -5e3, 3000.0, 180.0, 0.3, 70e3],
+                   [-10e3, 8e3, 2500.0, 200.0, -2.0, 65e3]])
+    n = 10
+    new, k_new, ev = mpc.plant_step(s, _level(s, st[:, 3][:, None]), st, np.zeros(2, np.int32),
+                                    n, plant_iter=9, mpc_step=0)
+    for i in range(2):
+        v, chi = st[i, 3], st[i, 4]
+        assert math.isclose(new[i, 0], st[i, 0] + n * 5.0 * v * math.cos(chi), rel_tol=1e-12)
+        assert math.isclose(new[i, 1], st[i, 1] + n * 5.0 * v * math.sin(chi), rel_tol=1e-12,
+                            abs_tol=1e-9)
+    assert list(ev) == [0, 0]
+
+
+def test_plant_flies_each_steps_field_of_sample_zero():
+    """Under the time-correlated model with zero decay rates in space
+    (beta = gamma = 0: every field is one vector over the whole grid, up to
+    the nugget) the plant's displacement over n steps of straight and level
+    flight is n dt v (cos chi, sin chi) plus dt times the sum of sample 0's
+    wind vectors of steps 0 .. n-1 (Euler: the wind at the start of each
+    step).  Using one field for all steps, or another sample, fails."""
+    from oracle import wind as owind
+    s = dict(_still_air(0, 1, wind_model="ar1"))
+    s["wind_sigma"] = 5.0
+    s["wind_beta"] = 0.0
+    s["wind_gamma"] = 0.0
+    s["wind_tcorr"] = 60.0            # a = exp(-dt / G_t): fields change from step to step
+    st = np.array([[5e3, 2e3, 3000.0, 190.0, 0.7, 68e3]])
+    n = 8
+    new, _, _ = mpc.plant_step(s, _level(s, 190.0), st, np.zeros(1, np.int32), n,
+                               plant_iter=9, mpc_step=0)
+    W = owind.sample_field(s, 9, 0)                       # [H, M, G, 2]
+    assert W.ndim == 4
+    w = W[:n, 0, 0, :]                                    # sample 0, grid point 0
+    assert np.ptp(W[:n, 0], axis=1).max() < 1e-3          # uniform over the grid
+    assert np.ptp(w[:, 0]) > 0.1                          # and changing in time
+    dx = n * 5.0 * 190.0 * math.cos(0.7) + 5.0 * w[:, 0].sum()
+    dy = n * 5.0 * 190.0 * math.sin(0.7) + 5.0 * w[:, 1].sum()
+    assert abs(new[0, 0] - (st[0, 0] + dx)) < 0.05
+    assert abs(new[0, 1] - (st[0, 1] + dy)) < 0.05
+    # a plant that used step 0's field throughout would be off by this much
+    assert abs(5.0 * (w[:, 0].sum() - n * w[0, 0])) > 1.0
