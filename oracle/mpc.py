@@ -71,7 +71,9 @@ def plant_step(scen, controls, states, k_active, n_steps, plant_iter, mpc_step,
 
 def rolling_window(scen, n_updates, plant_iter=None, Lfac=None):
     """n_updates receding-horizon updates from the scenario's states: solve
-    (Alg. 1), apply the first segment to the plant, shift the window.
+    (Alg. 1), apply the first segment to the plant, shift the window (with
+    the scenario's warm start on, each update after the first starts from
+    the previous update's final population shifted by that segment).
     Returns a list of per-update dicts (controls, cost, states after the
     plant step, k_active, events)."""
     plant_iter = scen["K"] + 1 if plant_iter is None else plant_iter
@@ -81,9 +83,12 @@ def rolling_window(scen, n_updates, plant_iter=None, Lfac=None):
     kact = np.array(scen["k_active"], dtype=np.int32)
     n = applied_steps(scen)
     out = []
+    u_prev = None
     for t in range(n_updates):
         step = int(scen["mpc_step"]) + t
-        res = _smc.smc_mpc_step(scen, states=states, k_active=kact, mpc_step=step)
+        res = _smc.smc_mpc_step(scen, states=states, k_active=kact, mpc_step=step,
+                                u_prev=u_prev)
+        u_prev = res["result"]["u"]
         states, kact, ev = plant_step(scen, res["controls"], states, kact, n, plant_iter,
                                       step, Lfac=Lfac)
         out.append(dict(controls=res["controls"], cost=res["cost"], states=states.copy(),

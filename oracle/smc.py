@@ -66,6 +66,20 @@ def init_particles(scen, mpc_step=None, L=None):
     return u.reshape(L, N, S, 3)
 
 
+def warm_start_particles(scen, u_prev, mpc_step=None):
+    """Initial population of a warm-started update (Sec. "Model Predictive
+    Control", "Rolling Window": the window moves by the applied part, the
+    first control segment).  Particle l's segment s is the previous update's
+    final particle l's segment s + 1; the last segment, past the previous
+    horizon, is drawn U(0, 1) as a fresh initialisation draws that element."""
+    u_prev = np.asarray(u_prev, dtype=np.float64)
+    L, N, S = u_prev.shape[0], scen["N"], scen["S"]
+    u = np.empty_like(u_prev)
+    u[:, :, :S - 1] = u_prev[:, :, 1:]
+    u[:, :, S - 1] = init_particles(scen, mpc_step, L)[:, :, S - 1]
+    return u
+
+
 def expected_cost(cost, feas):
     """c_hat[l, i] = (1/M) sum_m cost[l, m, i] (exactly rounded sum),
     feasible[l, i] = all_m feas[l, m, i]."""
@@ -358,10 +372,12 @@ def physical(scen, u_norm):
 
 
 def smc_mpc_step(scen, states=None, k_active=None, horizon=None, mpc_step=None,
-                 trace=None):
+                 trace=None, u_prev=None):
     """One MPC update: returns the optimised controls [N, S, 3] (physical),
     the expected cost (total, per aircraft) of the chosen particle and the
-    infeasible flag."""
+    infeasible flag.  With the scenario's warm start on and the previous
+    update's final population u_prev [L, N, S, 3], the update starts from
+    warm_start_particles instead of a fresh draw."""
     N, S, L, K = scen["N"], scen["S"], scen["L"], scen["K"]
     step = scen["mpc_step"] if mpc_step is None else mpc_step
     Lfac = _wind.factor(scen)
@@ -387,7 +403,10 @@ def smc_mpc_step(scen, states=None, k_active=None, horizon=None, mpc_step=None,
         from .grad import grad_fuel_time
         return grad_fuel_time(scen, u, field(J), states, k_active, horizon)[1]
 
-    res = run_smc(scen, evaluate, L, K, N, S, step, trace, grad=grad)
+    u_init = None
+    if scen.get("warm_start", 0) and u_prev is not None:
+        u_init = warm_start_particles(scen, u_prev, step)
+    res = run_smc(scen, evaluate, L, K, N, S, step, trace, u_init=u_init, grad=grad)
     l = res["best"]
     per = res["chat"][l]
     total = 0.0

@@ -30,7 +30,9 @@ units (angles in radians).  Field list, in the order the C ABI takes them:
     time_norm, noise_alt, popdense[ny_p, nx_p] float32 or None,
     precision (0 fp64, 1 fp32), move (0 jitter, 1 rwmh, 2 mala),
     control_model (0 kinematic segment controls, 1 the paper's per-step
-    thrust fraction / flight-path angle / bank, S = H),
+    thrust fraction / flight-path angle / bank, S = H), warm_start (1: an
+    update after the first starts from the previous update's final
+    population shifted by one control segment),
     kappa, sigma_move, mala_step (standard deviation of the Langevin proposal
     in logit coordinates: the time step h = 1e-2 of the differentiable
     workload gives sqrt(h) = 0.1), seed,
@@ -126,7 +128,8 @@ def make_scenario(name: str, *, n_arr: int, n_dep: int, box, grid, H: int,
                   noise_alt: float = 2000.0, pop_n=None, kappa: float = 1.0,
                   sigma_move: float = 0.02, mala_step: float = 0.1,
                   mpc_step: int = 0, wind_model: str = "se",
-                  wind_tcorr: float = 1800.0, controls: str = "kinematic") -> dict:
+                  wind_tcorr: float = 1800.0, controls: str = "kinematic",
+                  warm_start: bool = False) -> dict:
     rng = np.random.default_rng(seed)
     box = tuple(float(b) for b in box)
     N = n_arr + n_dep
@@ -182,6 +185,7 @@ def make_scenario(name: str, *, n_arr: int, n_dep: int, box, grid, H: int,
         wind_model=WIND_MODELS[wind_model], wind_beta=1.6e-6, wind_gamma=1.5e-5,
         wind_tcorr=float(wind_tcorr),
         control_model=CONTROL_MODELS[controls],
+        warm_start=int(bool(warm_start)),
     )
 
 
