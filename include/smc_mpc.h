@@ -120,8 +120,8 @@ enum { SMC_CONTROLS_KINEMATIC = 0, SMC_CONTROLS_PAPER = 1 };
  *  W(k+1) = a W(k) + sqrt(1 - a^2) Qhat v(k+1), a = exp(-dt / wind_tcorr)
  *  (wind_tcorr = G_t [s], > 0; infinity freezes the field), v(k) of sample m
  *  being the normals of sample k M + m; wind_ell is not used.  Limits of
- *  SMC_WIND_EXP_AR1: n_aircraft <= 20, move not SMC_MOVE_MALA, no
- *  smc_plant_step, not in the batched form; horizon_max * n_wind * G * 2
+ *  SMC_WIND_EXP_AR1: n_aircraft <= 20, move not SMC_MOVE_MALA, not in
+ *  the batched form; horizon_max * n_wind * G * 2
  *  reals below 2^31 bytes; at most 16 levels (nz); init factors the
  *  (nx ny)^2 horizontal Gram matrix on the host.
  *  weighting SMC_WEIGHT_TEMPERED: every iteration J rolls out all n_wind
@@ -145,6 +145,14 @@ enum { SMC_CONTROLS_KINEMATIC = 0, SMC_CONTROLS_PAPER = 1 };
  *  altitude band grows at v_max sin(max |gamma bound|).  Limits:
  *  n_aircraft <= 20 (world-per-lane rollout), static wind model, move not
  *  SMC_MOVE_MALA, no smc_plant_step, not in the batched form.
+ *  warm_start 1 (Sec. "Model Predictive Control", "Rolling Window": the
+ *  window moves by the applied first control segment): every update after
+ *  the context's first starts from the previous update's final population
+ *  (the particles of its last weighting pass), particle l's segment s taken
+ *  from the previous particle l's segment s + 1 and the last segment drawn
+ *  U(0, 1) as a fresh initialisation draws that element; 0: every update
+ *  draws fresh particles (Alg. 1).  Kinematic controls only; not in the
+ *  batched form.
  */
 typedef struct {
     int32_t n_aircraft, n_segments, horizon_max, n_particles, n_wind, n_iters;
@@ -171,6 +179,7 @@ typedef struct {
     double wind_beta, wind_gamma, wind_tcorr;   /* SMC_WIND_EXP_AR1 only */
     int32_t weighting;                          /* SMC_WEIGHT_* */
     int32_t control_model;                      /* SMC_CONTROLS_* */
+    int32_t warm_start;                         /* 0 or 1 */
 } smc_scenario;
 
 /* Diagnostics of one MPC update (optional output).  When requested, device
@@ -251,10 +260,11 @@ smc_status smc_eval_cost(smc_ctx* ctx, int64_t mpc_step, int32_t iter,
  * n_steps steps of the plan `controls` [N x S x 3] (physical units, as
  * returned by smc_mpc_step for `horizon`; segment s(k) = floor(k S /
  * horizon)) from `states` with the rollout's arithmetic (the context's
- * precision), through one wind field: sample 0 of the fields of iteration
+ * precision), through one wind sample: sample 0 of the fields of iteration
  * word `plant_iter` of update `mpc_step` (an iteration word >= n_iters is
- * never drawn by the optimiser), with mean wind_mean.  An arrival stops when
- * it meets the landing sector.
+ * never drawn by the optimiser), with mean wind_mean; one static field, or
+ * under SMC_WIND_EXP_AR1 that sample's field of each step (Sec. "Wind
+ * Model").  An arrival stops when it meets the landing sector.
  *  states_out[N x 6]: states after the steps (an aircraft that has not
  *     joined keeps its state; a landed one its landing state).
  *  k_active_out[N]: activation steps for the next update: k_active -

@@ -61,6 +61,7 @@ class Scenario(C.Structure):
         ("seed", C.c_uint64), ("scenario_id", C.c_int32),
         ("wind_model", C.c_int32), ("wind_beta", C.c_double), ("wind_gamma", C.c_double),
         ("wind_tcorr", C.c_double), ("weighting", C.c_int32), ("control_model", C.c_int32),
+        ("warm_start", C.c_int32),
     ]
 
 
@@ -358,6 +359,7 @@ def make_scenario_struct(s: dict):
     sc.wind_tcorr = float(s.get("wind_tcorr", 0.0))
     sc.weighting = int(s.get("weighting", 0))
     sc.control_model = int(s.get("control_model", 0))
+    sc.warm_start = int(s.get("warm_start", 0))
     return sc, keep
 
 

@@ -121,6 +121,11 @@ struct BatchStep {
 // precision: 0 = double, 1 = float
 hipError_t launch_philox_words(Stream s, uint32_t e0, int64_t n, uint32_t* out,
                                hipStream_t st);
+// Warm start: u = the previous final population moved one control segment
+// earlier, the last segment drawn as launch_init_particles draws it
+// (count = P N S 3 elements; prev and u distinct).
+hipError_t launch_warm_start(int prec, Stream s, int64_t count, int S, const void* prev,
+                             void* u, hipStream_t st);
 hipError_t launch_init_particles(int prec, Stream s, int64_t count, void* u,
                                  hipStream_t st);
 hipError_t launch_wind_normals(int prec, Stream s, int G, int M, void* Z,

@@ -3,8 +3,10 @@
 // plant's disturbance differs from the optimiser's predictions; Sec.
 // "Rolling Window": aircraft join at their pre-determined step and leave the
 // problem when they finish).  One lane per aircraft: every aircraft that has
-// joined flies the applied steps of its plan through one wind field with the
-// rollout's per-step arithmetic; an arrival stops when it meets the landing
+// joined flies the applied steps of its plan through one wind sample (one
+// static field, or under the paper's time-correlated model that sample's
+// field of each step, p.w_kstride reals apart) with the rollout's per-step
+// arithmetic; an arrival stops when it meets the landing
 // sector.  Written back: the states after the steps, the shifted activation
 // steps and the events (1 landed, 2 left through the exit radius).
 #include "rollout_math.h"
@@ -43,7 +45,7 @@ k_plant(const RolloutParams p, const double* __restrict__ ctrl, const R* __restr
     const R p_run = (R)p.p_run, p_beta = (R)p.p_beta, p_chi = (R)p.p_chi, p_vs = (R)p.p_vs;
     const R isa_c = (R)(kLapse / kT0), isa_e = (R)(kG0 / (kRair * kLapse) - 1.0);
     const R rho0 = (R)kRho0;
-    const R2* Wm = (const R2*)W;                 // the plant's one wind field
+    const R2* W0 = (const R2*)W;                 // the plant's wind sample (step 0)
 
     bool landed = false;
     for (int k = 0; k < n_steps; ++k) {
@@ -55,7 +57,8 @@ k_plant(const RolloutParams p, const double* __restrict__ ctrl, const R* __restr
         const R zdot = (R)ctrl[(i * S + s) * 3 + 2];
         const R inv_rem = O::rcp((R)(k_end - k));
 
-        // trilinear wind at the current position (coordinates clamped)
+        // trilinear wind of step k at the current position (coordinates clamped)
+        const R2* Wm = (const R2*)((const R*)W0 + (int64_t)k * p.w_kstride);
         const R fx = clampr((x + half_wx) * inv_hx, (R)0, fnx1);
         const R fy = clampr((y + half_wy) * inv_hy, (R)0, fny1);
         const R fz = clampr(z * inv_hz, (R)0, fnz1);

@@ -21,6 +21,20 @@ __global__ void k_init_particles(Stream s, int64_t count, R* u) {
     u[e] = to_real<R>(init_value(s, (uint32_t)e));
 }
 
+// Warm start of the receding-horizon loop (Sec. "Model Predictive Control",
+// "Rolling Window": the window moved by the applied first control
+// segment): element e = ((l N + i) S + s) 3 + c takes element e + 3 of the
+// previous final population (segment s + 1) for s < S - 1; the last
+// segment is the fresh initialisation's draw of element e.
+template <typename R>
+__global__ void k_warm_start(Stream s, int64_t count, int S, const R* __restrict__ prev,
+                             R* __restrict__ u) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const int seg = (int)((e / 3) % S);
+    u[e] = seg < S - 1 ? prev[e + 3] : to_real<R>(init_value(s, (uint32_t)e));
+}
+
 // Z[g][2m + c]: thread per (g, m) with m fastest so that the pair of
 // components is one coalesced 2-element store; counter element m G + g.
 template <typename R>
@@ -180,6 +194,18 @@ hipError_t launch_init_particles(int prec, Stream s, int64_t count, void* u,
     else
         hipLaunchKernelGGL(k_init_particles<float>, dim3(blocks_for(count, 256)),
                            dim3(256), 0, st, s, count, (float*)u);
+    return hipGetLastError();
+}
+
+hipError_t launch_warm_start(int prec, Stream s, int64_t count, int S, const void* prev,
+                             void* u, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_warm_start<double>, dim3(blocks_for(count, 256)), dim3(256), 0, st,
+                           s, count, S, (const double*)prev, (double*)u);
+    else
+        hipLaunchKernelGGL(k_warm_start<float>, dim3(blocks_for(count, 256)), dim3(256), 0, st,
+                           s, count, S, (const float*)prev, (float*)u);
     return hipGetLastError();
 }
 

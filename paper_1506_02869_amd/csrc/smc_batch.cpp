@@ -159,6 +159,8 @@ smc_status validate_batch(const smc_scenario* sc, int ns) {
             return bfail(nullptr, SMC_EINVAL, "scenario %d: the batched form takes the tempered weighting only", s);
         if (sc[s].wind_model != SMC_WIND_SE)
             return bfail(nullptr, SMC_EINVAL, "scenario %d: the batched form takes the static wind model only", s);
+        if (sc[s].warm_start != 0)
+            return bfail(nullptr, SMC_EINVAL, "scenario %d: warm_start is not supported in the batched form", s);
         if (sc[s].control_model != SMC_CONTROLS_KINEMATIC)
             return bfail(nullptr, SMC_EINVAL, "scenario %d: the batched form takes the kinematic controls only", s);
         if (host::validate_scenario(&sc[s], msg))

@@ -61,6 +61,8 @@ struct smc_ctx {
     float* d_pop = nullptr;
     void* d_Lfac = nullptr;
     void *d_Z = nullptr, *d_W = nullptr, *d_Wt = nullptr;
+    int warm_start = 0;          // start from the previous update's population
+    void* u_last = nullptr;      // the buffer holding the last update's final population
     void* d_wpart = nullptr;   // wind GEMM chunk products (few-tile shapes)
     // time-correlated wind: sigma L_h [nh][nh] real, L_z [nz][nz] double, the
     // level-mixed normals Y [nh][2 Mf][nz] real
@@ -198,6 +200,10 @@ smc_status validate(const smc_scenario* s) {
     }
     if (s->control_model != SMC_CONTROLS_KINEMATIC && s->control_model != SMC_CONTROLS_PAPER)
         return fail(nullptr, SMC_EINVAL, "control_model must be SMC_CONTROLS_KINEMATIC or SMC_CONTROLS_PAPER");
+    if (s->warm_start != 0 && s->warm_start != 1)
+        return fail(nullptr, SMC_EINVAL, "warm_start must be 0 or 1");
+    if (s->warm_start && s->control_model != SMC_CONTROLS_KINEMATIC)
+        return fail(nullptr, SMC_EINVAL, "warm_start: kinematic segment controls only");
     if (s->control_model == SMC_CONTROLS_PAPER) {
         if (s->n_segments < s->horizon_max)
             return fail(nullptr, SMC_EINVAL, "the paper's controls need n_segments >= horizon_max (one control set per step)");
@@ -400,8 +406,15 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
     }
     void* u = c->d_u;
     void* u2 = c->d_u2;
-    HIP_OK(c, launch_init_particles(c->prec, make_stream(c->seed, mpc_step, 0, P_INIT, c->scen_id),
-                                    count, u, st));
+    const Stream s_init = make_stream(c->seed, mpc_step, 0, P_INIT, c->scen_id);
+    if (c->warm_start && c->u_last) {
+        // the previous final population, moved one segment earlier, into
+        // the other buffer
+        if (c->u_last == u) std::swap(u, u2);
+        HIP_OK(c, launch_warm_start(c->prec, s_init, count, c->S, c->u_last, u, st));
+    } else {
+        HIP_OK(c, launch_init_particles(c->prec, s_init, count, u, st));
+    }
     double acc_sum = 0.0;
     int acc_n = 0, n_roll = 0, n_roll2 = 0;
     std::vector<int32_t> hflags;
@@ -499,6 +512,7 @@ smc_status run_step(smc_ctx* c, int64_t mpc_step, const double* d_states, const 
                                      c->sigma_move, c->move == SMC_MOVE_JITTER ? 1 : 0, st));
         std::swap(u, u2);
     }
+    c->u_last = u;   // this update's final population (a warm start's source)
     const double beta_last = beta_of(c, c->K - 1);
     HIP_OK(c, launch_select(L, N, c->d_logw, c->d_chat, beta_last, c->d_best, st));
     HIP_OK(c, launch_write_result(c->prec, N, c->S, u, c->d_best, c->d_chat, c->ctrl_lo,
@@ -820,6 +834,7 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     c->bar1 = std::sqrt(std::max(0.0, 1.0 - c->war1 * c->war1));
     c->Mf = c->wind_model == SMC_WIND_EXP_AR1 ? c->Hmax * c->M : c->M;
     c->weighting = s->weighting;
+    c->warm_start = s->warm_start;
 
     host::fill_rollout_params(s, c->rp);
     c->rp.w_kstride = c->wind_model == SMC_WIND_EXP_AR1 ? (int64_t)c->M * c->G * 2 : 0;
@@ -1016,8 +1031,6 @@ smc_status smc_plant_step(smc_ctx* c, int64_t mpc_step, int32_t plant_iter, cons
     if (vs) return vs;
     if (n_steps < 1 || n_steps > horizon) return fail(c, SMC_EINVAL, "n_steps must be in [1, horizon]");
     if (plant_iter < 0) return fail(c, SMC_EINVAL, "plant_iter must be >= 0");
-    if (c->wind_model != SMC_WIND_SE)
-        return fail(c, SMC_EINVAL, "smc_plant_step: static wind model only");
     if (c->rp.control_model != SMC_CONTROLS_KINEMATIC)
         return fail(c, SMC_EINVAL, "smc_plant_step: kinematic controls only");
     hipStream_t st = c->stream;
@@ -1026,10 +1039,10 @@ smc_status smc_plant_step(smc_ctx* c, int64_t mpc_step, int32_t plant_iter, cons
     HIP_OK(c, hipMemcpyAsync(c->d_kact, k_active, sizeof(int32_t) * N, hipMemcpyHostToDevice, st));
     HIP_OK(c, hipMemcpyAsync(c->d_ctrl_out, controls, sizeof(double) * N * c->S * 3,
                              hipMemcpyHostToDevice, st));
-    HIP_OK(c, launch_wind_normals(c->prec, make_stream(c->seed, mpc_step, plant_iter, P_WIND, c->scen_id),
-                                  c->G, c->M, c->d_Z, st));
-    HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G, c->M,
-                               c->d_W, c->d_wpart, st));
+    // the fields of iteration word plant_iter (every step's under the
+    // time-correlated model, rp.w_kstride apart); the plant flies sample 0
+    HIP_OK(c, wind_normals(c, mpc_step, plant_iter, st));
+    HIP_OK(c, wind_fields_gemm(c, wind_mean, c->d_W, st));
     RolloutParams rp = c->rp;
     rp.H = horizon;
     HIP_OK(c, launch_plant(c->prec, rp, c->d_ctrl_out, c->d_W, c->d_states, c->d_kact, c->d_acpar,

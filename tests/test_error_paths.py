@@ -61,3 +61,18 @@ def test_the_same_grid_with_its_nugget_factorises():
         assert st in (smc.SMC_EDEVICE, smc.SMC_ENOMEM)
     else:
         smc.lib().smc_destroy(C.c_void_p(h))
+
+
+@pytest.mark.parametrize("case", ["value", "paper_controls"])
+def test_warm_start_refusals(case):
+    """warm_start must be 0 or 1 and takes the kinematic segment controls
+    (the shift is by one control segment)."""
+    if case == "value":
+        s = dict(synth.shrink(synth.c1(), L=16, K=2), warm_start=2)
+    else:
+        s = dict(synth.shrink(synth.make_scenario("W", n_arr=1, n_dep=1, box=(60e3, 60e3, 6e3),
+                                                  grid=(4, 4, 2), H=6, dt=10.0, S=6, M=2,
+                                                  L=16, K=2, controls="paper")), warm_start=1)
+    st, h, msg = _init(s)
+    assert st == smc.SMC_EINVAL and h is None
+    assert "warm_start" in msg

@@ -93,3 +93,42 @@ def test_rolling_window_c1_matches_oracle(lib):
         assert np.abs(g["controls"] - r["controls"]).max() < 1e-6 * 250.0, t
         assert np.array_equal(g["k_active"], r["k_active"]) and np.array_equal(g["event"], r["event"])
         assert np.all(rel_err(g["states"], r["states"], floor=1.0) < 1e-8), t
+
+
+@pytest.mark.parametrize("move", ["jitter", "rwmh"])
+def test_rolling_window_c1_warm_start_matches_oracle(lib, move):
+    """With the warm start each update after the first starts from the
+    previous update's final population moved one control segment earlier:
+    three C1 updates in FP64 against the oracle's loop (same controls, same
+    plant states); the second update differs from a cold loop's."""
+    s = synth.shrink(synth.c1(move=move), L=128, K=6)
+    sw = dict(s, warm_start=1)
+    got = lib.rolling_window(lib.smc_mpc_init(sw), 3)
+    ref = ompc.rolling_window(sw, 3)
+    for t, (g, r) in enumerate(zip(got, ref)):
+        assert np.abs(g["controls"] - r["controls"]).max() < 1e-6 * 250.0, t
+        assert np.array_equal(g["k_active"], r["k_active"]) and np.array_equal(g["event"], r["event"])
+        assert np.all(rel_err(g["states"], r["states"], floor=1.0) < 1e-8), t
+    cold = lib.rolling_window(lib.smc_mpc_init(s), 2)
+    assert np.array_equal(cold[0]["controls"], got[0]["controls"])
+    assert not np.array_equal(cold[1]["controls"], got[1]["controls"])
+
+
+def test_warm_start_fp32_update(lib):
+    """FP32, 10 aircraft: the second update of a warm-started context
+    differs from a cold context's second update, and its returned cost is
+    what the FP64 oracle gives the returned particle on that update's last
+    fields (within the FP32 bound)."""
+    from oracle import smc as osmc
+    s = synth.shrink(synth.c2(), M=8, L=64, K=3, H=60, S=6, grid=(8, 8, 4))
+    warm = lib.smc_mpc_init(dict(s, warm_start=1))
+    cold = lib.smc_mpc_init(s)
+    for ctx in (warm, cold):
+        lib.smc_mpc_step(ctx, mpc_step=0)
+    gw = lib.smc_mpc_step(warm, mpc_step=1)
+    gc = lib.smc_mpc_step(cold, mpc_step=1)
+    assert not np.array_equal(gw[0], gc[0])
+    lo, hi = s["ctrl_lo"], s["ctrl_hi"]
+    u_got = (gw[0] - lo) / (hi - lo)
+    rc, _ = osmc.eval_cost(s, u_got[None], s["K"] - 1, mpc_step=1)
+    assert abs(float(rc.sum()) - gw[1][0]) <= 1e-4 * max(abs(float(rc.sum())), 1.0)

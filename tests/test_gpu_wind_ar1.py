@@ -134,8 +134,6 @@ def test_time_correlated_wind_rejects_unsupported_calls(lib):
     s = _ar1(synth.c1, M=2, grid=(4, 4, 2), L=16)
     ctx = lib.smc_mpc_init(s)
     with pytest.raises(lib.SmcError):
-        lib.smc_plant_step(ctx, np.zeros((s["N"], s["S"], 3)), plant_iter=3, n_steps=5)
-    with pytest.raises(lib.SmcError):
         lib.smc_set_rollout_layout(ctx, 1)
     P, N = 4, s["N"]
     u = zeros((P, N, s["S"], 3), torch.float64)
@@ -211,3 +209,38 @@ def test_frozen_time_correlation_repeats_the_first_field(lib, grid):
         assert np.array_equal(got[k], got[0]), k
     ref = owind.sample_field(s, 2)
     assert np.abs(got[0] - ref[0]).max() < 1e-4 * s["wind_sigma"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n_steps", [1, 12])
+def test_plant_step_time_correlated_wind_matches_oracle(lib, prec, n_steps):
+    """The plant under the paper's wind model flies sample 0's field of each
+    step (iteration word plant_iter): ten aircraft, random plans; states,
+    activation steps and events against the oracle's plant."""
+    import math
+    s = _ar1(synth.c2, prec, M=4, L=8, K=2, H=30, S=3, grid=(8, 8, 4))
+    ctx = lib.smc_mpc_init(s)
+    rng = np.random.default_rng(n_steps)
+    lo, hi = s["ctrl_lo"], s["ctrl_hi"]
+    ctrl = lo + rng.uniform(0.2, 0.8, (s["N"], s["S"], 3)) * (hi - lo)
+    from oracle import mpc as ompc
+    got = lib.smc_plant_step(ctx, ctrl, plant_iter=5, n_steps=n_steps, mpc_step=3)
+    ref = ompc.plant_step(s, ctrl, s["states"], s["k_active"], n_steps, plant_iter=5, mpc_step=3)
+    tol = 1e-10 if prec == "fp64" else 2e-5
+    assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
+    scale = np.array([1e5, 1e5, 1e4, 250.0, 2 * math.pi, 1e5])
+    assert (np.abs(got[0] - ref[0]) / scale).max() < tol
+
+
+def test_rolling_window_time_correlated_wind_matches_oracle(lib):
+    """Two receding-horizon updates of C1 in FP64 under the paper's wind
+    model, the plant flying sample 0's step fields: the oracle's controls,
+    plant states, activation steps and events."""
+    from oracle import mpc as ompc
+    s = _ar1(synth.c1, L=64, K=4)
+    got = lib.rolling_window(lib.smc_mpc_init(s), 2)
+    ref = ompc.rolling_window(s, 2)
+    for t, (g, r) in enumerate(zip(got, ref)):
+        assert np.abs(g["controls"] - r["controls"]).max() < 1e-6 * 250.0, t
+        assert np.array_equal(g["k_active"], r["k_active"]) and np.array_equal(g["event"], r["event"])
+        assert np.all(rel_err(g["states"], r["states"], floor=1.0) < 1e-8), t
