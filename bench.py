@@ -380,6 +380,80 @@ def compare_moves(args):
     print(json.dumps(out), flush=True)
 
 
+def compare_moves_batch(args):
+    """The same comparison in the batched form (C3: 64 scenarios in one
+    batched update): wall time per batched update for each move, the
+    acceptance rate of the Metropolis moves, and the summed expected cost
+    of the 64 returned control sequences, each re-scored by its own
+    scenario's smc_eval_cost on wind fields of an iteration word no run
+    draws.  Prints one JSON line."""
+    import numpy as np
+
+    import paper_1506_02869_amd as smc
+    import synth
+
+    iters = [int(k) for k in args.compare_iters.split(",")]
+    j_eval = 1 << 20
+    base = synth.c3()
+    # one scoring context per scenario (one particle each)
+    evals = [smc.smc_mpc_init(synth.shrink(sc, L=8, K=2)) for sc in base]
+    runs = {}
+    for move in ("rwmh", "mala", "jitter"):
+        runs[move] = []
+        for K in iters:
+            scens = synth.c3(move=move, K=K)
+            b = smc.smc_batch_init(scens)
+            smc.smc_batch_step(b, 0)                      # warm-up (graph capture off)
+            print(f"compare-moves (batched) {move} K={K}: warm-up done", file=sys.stderr,
+                  flush=True)
+            t0 = time.perf_counter()
+            ctrl, cost, status, _, info = smc.smc_batch_step(b, 0)
+            ms = (time.perf_counter() - t0) * 1e3
+            score, nfeas = 0.0, 0
+            for s, sc in enumerate(scens):
+                o = int(b.ctrl_off[s])
+                c_s = ctrl[o:o + sc["N"] * sc["S"] * 3].reshape(sc["N"], sc["S"], 3)
+                u = (c_s - sc["ctrl_lo"]) / (sc["ctrl_hi"] - sc["ctrl_lo"])
+                ec, ef = smc.smc_eval_cost(evals[s], u[None], j_eval)
+                score += float(ec.sum())
+                nfeas += int(np.all(ef))
+            runs[move].append({"K": K, "ms_per_update": round(ms, 1), "score": score,
+                               "feasible_scenarios": nfeas,
+                               "accept_rate": round(float(info.get("accept_rate", 0.0)), 6)})
+            print(f"compare-moves (batched) {move} K={K}: {ms:.1f} ms, score {score:.6f} "
+                  f"({nfeas} of {len(scens)} scenarios feasible, acceptance "
+                  f"{info.get('accept_rate', 0.0):.4f})", file=sys.stderr, flush=True)
+            b.close()
+    for e in evals:
+        e.close()
+    ref = runs["rwmh"][-1]["score"]
+    ref_feas = runs["rwmh"][-1]["feasible_scenarios"]
+    target = ref * (1.0 + 1e-3)
+
+    def reach(move):
+        # the summed cost within 1e-3 of the reference with at least as many
+        # scenarios feasible on the scoring fields
+        for r in runs[move]:
+            if r["feasible_scenarios"] >= ref_feas and r["score"] <= target:
+                return r
+        return None
+
+    out = {"metric": "wall time per batched MPC update to reach plain SMC's converged expected "
+                     "cost within 1e-3 relative", "workload": WORKLOADS["c3"][0],
+           "converged_cost": ref, "converged_from": f"rwmh, K={runs['rwmh'][-1]['K']}",
+           "scoring": f"sum over the 64 scenarios of smc_eval_cost on the wind fields of "
+                      f"iteration word {j_eval}",
+           "runs": runs}
+    rr = reach("rwmh")
+    for move in ("mala", "jitter"):
+        rm = reach(move)
+        out[f"{move}_reaches"] = rm
+        out[f"{move}_speedup_vs_rwmh"] = (None if rm is None or rr is None
+                                          else round(rr["ms_per_update"] / rm["ms_per_update"], 3))
+    out["rwmh_reaches"] = rr
+    print(json.dumps(out), flush=True)
+
+
 def rolling(args):
     """The receding-horizon loop (solve, apply the first control segment to
     the plant, move the window) for --rolling updates of the chosen workload,
@@ -428,7 +502,8 @@ def main():
     ap.add_argument("--move", choices=["jitter", "rwmh", "mala"], default=None,
                     help="batched workload: move of every scenario (default jitter)")
     ap.add_argument("--compare-moves", action="store_true",
-                    help="C4: time each move to reach plain SMC's converged cost")
+                    help="C4 (or C3 with --workload c3, the batched form): time each move to "
+                         "reach plain SMC's converged cost")
     ap.add_argument("--compare-iters", default="5,10,20,40,80,160")
     ap.add_argument("--rolling", type=int, default=0,
                     help="run this many receding-horizon updates (solve + plant) instead")
@@ -474,7 +549,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.compare_moves:
-        return compare_moves(args)
+        return compare_moves_batch(args) if key == "c3" else compare_moves(args)
     if args.rolling > 0:
         return rolling(args)
     if ar1 and key not in ("c1", "c2"):

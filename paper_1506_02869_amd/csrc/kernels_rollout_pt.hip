@@ -92,8 +92,10 @@ __device__ __forceinline__ void pt_aircraft(
     float cst;
     bool landed = false;
     if (!dep) {               // arrival (uniform)
-        const float ratio = tha > 1e-4f ? tha * O::rcp(maxr(O::sin(tha), 1e-6f))
-                                        : 1.f + tha * tha * (1.f / 6.f);
+        // both forms, then a select: no divergent branch
+        const float r_arc = tha * O::rcp(maxr(O::sin(tha), 1e-6f));
+        const float r_small = 1.f + tha * tha * (1.f / 6.f);
+        const float ratio = tha > 1e-4f ? r_arc : r_small;
         const float s_arc = r * ratio;
         const float beta = O::atan2_xpos(zn, s_arc);                 // s_arc >= 0
         landed = !wasdone & (r <= q.p_run) & (beta <= q.p_beta) & (tha <= q.p_chi) &
