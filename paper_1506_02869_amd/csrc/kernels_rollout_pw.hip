@@ -85,7 +85,8 @@ __device__ __forceinline__ void pw_aircraft(
     bool landed = false;
     if (!(flags & F_DEP)) {   // arrival (uniform)
         // both forms, then a select: no divergent branch
-        const float r_arc = tha * O::rcp(maxr(O::sin(tha), 1e-6f));
+        // sin|theta| = |y| / r: the ratio |theta| / sin|theta| without the sine
+        const float r_arc = tha * r * O::rcp(m_max(m_abs(yn), 1e-6f * r));
         const float r_small = 1.f + tha * tha * (1.f / 6.f);
         const float ratio = tha > 1e-4f ? r_arc : r_small;
         const float s_arc = r * ratio;

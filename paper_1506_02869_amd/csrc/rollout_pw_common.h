@@ -160,13 +160,13 @@ __device__ __forceinline__ float pw_phase1(const RolloutParams& p, const float* 
     const float sg = zdot * O::rcp(vj);
     const float cg = O::sqrt(1.f - sg * sg);
     const float tphi = vj * chidot * q.inv_g;
-    const float inv_cphi = O::sqrt(1.f + tphi * tphi);
     const float zc = clampr(zj, 0.f, 11000.f);
     const float rho = q.rho0 * O::pow_pos(1.f - q.isa_c * zc, q.isa_e);
     const float qS = 0.5f * rho * vj * vj * pj[A_SW];
     const float mass = pj[A_M0] - burnj;
-    const float CL = O::div(mass * q.g0 * inv_cphi, qS);
-    const float D = qS * (pj[A_CD0] + pj[A_CD2] * CL * CL);
+    // only C_L^2 = (m g / (q S))^2 (1 + tan^2 phi) enters the drag
+    const float wq = O::div(mass * q.g0, qS);
+    const float D = qS * (pj[A_CD0] + pj[A_CD2] * (wq * wq * (1.f + tphi * tphi)));
     const float dv = (vc - vj) * inv_rem;
     const float vn = vj + dv;
     const float T = mass * (dv * q.inv_dt + q.g0 * sg) + D;
