@@ -643,17 +643,20 @@ def bench_single(args, workload, steps, warmup, cpu=None, check_cost=True):
     # the rollout layout the library picks (world-per-lane up to 20 aircraft,
     # the particle tile above in FP32, aircraft-per-lane otherwise)
     layout = 2 if N <= 20 else (4 if not fp64 else 1)
+    # algorithmic work: the per-step operation list for every simulated
+    # aircraft-step and every pair of present aircraft, whatever the layout
+    # shares between the worlds of a particle
+    flops_launch = (as_per_launch * FLOPS_PER_AIRCRAFT_STEP
+                    + pt_per_launch * FLOPS_PER_PAIR_TEST)
+    split = None
     if layout in (3, 4):
-        # the wind-independent part of a step once per particle, the
-        # wind-dependent part per world; vertical pair tests once per
-        # particle, horizontal ones per world for pairs within sep_v
-        flops_launch = (as_per_launch * FLOPS_WIND_DEPENDENT
-                        + as_per_launch / scen["M"] * FLOPS_WIND_INDEPENDENT
-                        + pt_per_launch / scen["M"] * FLOPS_PAIR_VERTICAL
-                        + ph_per_launch * FLOPS_PAIR_HORIZONTAL)
-    else:
-        flops_launch = (as_per_launch * FLOPS_PER_AIRCRAFT_STEP
-                        + pt_per_launch * FLOPS_PER_PAIR_TEST)
+        # what these layouts compute: the wind-independent part of a step once
+        # per particle, the wind-dependent part per world; vertical pair tests
+        # once per particle, horizontal ones per world for pairs within sep_v
+        split = (as_per_launch * FLOPS_WIND_DEPENDENT
+                 + as_per_launch / scen["M"] * FLOPS_WIND_INDEPENDENT
+                 + pt_per_launch / scen["M"] * FLOPS_PAIR_VERTICAL
+                 + ph_per_launch * FLOPS_PAIR_HORIZONTAL)
     achieved = flops_launch / (ms_roll * 1e-3) / 1e12
     peak = PEAK_FP64_VECTOR_TFLOPS if fp64 else PEAK_FP32_VECTOR_TFLOPS
     world_lane = layout == 2
@@ -671,12 +674,10 @@ def bench_single(args, workload, steps, warmup, cpu=None, check_cost=True):
             "aircraft_steps_per_launch": int(as_per_launch),
             "pair_tests_per_launch": int(pt_per_launch),
             "horizontal_pair_tests_per_launch": int(ph_per_launch),
-            "flops_per_launch": flops_launch,
-            # the same launch priced at the whole per-step operation list for
-            # every world (170 per aircraft-step, 10 per pair test)
-            "survey_unit_tflops": round((as_per_launch * FLOPS_PER_AIRCRAFT_STEP
-                                         + pt_per_launch * FLOPS_PER_PAIR_TEST)
-                                        / (ms_roll * 1e-3) / 1e12, 3)}
+            "flops_per_launch": flops_launch}
+    if split is not None:
+        # the operations the layout executes (shared per particle), per second
+        roof["executed_split_tflops"] = round(split / (ms_roll * 1e-3) / 1e12, 3)
     G = int(np.prod(scen["grid"]))
     # triangular factor x 2M columns; under the time-correlated wind the
     # horizontal factor (nx ny rows) x 2 H M nz columns
