@@ -344,6 +344,42 @@ __device__ __forceinline__ void grad_reverse_step(const typename V2<R>::t* Wm,
     ax = nx_; ay = ny_; az = nz_; achi = nchi; av = nv; aB = nB;
 }
 
+// Segment checkpoints of a lane.  NSEG bounds the segment count of the
+// horizon, (H + GR_CK - 1) / GR_CK.  With REG, every access names its slot
+// at compile time (unrolled selects over the slots; the segment index j is
+// the same for every lane of a wave), so the array stays in registers
+// instead of scratch memory: worth its 6 NSEG registers for short horizons
+// in FP32.  Otherwise the slot is indexed directly (scratch memory).
+template <typename R, int NSEG, bool REG>
+__device__ __forceinline__ void ck_put(R (&ck)[NSEG][6], int j, R x, R y, R z, R v, R chi, R B) {
+    if constexpr (!REG) {
+        ck[j][0] = x; ck[j][1] = y; ck[j][2] = z; ck[j][3] = v; ck[j][4] = chi; ck[j][5] = B;
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < NSEG; ++q) {   // selects, not branches: no store is merged into ck[j]
+        const bool h = q == j;
+        ck[q][0] = h ? x : ck[q][0]; ck[q][1] = h ? y : ck[q][1]; ck[q][2] = h ? z : ck[q][2];
+        ck[q][3] = h ? v : ck[q][3]; ck[q][4] = h ? chi : ck[q][4]; ck[q][5] = h ? B : ck[q][5];
+    }
+}
+
+template <typename R, int NSEG, bool REG>
+__device__ __forceinline__ void ck_get(const R (&ck)[NSEG][6], int j, R& x, R& y, R& z, R& v,
+                                       R& chi, R& B) {
+    if constexpr (!REG) {
+        x = ck[j][0]; y = ck[j][1]; z = ck[j][2]; v = ck[j][3]; chi = ck[j][4]; B = ck[j][5];
+        return;
+    }
+    x = ck[0][0]; y = ck[0][1]; z = ck[0][2]; v = ck[0][3]; chi = ck[0][4]; B = ck[0][5];
+#pragma unroll
+    for (int q = 1; q < NSEG; ++q) {
+        const bool h = q == j;
+        x = h ? ck[q][0] : x; y = h ? ck[q][1] : y; z = h ? ck[q][2] : z;
+        v = h ? ck[q][3] : v; chi = h ? ck[q][4] : chi; B = h ? ck[q][5] : B;
+    }
+}
+
 // Adjoint of the fuel + time cost of one (particle, aircraft, wind sample)
 // per lane.  The step loops run over absolute steps, the same for every lane
 // of a wave (a lane takes part in the steps k0 <= k <= its last step), so the
@@ -351,7 +387,7 @@ __device__ __forceinline__ void grad_reverse_step(const typename V2<R>::t* Wm,
 // indexed by a wave-uniform step: it stays in registers.  A control
 // segment's gradient is summed over its steps in three registers and reduced
 // over the wind samples when the reverse sweep leaves the segment.
-template <typename R>
+template <typename R, int NSEG, bool REG>
 __global__ void __launch_bounds__(GR_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_rollout_grad(const GradParams gp, const R* __restrict__ u,
                                                       const R* __restrict__ W,
                                                       const double* __restrict__ states,
@@ -385,7 +421,7 @@ __global__ void __launch_bounds__(GR_BLOCK) __attribute__((amdgpu_waves_per_eu(2
     const double sp[3] = {p.ctrl_span[0], p.ctrl_span[1], p.ctrl_span[2]};
 
     // forward sweep: checkpoints at every GR_CK-th step and the landing step
-    R ck[GR_MAXSEG][6];
+    R ck[NSEG][6];
     R x = (R)states[i * 6 + 0], y = (R)states[i * 6 + 1], z = (R)states[i * 6 + 2];
     R v = (R)states[i * 6 + 3], chi = (R)states[i * 6 + 4], B = (R)0;
     int k_land = H;   // step whose new state lands (H: none)
@@ -393,10 +429,7 @@ __global__ void __launch_bounds__(GR_BLOCK) __attribute__((amdgpu_waves_per_eu(2
     int s_cur = -1, k_end = 0;
     R cd = 0, vc = 0, zd = 0;
     for (int k = 0; k < H; ++k) {
-        if ((k % GR_CK) == 0) {
-            R* c = ck[k / GR_CK];
-            c[0] = x; c[1] = y; c[2] = z; c[3] = v; c[4] = chi; c[5] = B;
-        }
+        if ((k % GR_CK) == 0) ck_put<R, NSEG, REG>(ck, k / GR_CK, x, y, z, v, chi, B);
         const int s = (k * S) / H;
         if (s != s_cur) {   // wave-uniform
             s_cur = s;
@@ -431,8 +464,8 @@ __global__ void __launch_bounds__(GR_BLOCK) __attribute__((amdgpu_waves_per_eu(2
         const int ka = j * GR_CK;
         const int kb = min(H, ka + GR_CK) - 1;
         {   // inner checkpoints: the state at the start of each block
-            R x1 = ck[j][0], y1 = ck[j][1], z1 = ck[j][2], v1 = ck[j][3], chi1 = ck[j][4],
-              B1 = ck[j][5];
+            R x1, y1, z1, v1, chi1, B1;
+            ck_get<R, NSEG, REG>(ck, j, x1, y1, z1, v1, chi1, B1);
             for (int k = ka; k <= kb; ++k) {
                 if (((k - ka) % GR_IN) == 0) {
                     R* c = &ick[(k - ka) / GR_IN][0][tl];
@@ -581,14 +614,18 @@ hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u,
     const int64_t lanes = (int64_t)rp.P * rp.N * gp.Mp;
     const unsigned blocks = (unsigned)((lanes + GR_BLOCK - 1) / GR_BLOCK);
     double* dst = gp.chunks > 1 ? partial : grad_out;
-    if (prec == 0)
-        hipLaunchKernelGGL(k_rollout_grad<double>, dim3(blocks), dim3(GR_BLOCK), 0, st, gp,
-                           (const double*)u, (const double*)Wt, states, k_active, acpar, targets,
-                           kind, dst);
-    else
-        hipLaunchKernelGGL(k_rollout_grad<float>, dim3(blocks), dim3(GR_BLOCK), 0, st, gp,
-                           (const float*)u, (const float*)Wt, states, k_active, acpar, targets,
-                           kind, dst);
+    const int nseg = (rp.H + GR_CK - 1) / GR_CK;
+    if (prec == 0) {
+        hipLaunchKernelGGL((k_rollout_grad<double, GR_MAXSEG, false>), dim3(blocks),
+                           dim3(GR_BLOCK), 0, st, gp, (const double*)u, (const double*)Wt, states,
+                           k_active, acpar, targets, kind, dst);
+    } else {
+        // register checkpoints up to 6 segments (150 steps): 166 VGPRs, still
+        // three waves per SIMD; longer horizons keep them in scratch memory
+        auto k = nseg <= 6 ? k_rollout_grad<float, 6, true> : k_rollout_grad<float, GR_MAXSEG, false>;
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(GR_BLOCK), 0, st, gp, (const float*)u,
+                           (const float*)Wt, states, k_active, acpar, targets, kind, dst);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || gp.chunks == 1) return e;
     const int64_t n = (int64_t)rp.P * rp.N * rp.S * 3;

@@ -29,15 +29,19 @@ def _grad_case(lib, prec, M=3, P=7, H=40, S=4, seed=0):
     return host(g), ref * M
 
 
-@pytest.mark.parametrize("M", [3, 16, 80])
-def test_adjoint_fp64_matches_reference(lib, M):
-    got, ref = _grad_case(lib, "fp64", M=M, P=5 if M == 80 else 7)
+@pytest.mark.parametrize("M,H", [(3, 40), (16, 40), (80, 40), (64, 150)])
+def test_adjoint_fp64_matches_reference(lib, M, H):
+    got, ref = _grad_case(lib, "fp64", M=M, P=5 if M == 80 else 7, H=H,
+                          S=6 if H > 100 else 4)
     scale = np.abs(ref).max()
     assert np.abs(got - ref).max() <= 1e-9 * scale
 
 
-def test_adjoint_fp32_matches_reference(lib):
-    got, ref = _grad_case(lib, "fp32", M=8)
+# (M, H, S): segment checkpoints in registers up to 6 segments (H <= 150),
+# in scratch memory beyond; one wave per (particle, aircraft) at M = 64
+@pytest.mark.parametrize("M,H,S", [(8, 40, 4), (64, 150, 6), (5, 180, 6)])
+def test_adjoint_fp32_matches_reference(lib, M, H, S):
+    got, ref = _grad_case(lib, "fp32", M=M, H=H, S=S)
     scale = np.abs(ref).max()
     err = np.abs(got - ref)
     assert err.max() <= 2e-3 * scale
