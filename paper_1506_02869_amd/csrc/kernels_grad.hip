@@ -38,55 +38,101 @@ struct StepFwd {     // intermediates of one step, recomputed in the reverse swe
     R sc, cc;
 };
 
-// Trilinear wind and its derivative with respect to (x, y, z) (zero along a
-// clamped coordinate).  Wm points at the lane's sample in the sample-
-// interleaved field Wt[g][m] (row stride M), so the lanes of a wave, which
-// hold the samples of one (particle, aircraft), read adjacent elements
-// wherever their positions share a grid cell.
+// The wind's grid cell at (x, y, z): clamped coordinates, the interpolation
+// weights, the derivative of each grid coordinate (zero along a clamped
+// one) and the eight corners c[4 dx + 2 dy + dz] of the lane's sample.
 template <typename R>
-__device__ __forceinline__ void wind_and_grad(const typename V2<R>::t* Wm, const RolloutParams& p,
-                                              R x, R y, R z, StepFwd<R>& o) {
-    typedef typename V2<R>::t R2;
+struct WindCell {
+    typename V2<R>::t c[8];
+    R tx, ty, tz, jx, jy, jz;
+};
+
+// Cell index ((ix ny + iy) nz + iz) and weights of (x, y, z).  With NARROW
+// the index arithmetic is 24-bit (grids below 2^24 cells).
+template <typename R, bool NARROW = false>
+__device__ __forceinline__ int wind_locate(const RolloutParams& p, R x, R y, R z, WindCell<R>& w) {
     const R ux = (x + (R)p.half_wx) * (R)p.inv_hx;
     const R uy = (y + (R)p.half_wy) * (R)p.inv_hy;
     const R uz = z * (R)p.inv_hz;
     const R fx = clampr(ux, (R)0, (R)(p.nx - 1));
     const R fy = clampr(uy, (R)0, (R)(p.ny - 1));
     const R fz = clampr(uz, (R)0, (R)(p.nz - 1));
-    const R jx = (ux >= (R)0 && ux <= (R)(p.nx - 1)) ? (R)p.inv_hx : (R)0;
-    const R jy = (uy >= (R)0 && uy <= (R)(p.ny - 1)) ? (R)p.inv_hy : (R)0;
-    const R jz = (uz >= (R)0 && uz <= (R)(p.nz - 1)) ? (R)p.inv_hz : (R)0;
+    w.jx = (ux >= (R)0 && ux <= (R)(p.nx - 1)) ? (R)p.inv_hx : (R)0;
+    w.jy = (uy >= (R)0 && uy <= (R)(p.ny - 1)) ? (R)p.inv_hy : (R)0;
+    w.jz = (uz >= (R)0 && uz <= (R)(p.nz - 1)) ? (R)p.inv_hz : (R)0;
     const int ix = min((int)fx, p.nx - 2), iy = min((int)fy, p.ny - 2), iz = min((int)fz, p.nz - 2);
-    const R tx = fx - (R)ix, ty = fy - (R)iy, tz = fz - (R)iz;
+    w.tx = fx - (R)ix; w.ty = fy - (R)iy; w.tz = fz - (R)iz;
+    if constexpr (NARROW)
+        return (int)(__umul24(__umul24((unsigned)ix, (unsigned)p.ny) + (unsigned)iy, (unsigned)p.nz) +
+                     (unsigned)iz);
+    return (ix * p.ny + iy) * p.nz + iz;
+}
+
+// Corners of cell g from the sample-interleaved field Wt[g][m] (row stride
+// M); Wm points at the lane's sample, so the lanes of a wave, which hold the
+// samples of one (particle, aircraft), read adjacent elements wherever their
+// positions share a cell.
+template <typename R, bool NARROW = false>
+__device__ __forceinline__ void wind_corners(const typename V2<R>::t* Wm, const RolloutParams& p,
+                                             int g, WindCell<R>& w) {
+    typedef typename V2<R>::t R2;
     const int M = p.M, nzz = p.nz * M, nyz = p.ny * p.nz * M;
-    const R2* Wg = Wm + (int64_t)((ix * p.ny + iy) * p.nz + iz) * M;
-    const R2 c000 = Wg[0], c001 = Wg[M], c010 = Wg[nzz], c011 = Wg[nzz + M];
-    const R2 c100 = Wg[nyz], c101 = Wg[nyz + M], c110 = Wg[nyz + nzz], c111 = Wg[nyz + nzz + M];
-    // component x
+    // NARROW: g < 2^24 and M < 2^24, a 24-bit multiply
+    const R2* Wg = Wm + (NARROW ? (int64_t)__umul24((unsigned)g, (unsigned)M) : (int64_t)g * M);
+    w.c[0] = Wg[0]; w.c[1] = Wg[M]; w.c[2] = Wg[nzz]; w.c[3] = Wg[nzz + M];
+    w.c[4] = Wg[nyz]; w.c[5] = Wg[nyz + M]; w.c[6] = Wg[nyz + nzz]; w.c[7] = Wg[nyz + nzz + M];
+}
+
+// Trilinear wind value.
+template <typename R>
+__device__ __forceinline__ void wind_interp(const WindCell<R>& w, R& wx, R& wy) {
+    const R tx = w.tx, ty = w.ty, tz = w.tz;
     {
-        const R a00 = c000.x + tz * (c001.x - c000.x), a01 = c010.x + tz * (c011.x - c010.x);
-        const R a10 = c100.x + tz * (c101.x - c100.x), a11 = c110.x + tz * (c111.x - c110.x);
+        const R a00 = w.c[0].x + tz * (w.c[1].x - w.c[0].x), a01 = w.c[2].x + tz * (w.c[3].x - w.c[2].x);
+        const R a10 = w.c[4].x + tz * (w.c[5].x - w.c[4].x), a11 = w.c[6].x + tz * (w.c[7].x - w.c[6].x);
         const R b0 = a00 + ty * (a01 - a00), b1 = a10 + ty * (a11 - a10);
-        o.wx = b0 + tx * (b1 - b0);
-        const R d_tx = b1 - b0;
-        const R d_ty = ((R)1 - tx) * (a01 - a00) + tx * (a11 - a10);
-        const R dz0 = ((R)1 - ty) * (c001.x - c000.x) + ty * (c011.x - c010.x);
-        const R dz1 = ((R)1 - ty) * (c101.x - c100.x) + ty * (c111.x - c110.x);
-        const R d_tz = ((R)1 - tx) * dz0 + tx * dz1;
-        o.dwx[0] = d_tx * jx; o.dwx[1] = d_ty * jy; o.dwx[2] = d_tz * jz;
+        wx = b0 + tx * (b1 - b0);
     }
     {
-        const R a00 = c000.y + tz * (c001.y - c000.y), a01 = c010.y + tz * (c011.y - c010.y);
-        const R a10 = c100.y + tz * (c101.y - c100.y), a11 = c110.y + tz * (c111.y - c110.y);
+        const R a00 = w.c[0].y + tz * (w.c[1].y - w.c[0].y), a01 = w.c[2].y + tz * (w.c[3].y - w.c[2].y);
+        const R a10 = w.c[4].y + tz * (w.c[5].y - w.c[4].y), a11 = w.c[6].y + tz * (w.c[7].y - w.c[6].y);
         const R b0 = a00 + ty * (a01 - a00), b1 = a10 + ty * (a11 - a10);
-        o.wy = b0 + tx * (b1 - b0);
+        wy = b0 + tx * (b1 - b0);
+    }
+}
+
+// Trilinear wind and its derivative with respect to (x, y, z), by the same
+// expressions for the value.
+template <typename R>
+__device__ __forceinline__ void wind_interp_grad(const WindCell<R>& w, StepFwd<R>& o) {
+    const R tx = w.tx, ty = w.ty, tz = w.tz;
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        R c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = comp == 0 ? w.c[q].x : w.c[q].y;
+        const R a00 = c[0] + tz * (c[1] - c[0]), a01 = c[2] + tz * (c[3] - c[2]);
+        const R a10 = c[4] + tz * (c[5] - c[4]), a11 = c[6] + tz * (c[7] - c[6]);
+        const R b0 = a00 + ty * (a01 - a00), b1 = a10 + ty * (a11 - a10);
+        const R val = b0 + tx * (b1 - b0);
         const R d_tx = b1 - b0;
         const R d_ty = ((R)1 - tx) * (a01 - a00) + tx * (a11 - a10);
-        const R dz0 = ((R)1 - ty) * (c001.y - c000.y) + ty * (c011.y - c010.y);
-        const R dz1 = ((R)1 - ty) * (c101.y - c100.y) + ty * (c111.y - c110.y);
+        const R dz0 = ((R)1 - ty) * (c[1] - c[0]) + ty * (c[3] - c[2]);
+        const R dz1 = ((R)1 - ty) * (c[5] - c[4]) + ty * (c[7] - c[6]);
         const R d_tz = ((R)1 - tx) * dz0 + tx * dz1;
-        o.dwy[0] = d_tx * jx; o.dwy[1] = d_ty * jy; o.dwy[2] = d_tz * jz;
+        R* d = comp == 0 ? o.dwx : o.dwy;
+        (comp == 0 ? o.wx : o.wy) = val;
+        d[0] = d_tx * w.jx; d[1] = d_ty * w.jy; d[2] = d_tz * w.jz;
     }
+}
+
+template <typename R, bool NARROW = false>
+__device__ __forceinline__ void wind_and_grad(const typename V2<R>::t* Wm, const RolloutParams& p,
+                                              R x, R y, R z, StepFwd<R>& o) {
+    WindCell<R> w;
+    const int g = wind_locate<R, NARROW>(p, x, y, z, w);
+    wind_corners<R, NARROW>(Wm, p, g, w);
+    wind_interp_grad<R>(w, o);
 }
 
 struct AcConst {
@@ -94,37 +140,13 @@ struct AcConst {
     bool arr;
 };
 
-// Trilinear wind value only, by the same expressions as wind_and_grad, so
-// the light steps of the forward sweep and of the recomputation produce the
-// same states as the full step of the reverse sweep.
-template <typename R>
+template <typename R, bool NARROW = false>
 __device__ __forceinline__ void wind_value(const typename V2<R>::t* Wm, const RolloutParams& p,
                                            R x, R y, R z, R& wx, R& wy) {
-    typedef typename V2<R>::t R2;
-    const R ux = (x + (R)p.half_wx) * (R)p.inv_hx;
-    const R uy = (y + (R)p.half_wy) * (R)p.inv_hy;
-    const R uz = z * (R)p.inv_hz;
-    const R fx = clampr(ux, (R)0, (R)(p.nx - 1));
-    const R fy = clampr(uy, (R)0, (R)(p.ny - 1));
-    const R fz = clampr(uz, (R)0, (R)(p.nz - 1));
-    const int ix = min((int)fx, p.nx - 2), iy = min((int)fy, p.ny - 2), iz = min((int)fz, p.nz - 2);
-    const R tx = fx - (R)ix, ty = fy - (R)iy, tz = fz - (R)iz;
-    const int M = p.M, nzz = p.nz * M, nyz = p.ny * p.nz * M;
-    const R2* Wg = Wm + (int64_t)((ix * p.ny + iy) * p.nz + iz) * M;
-    const R2 c000 = Wg[0], c001 = Wg[M], c010 = Wg[nzz], c011 = Wg[nzz + M];
-    const R2 c100 = Wg[nyz], c101 = Wg[nyz + M], c110 = Wg[nyz + nzz], c111 = Wg[nyz + nzz + M];
-    {
-        const R a00 = c000.x + tz * (c001.x - c000.x), a01 = c010.x + tz * (c011.x - c010.x);
-        const R a10 = c100.x + tz * (c101.x - c100.x), a11 = c110.x + tz * (c111.x - c110.x);
-        const R b0 = a00 + ty * (a01 - a00), b1 = a10 + ty * (a11 - a10);
-        wx = b0 + tx * (b1 - b0);
-    }
-    {
-        const R a00 = c000.y + tz * (c001.y - c000.y), a01 = c010.y + tz * (c011.y - c010.y);
-        const R a10 = c100.y + tz * (c101.y - c100.y), a11 = c110.y + tz * (c111.y - c110.y);
-        const R b0 = a00 + ty * (a01 - a00), b1 = a10 + ty * (a11 - a10);
-        wy = b0 + tx * (b1 - b0);
-    }
+    WindCell<R> w;
+    const int g = wind_locate<R, NARROW>(p, x, y, z, w);
+    wind_corners<R, NARROW>(Wm, p, g, w);
+    wind_interp<R>(w, wx, wy);
 }
 
 // Climb, bank, density, drag, thrust and fuel of one step (the rollout's
@@ -200,13 +222,14 @@ __device__ __forceinline__ R time_elem(const RolloutParams& p, const AcConst& ac
         const R th = O::atan2(y, x);
         const R tha = m_abs(th);
         const R sgn = th < (R)0 ? (R)-1 : (R)1;
+        const R ir = r > (R)0 ? O::rcp(r) : (R)0;
         R ratio, dratio;
         if (tha > (R)1e-4) {
-            const R s = O::sin(tha);
+            // tha = |atan2(y, x)| in [0, pi]: sin(tha) = |y| / r, cos(tha) = x / r
+            const R s = m_abs(y) * ir;
             if (s > (R)1e-6) {
                 ratio = tha * O::rcp(s);
-                R c, sdummy;
-                O::sincos(tha, &sdummy, &c);
+                const R c = x * ir;
                 dratio = (s - tha * c) * O::rcp(s * s);
             } else {
                 ratio = tha * (R)1e6;
@@ -217,7 +240,6 @@ __device__ __forceinline__ R time_elem(const RolloutParams& p, const AcConst& ac
             dratio = tha * (R)(1.0 / 3.0);
         }
         num = r * ratio;
-        const R ir = r > (R)0 ? O::rcp(r) : (R)0;
         const R ir2 = ir * ir;
         // d theta / dx = -y / r^2, d theta / dy = x / r^2
         dn_dx = x * ir * ratio + r * dratio * sgn * (-y * ir2);
@@ -535,6 +557,332 @@ __global__ void __launch_bounds__(GR_BLOCK) __attribute__((amdgpu_waves_per_eu(2
     flush_segment<R>(gp, s_grad, gc, sp, m, grp, ngrp, l, i, out);
 }
 
+// ---- Adjoint with the sample-independent chain hoisted ----------------------------
+//
+// Of an aircraft's state only (x, y) depend on the wind sample: heading,
+// speed, altitude and burn follow from the controls alone (eq. hor), and a
+// sample's landing only ends that sample's steps.  So for 33 ... 64 samples
+// one wave takes one (particle, aircraft): it computes that chain and every
+// step's reverse coefficients once, into an LDS record per step, and each
+// lane then carries only its sample's (x, y) forward and the adjoint
+// backward.  The adjoint of (z, v, chi, burn) stays per lane (it depends on
+// the sample through the wind's altitude derivative and the landing step);
+// its update is linear with the record's coefficients.  The step arithmetic
+// is k_rollout_grad's (up to the order of some products).
+//
+// Per lane: a forward pass over (x, y) keeps a checkpoint every GS_CK steps
+// and finds the landing step; then, block by block from the last, a pass
+// from the block's checkpoint keeps (x, y) and the wind's spatial derivative
+// at every step in registers, and the backward sweep over the block reads
+// no field.  The field is the bound (every load comes from L2), so a lane
+// fetches its cell's eight corners only when it enters another cell, which
+// at these grid spacings holds several consecutive steps.
+//
+// Record of step k (reals), in its final form:
+//   z_k, v cos(chi) cos(gamma), chi_k, v_{k+1}, 1 / (steps to the segment's
+//   end), dt cos(chi) / cos(gamma), dt sin(chi) / cos(gamma), -sin(gamma),
+//   d burn / d (z, v, mass, chi rate, commanded v, climb rate),
+//   v sin(chi) cos(gamma)
+// (record H holds the final z and chi).  While it is built, slots 0-2 hold
+// z, v, chi (sequential pass), 3-7 the burn's step inputs (step-parallel
+// pass) and 8-10 burn, lift coefficient and thrust (sequential burn pass);
+// each pass writes only its own steps' records.
+constexpr int GS_CK = 8;      // (x, y) checkpoint interval [steps]
+constexpr int GS_REC = 16;    // reals per step record
+constexpr int GS_MAXH = 160;  // horizons of the hoisted form (16 checkpoints)
+enum {
+    RS_Z = 0, RS_A, RS_CHI, RS_VN, RS_IR, RS_C1, RS_C2, RS_C3,
+    RS_DFZ, RS_DFV, RS_DFM, RS_DFCD, RS_DFVC, RS_DFZD, RS_B
+};
+
+template <typename R, int NSEG>
+__device__ __forceinline__ void ck2_put(R (&cx)[NSEG], R (&cy)[NSEG], int j, R x, R y) {
+#pragma unroll
+    for (int q = 0; q < NSEG; ++q) {   // selects: every slot named at compile time
+        const bool h = q == j;
+        cx[q] = h ? x : cx[q];
+        cy[q] = h ? y : cy[q];
+    }
+}
+
+template <typename R, int NSEG>
+__device__ __forceinline__ void ck2_get(const R (&cx)[NSEG], const R (&cy)[NSEG], int j, R& x,
+                                        R& y) {
+    x = cx[0]; y = cy[0];
+#pragma unroll
+    for (int q = 1; q < NSEG; ++q) {
+        const bool h = q == j;
+        x = h ? cx[q] : x;
+        y = h ? cy[q] : y;
+    }
+}
+
+// (FP32: held to 168 registers, three waves per SIMD; one value spills,
+// outside the step loops)
+template <typename R>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1)))
+k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __restrict__ W,
+                     const double* __restrict__ states, const int32_t* __restrict__ k_active,
+                     const double* __restrict__ acpar, const double* __restrict__ targets,
+                     const int8_t* __restrict__ kind, double* __restrict__ out) {
+    typedef typename V2<R>::t R2;
+    typedef Ops<R> O;
+    constexpr int NSEG = (GS_MAXH + GS_CK - 1) / GS_CK;
+    extern __shared__ __align__(16) unsigned char gs_smem[];
+    R* rec = (R*)gs_smem;    // [H + 1][GS_REC]
+    const RolloutParams& p = gp.rp;
+    const int N = p.N, S = p.S, H = p.H, M = p.M;
+    const int lane = threadIdx.x;
+    const int64_t grp = blockIdx.x;   // (l, i), one wave
+    const int l = (int)(grp / N), i = (int)(grp % N);
+    const bool valid = lane < M;
+
+    AcConst ac;
+    ac.Sw = acpar[i * 9 + 0]; ac.cd0 = acpar[i * 9 + 1]; ac.cd2 = acpar[i * 9 + 2];
+    ac.cf1 = acpar[i * 9 + 3]; ac.cf2 = acpar[i * 9 + 4]; ac.tmax = acpar[i * 9 + 5];
+    ac.dtma = targets[i * 4 + 3]; ac.m0 = states[i * 6 + 5];
+    ac.arr = kind[i] == 0;
+    const int k0 = k_active[i];
+    const bool gact = k0 >= 0 && k0 < H;   // the same for the whole wave
+    const bool active = valid && gact;
+    const R2* Wm = (const R2*)W + (valid ? lane : 0);   // sample-interleaved Wt[g][m]
+    const R* ub = u + ((int64_t)l * N + i) * S * 3;
+    const double lo[3] = {p.ctrl_lo[0], p.ctrl_lo[1], p.ctrl_lo[2]};
+    const double sp[3] = {p.ctrl_span[0], p.ctrl_span[1], p.ctrl_span[2]};
+    const R dt = (R)p.dt;
+
+    if (gact) {
+        // (1) sequential: z, v, chi at every step from k0
+        {
+            R z = (R)states[i * 6 + 2], v = (R)states[i * 6 + 3], chi = (R)states[i * 6 + 4];
+            int s_cur = -1, k_end = 0;
+            R cd = 0, vc = 0, zd = 0;
+            for (int k = k0; k < H; ++k) {
+                const int s = (k * S) / H;
+                if (s != s_cur) {
+                    s_cur = s;
+                    k_end = ((s + 1) * H + S - 1) / S;
+                    seg_controls<R>(ub, s, lo, sp, cd, vc, zd);
+                }
+                if (lane == 0) {
+                    R* r = rec + k * GS_REC;
+                    r[0] = z; r[1] = v; r[2] = chi;
+                }
+                const R sg = zd * O::rcp(v);   // as step_core / step_state
+                z = z + dt * (v * sg);
+                chi = chi + dt * cd;
+                v = v + (vc - v) * O::rcp((R)(k_end - k));
+            }
+            if (lane == 0) {
+                R* r = rec + H * GS_REC;
+                r[0] = z; r[1] = v; r[2] = chi;
+            }
+        }
+        __syncthreads();
+        // (2) step-parallel: the burn's inputs that do not depend on the mass
+        for (int k = k0 + lane; k < H; k += 64) {
+            R* r = rec + k * GS_REC;
+            const R z = r[0], v = r[1], chi = r[2];
+            const int s = (k * S) / H;
+            const int k_end = ((s + 1) * H + S - 1) / S;
+            R cd, vc, zd;
+            seg_controls<R>(ub, s, lo, sp, cd, vc, zd);
+            StepFwd<R> o;
+            step_core<R>(p, ac, z, v, chi, (R)0, cd, vc, zd, O::rcp((R)(k_end - k)), o);
+            r[3] = o.icphi; r[4] = o.qd * (R)ac.Sw; r[5] = o.vn - v; r[6] = o.sg;
+            r[7] = (R)p.dt * o.eta;
+        }
+        __syncthreads();
+        // (3) sequential: the burn, by step_core's expressions
+        {
+            const R g0 = (R)kG0, inv_dt = (R)(1.0 / p.dt);
+            R B = 0;
+#pragma unroll 4
+            for (int k = k0; k < H; ++k) {   // (unrolled: the record reads run ahead of the chain)
+                R* r = rec + k * GS_REC;
+                const R icphi = r[3], A0 = r[4], dv = r[5], sg = r[6], dteta = r[7];
+                const R mass = (R)ac.m0 - B;
+                const R CL = O::div(mass * g0 * icphi, A0);
+                const R D = A0 * ((R)ac.cd0 + (R)ac.cd2 * CL * CL);
+                const R T = mass * dv * inv_dt + D + mass * g0 * sg;
+                if (lane == 0) { r[8] = B; r[9] = CL; r[10] = T; }
+                B = B + dteta * m_max(T, (R)0);
+            }
+        }
+        __syncthreads();
+        // (4) step-parallel: the record (reverse coefficients)
+        for (int k = k0 + lane; k < H; k += 64) {
+            R* r = rec + k * GS_REC;
+            const R z = r[0], v = r[1], chi = r[2], B = r[8], CL = r[9], T = r[10];
+            const int s = (k * S) / H;
+            const int k_end = ((s + 1) * H + S - 1) / S;
+            R cd, vc, zd;
+            seg_controls<R>(ub, s, lo, sp, cd, vc, zd);
+            const R ir = O::rcp((R)(k_end - k));
+            StepFwd<R> o;
+            step_core<R>(p, ac, z, v, chi, B, cd, vc, zd, ir, o);
+            o.CL = CL; o.T = T;
+            const R isa_c = (R)(kLapse / kT0), isa_e = (R)(kG0 / (kRair * kLapse) - 1.0);
+            const bool zin = z > (R)0 && z < (R)11000;
+            const R base = (R)1 - isa_c * clampr(z, (R)0, (R)11000);
+            const R drho_dz = zin ? -o.rho * isa_e * isa_c * O::rcp(base) : (R)0;
+            R df_dv = 0, df_dvc = 0, df_dzd = 0, df_dcd = 0, df_dz = 0, df_dm = 0;
+            if (o.T > (R)0) {   // as grad_reverse_step
+                const R g0 = (R)kG0;
+                const R A0 = o.qd * (R)ac.Sw;
+                const R dD_dA0 = (R)ac.cd0 - (R)ac.cd2 * o.CL * o.CL;
+                const R dD_dK = (R)2 * (R)ac.cd2 * o.CL;
+                const R inv_dt = (R)(1.0 / p.dt);
+                const R dT_dv = -o.mass * ir * inv_dt + dD_dA0 * ((R)2 * A0 * O::rcp(v)) +
+                                dD_dK * o.mass * g0 * (o.tphi * O::rcp(o.icphi)) * (cd * (R)(1.0 / kG0)) -
+                                o.mass * g0 * o.sg * O::rcp(v);
+                const R dT_dvc = o.mass * ir * inv_dt;
+                const R dT_dzd = o.mass * g0 * O::rcp(v);
+                const R dT_dcd = dD_dK * o.mass * g0 * (o.tphi * O::rcp(o.icphi)) * (v * (R)(1.0 / kG0));
+                const R dT_dz = dD_dA0 * (A0 * O::rcp(o.rho)) * drho_dz;
+                const R dT_dm = (o.vn - v) * inv_dt + dD_dK * g0 * o.icphi + g0 * o.sg;
+                const R dt_eta = dt * o.eta;
+                df_dv = dt * (R)(ac.cf1 / ac.cf2) * o.T + dt_eta * dT_dv;
+                df_dvc = dt_eta * dT_dvc;
+                df_dzd = dt_eta * dT_dzd;
+                df_dcd = dt_eta * dT_dcd;
+                df_dz = dt_eta * dT_dz;
+                df_dm = dt_eta * dT_dm;
+            }
+            const R icg = O::rcp(o.cg);
+            const R a = v * o.cc * o.cg, b = v * o.sc * o.cg;
+            r[RS_Z] = z; r[RS_A] = a; r[RS_CHI] = chi; r[RS_VN] = o.vn; r[RS_IR] = ir;
+            r[RS_C1] = dt * o.cc * icg; r[RS_C2] = dt * o.sc * icg; r[RS_C3] = -o.sg;
+            r[RS_DFZ] = df_dz; r[RS_DFV] = df_dv; r[RS_DFM] = df_dm; r[RS_DFCD] = df_dcd;
+            r[RS_DFVC] = df_dvc; r[RS_DFZD] = df_dzd; r[RS_B] = b;
+        }
+        __syncthreads();
+    }
+
+    // forward over the sample's (x, y): checkpoints every GS_CK steps, landing step
+    R ckx[NSEG], cky[NSEG];
+#pragma unroll
+    for (int q = 0; q < NSEG; ++q) { ckx[q] = (R)0; cky[q] = (R)0; }
+    R x = (R)states[i * 6 + 0], y = (R)states[i * 6 + 1];
+    int k_land = H;
+    bool flying = active;
+    // the next step's record is read one step ahead (records before k0 are
+    // read but not used; record H exists)
+    R pz = rec[RS_Z], pa = rec[RS_A], pb = rec[RS_B];
+    // a lane fetches its cell's corners only when it enters another cell
+    // (a cell spans several steps); lanes that stay fetch nothing
+    WindCell<R> wc;
+    int gprev = -1;
+    for (int k = 0; k < H; ++k) {
+        const R rz = pz, ra = pa, rb = pb;
+        {
+            const R* rn = rec + (k + 1) * GS_REC;
+            pz = rn[RS_Z]; pa = rn[RS_A]; pb = rn[RS_B];
+        }
+        if ((k % GS_CK) == 0) ck2_put<R, NSEG>(ckx, cky, k / GS_CK, x, y);
+        if (flying && k >= k0) {
+            const R* r = rec + k * GS_REC;
+            const int g = wind_locate<R, true>(p, x, y, rz, wc);
+            if (g != gprev) {
+                wind_corners<R, true>(Wm, p, g, wc);
+                gprev = g;
+            }
+            R wx, wy;
+            wind_interp<R>(wc, wx, wy);
+            x = x + dt * (ra + wx);
+            y = y + dt * (rb + wy);
+            if (ac.arr && landed_at<R>(p, x, y, pz, r[RS_VN], r[GS_REC + RS_CHI])) {
+                k_land = k;
+                flying = false;
+            }
+        }
+    }
+
+    // reverse, block by block of GS_CK steps from the last: the block's (x, y)
+    // tape recomputed from its checkpoint, indexed at compile time
+    const int k_last = min(k_land, H - 1);
+    const int nsteps = H - k0;
+    const double wf = ac.arr ? p.w[2] : p.w[4];
+    const double denom = p.dt * (double)nsteps * ac.tmax * (ac.cf1 * (1.0 + p.vmax / ac.cf2));
+    const R kf = (R)((1.0 - p.w[7] - p.w[8]) * wf / denom);
+    const R kt = (R)(p.w[7] / (double)nsteps);
+    R ax = 0, ay = 0, az = 0, av = 0, achi = 0, aB = kf;
+    R gc[3] = {(R)0, (R)0, (R)0};
+    int s_grad = S - 1;
+    const int nblk = (H + GS_CK - 1) / GS_CK;
+    for (int j = nblk - 1; j >= 0; --j) {
+        const int kc = j * GS_CK;
+        const int kd = min(H, kc + GS_CK) - 1;
+        // the block's tape, indexed at compile time: (x, y) before each step
+        // and after the last, and the wind's spatial derivative (times dt)
+        // at each step, so the reverse sweep reads no field
+        R tx_[GS_CK + 1], ty_[GS_CK + 1], tw_[GS_CK][6];
+        {
+            R x1, y1;
+            ck2_get<R, NSEG>(ckx, cky, j, x1, y1);
+            tx_[0] = x1; ty_[0] = y1;
+            WindCell<R> wt;     // this pass's corner cache (not kept over the sweep below)
+            int gt = -1;
+#pragma unroll
+            for (int q = 0; q < GS_CK; ++q) {
+                const int k = kc + q;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) tw_[q][c] = (R)0;
+                tx_[q + 1] = x1; ty_[q + 1] = y1;
+                if (k > kd) continue;   // uniform
+                const R* r = rec + k * GS_REC;
+                const R rz = r[RS_Z], ra = r[RS_A], rb = r[RS_B];   // ahead of the lane test
+                if (active && k >= k0 && k <= k_last) {
+                    StepFwd<R> o;
+                    const int g = wind_locate<R, true>(p, x1, y1, rz, wt);
+                    if (g != gt) {
+                        wind_corners<R, true>(Wm, p, g, wt);
+                        gt = g;
+                    }
+                    wind_interp_grad<R>(wt, o);
+                    x1 = x1 + dt * (ra + o.wx);
+                    y1 = y1 + dt * (rb + o.wy);
+                    tx_[q + 1] = x1; ty_[q + 1] = y1;
+                    tw_[q][0] = dt * o.dwx[0]; tw_[q][1] = dt * o.dwx[1]; tw_[q][2] = dt * o.dwx[2];
+                    tw_[q][3] = dt * o.dwy[0]; tw_[q][4] = dt * o.dwy[1]; tw_[q][5] = dt * o.dwy[2];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = GS_CK - 1; q >= 0; --q) {
+            const int k = kc + q;
+            if (k > kd) continue;   // uniform
+            const int s = (k * S) / H;
+            if (s != s_grad) {      // uniform: the sweep leaves control segment s_grad
+                flush_segment<R>(gp, s_grad, gc, sp, lane, grp, (int64_t)p.P * N, l, i, out);
+                gc[0] = gc[1] = gc[2] = (R)0;
+                s_grad = s;
+            }
+            if (!(active && k >= k0 && k <= k_last)) continue;
+            const R* r = rec + k * GS_REC;
+            const R xn = tx_[q + 1], yn = ty_[q + 1];
+            if (k < k_land) {   // time element at the new state, unless this step lands
+                R dx, dy, dv;
+                time_elem<R>(p, ac, xn, yn, r[RS_VN], &dx, &dy, &dv);
+                ax += kt * dx; ay += kt * dy; av += kt * dv;
+            }
+            const R ir = r[RS_IR];
+            const R sx = r[RS_C1] * ax + r[RS_C2] * ay;   // dt (cos chi ax + sin chi ay) / cos gamma
+            const R nx_ = ax * ((R)1 + tw_[q][0]) + ay * tw_[q][3];
+            const R ny_ = ax * tw_[q][1] + ay * ((R)1 + tw_[q][4]);
+            const R nz_ = az + ax * tw_[q][2] + ay * tw_[q][5] + aB * r[RS_DFZ];
+            const R nchi = achi + dt * (ay * r[RS_A] - ax * r[RS_B]);
+            const R nv = av * ((R)1 - ir) + sx + aB * r[RS_DFV];
+            const R nB = aB - aB * r[RS_DFM];
+            gc[0] += achi * dt + aB * r[RS_DFCD];
+            gc[1] += av * ir + aB * r[RS_DFVC];
+            gc[2] += r[RS_C3] * sx + az * dt + aB * r[RS_DFZD];
+            ax = nx_; ay = ny_; az = nz_; achi = nchi; av = nv; aB = nB;
+        }
+    }
+    flush_segment<R>(gp, s_grad, gc, sp, lane, grp, (int64_t)p.P * N, l, i, out);
+}
+
 // W[m][g] -> Wt[m / B][g][m % B] (pairs of reals), one 32 x 32 tile per
 // workgroup through LDS so that both the reads and the writes are coalesced.
 template <typename R>
@@ -614,6 +962,20 @@ hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u,
     const int64_t lanes = (int64_t)rp.P * rp.N * gp.Mp;
     const unsigned blocks = (unsigned)((lanes + GR_BLOCK - 1) / GR_BLOCK);
     double* dst = gp.chunks > 1 ? partial : grad_out;
+    if (gp.Mp == 64 && rp.H <= GS_MAXH && rp.G < (1 << 24)) {
+        // one wave per (particle, aircraft): the sample-independent chain hoisted
+        const size_t lds = (size_t)(rp.H + 1) * GS_REC * (prec == 0 ? 8 : 4);
+        const unsigned groups = (unsigned)((int64_t)rp.P * rp.N);
+        if (prec == 0)
+            hipLaunchKernelGGL(k_rollout_grad_split<double>, dim3(groups), dim3(64), lds, st, gp,
+                               (const double*)u, (const double*)Wt, states, k_active, acpar,
+                               targets, kind, dst);
+        else
+            hipLaunchKernelGGL(k_rollout_grad_split<float>, dim3(groups), dim3(64), lds, st, gp,
+                               (const float*)u, (const float*)Wt, states, k_active, acpar,
+                               targets, kind, dst);
+        return hipGetLastError();
+    }
     const int nseg = (rp.H + GR_CK - 1) / GR_CK;
     if (prec == 0) {
         hipLaunchKernelGGL((k_rollout_grad<double, GR_MAXSEG, false>), dim3(blocks),
