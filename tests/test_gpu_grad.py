@@ -29,6 +29,59 @@ def _grad_case(lib, prec, M=3, P=7, H=40, S=4, seed=0):
     return host(g), ref * M
 
 
+def _grad_case_events(lib, prec, M, H, S=6, P=5):
+    """An arrival placed 14 km out on the runway axis, flying in at 120 m/s
+    and descending, lands after 12 ... 14 steps depending on the sample; one
+    aircraft joins at step 37, one never does, one joins 3 steps before the
+    end."""
+    import torch
+    s = synth.shrink(synth.c4(precision=prec), M=M, H=H, S=S, grid=(8, 8, 4), L=P)
+    s["states"] = s["states"].copy()
+    s["k_active"] = s["k_active"].copy()
+    assert s["kind"][0] == 0 and s["kind"][13] == 1
+    s["states"][0, :5] = [14000.0, 0.0, 700.0, 120.0, np.pi]
+    s["k_active"][1] = 37
+    s["k_active"][2] = -1
+    s["k_active"][13] = H - 3
+    ctx = lib.smc_mpc_init(s)
+    rng = np.random.default_rng(5)
+    u = rng.uniform(0.15, 0.85, (P, s["N"], s["S"], 3))
+    u[:, 0, :, :] = [0.5, 0.05, 0.4]     # no turn, 117 m/s commanded, -3 m/s climb
+    W = separable_field(s, 6)
+    if prec == "fp32":
+        u = u.astype(np.float32).astype(np.float64)
+        W = W.astype(np.float32).astype(np.float64)
+    g = empty((P, s["N"], s["S"], 3), torch.float64)
+    lib.smc_k_rollout_grad(ctx, dev(u, ctx.real_dtype), P, dev(W, ctx.real_dtype),
+                           dev(s["states"]), dev(s["k_active"]), s["H"], g)
+    _, ref = og.grad_fuel_time(s, u, W)
+    return host(g), ref * M
+
+
+# M = 40 and 64 with H <= 160: one wave per (particle, aircraft) (the last
+# 8-step block ragged at H = 157); H = 161: the per-lane form
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("M,H", [(40, 157), (64, 160), (40, 161)])
+def test_adjoint_landing_late_and_inactive_aircraft(lib, prec, M, H):
+    got, ref = _grad_case_events(lib, prec, M, H)
+    assert np.all(got[:, 2] == 0.0) and np.all(ref[:, 2] == 0.0)   # never active
+    # FP32: a sample that meets a discrete decision of the derivative (the
+    # grid clamp, the thrust floor, the time element's cap) on the other side
+    # than the FP64 oracle moves its group's sum by up to about 1/M of the
+    # group's scale (here 1.3 % for the late joiner at M = 64, the same with
+    # the per-lane form); the median error stays at rounding level
+    tol = 1e-9 if prec == "fp64" else 2e-2
+    for i in (0, 1, 13):   # the landing, late and last-moment aircraft, each on its own scale
+        sc = np.abs(ref[:, i]).max()
+        assert sc > 0.0
+        assert np.abs(got[:, i] - ref[:, i]).max() <= tol * sc, i
+    sc = np.abs(ref).max()
+    err = np.abs(got - ref)
+    assert err.max() <= (1e-9 if prec == "fp64" else 5e-3) * sc
+    if prec == "fp32":
+        assert np.median(err / np.maximum(np.abs(ref), 1e-3 * sc)) < 1e-4
+
+
 @pytest.mark.parametrize("M,H", [(3, 40), (16, 40), (80, 40), (64, 150)])
 def test_adjoint_fp64_matches_reference(lib, M, H):
     got, ref = _grad_case(lib, "fp64", M=M, P=5 if M == 80 else 7, H=H,
