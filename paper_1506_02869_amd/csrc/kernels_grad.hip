@@ -589,7 +589,8 @@ __global__ void __launch_bounds__(GR_BLOCK) __attribute__((amdgpu_waves_per_eu(2
 // each pass writes only its own steps' records.
 constexpr int GS_CK = 8;      // (x, y) checkpoint interval [steps]
 constexpr int GS_REC = 16;    // reals per step record
-constexpr int GS_MAXH = 160;  // horizons of the hoisted form (16 checkpoints)
+constexpr int GS_MAXH = 160;  // horizons of the hoisted form (20 checkpoints)
+constexpr int GS_MIN_M = 33;  // fewest samples for the hoisted form (idle lanes below)
 enum {
     RS_Z = 0, RS_A, RS_CHI, RS_VN, RS_IR, RS_C1, RS_C2, RS_C3,
     RS_DFZ, RS_DFV, RS_DFM, RS_DFCD, RS_DFVC, RS_DFZD, RS_B
@@ -962,18 +963,22 @@ hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u,
     const int64_t lanes = (int64_t)rp.P * rp.N * gp.Mp;
     const unsigned blocks = (unsigned)((lanes + GR_BLOCK - 1) / GR_BLOCK);
     double* dst = gp.chunks > 1 ? partial : grad_out;
-    if (gp.Mp == 64 && rp.H <= GS_MAXH && rp.G < (1 << 24)) {
-        // one wave per (particle, aircraft): the sample-independent chain hoisted
+    if (rp.M >= GS_MIN_M && rp.M <= 64 && rp.H <= GS_MAXH && rp.G < (1 << 24)) {
+        // one wave per (particle, aircraft): the sample-independent chain
+        // hoisted; lanes past M idle (a 64-lane sum, written by lane 0)
+        GradParams gs = gp;
+        gs.Mp = 64;
+        gs.chunks = 1;
         const size_t lds = (size_t)(rp.H + 1) * GS_REC * (prec == 0 ? 8 : 4);
         const unsigned groups = (unsigned)((int64_t)rp.P * rp.N);
         if (prec == 0)
-            hipLaunchKernelGGL(k_rollout_grad_split<double>, dim3(groups), dim3(64), lds, st, gp,
+            hipLaunchKernelGGL(k_rollout_grad_split<double>, dim3(groups), dim3(64), lds, st, gs,
                                (const double*)u, (const double*)Wt, states, k_active, acpar,
-                               targets, kind, dst);
+                               targets, kind, grad_out);
         else
-            hipLaunchKernelGGL(k_rollout_grad_split<float>, dim3(groups), dim3(64), lds, st, gp,
+            hipLaunchKernelGGL(k_rollout_grad_split<float>, dim3(groups), dim3(64), lds, st, gs,
                                (const float*)u, (const float*)Wt, states, k_active, acpar,
-                               targets, kind, dst);
+                               targets, kind, grad_out);
         return hipGetLastError();
     }
     const int nseg = (rp.H + GR_CK - 1) / GR_CK;
