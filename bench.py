@@ -34,6 +34,7 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
 
 # Algorithmic work of the rollout: elementary operations of the oracle's
 # per-step list (each transcendental, square root or division counted once)
@@ -570,8 +571,65 @@ def main():
         big = bench_single(args, "c5", 1, 0, None, False)
         out["large_form"] = {k: big[k] for k in ("value", "unit", "ms_per_step", "dtype",
                                                  "config", "roofline", "wind_gemm_roofline",
-                                                 "step_info", "status")}
+                                                 "step_info", "status", "smc_ops_roofline")}
     print(json.dumps(out), flush=True)
+
+
+def smc_ops_bandwidth(smc, torch, ctx, scen, reps=11):
+    """HBM rooflines of the SMC steps between rollouts (reduction and
+    log-weights, resampling, gather and move, final selection), each timed
+    alone at the workload's shape with device events on the stream it runs
+    on.  Algorithmic bytes per call:
+      k_reduce       M P N (8 + 1) read, P N (8 + 1 + 8) written
+      k_resample     P N 8 + 4 N read, 4 N P + 8 N written
+      k_gather_move  P D r + 4 N P read, P D r written (D = N S 3 reals of r bytes)
+      k_select       16 P N read, 8 written
+    (the median of `reps` calls, each between its own events)"""
+    import numpy as np
+    dev = torch.device("cuda")
+    P, N, M, S = scen["L"], scen["N"], scen["M"], scen["S"]
+    D = N * S * 3
+    rdt = torch.float64 if scen["precision"] == 0 else torch.float32
+    r = 8 if scen["precision"] == 0 else 4
+    g = torch.Generator(device="cpu").manual_seed(7)
+    cost = torch.rand((M, P, N), generator=g, dtype=torch.float64).to(dev)
+    feas = (torch.rand((M, P, N), generator=g) < 0.9).to(torch.uint8).to(dev)
+    chat = torch.empty((P, N), dtype=torch.float64, device=dev)
+    feas_pn = torch.empty((P, N), dtype=torch.uint8, device=dev)
+    logw = torch.empty((P, N), dtype=torch.float64, device=dev)
+    U = torch.empty(N, dtype=torch.int32, device=dev)
+    anc = torch.empty((N, P), dtype=torch.int32, device=dev)
+    u_in = torch.rand((P, N, S, 3), generator=g, dtype=torch.float64).to(rdt).to(dev)
+    u_out = torch.empty_like(u_in)
+    best = torch.empty(2, dtype=torch.int32, device=dev)
+    ops = {
+        "k_reduce": (lambda: smc.smc_k_reduce(ctx, P, cost, feas, 1.0, chat, feas_pn, logw),
+                     M * P * N * 9, P * N * 17),
+        "k_resample": (lambda: smc.smc_k_resample(ctx, P, logw, U, anc),
+                       P * N * 8 + 4 * N, 4 * N * P + 8 * N),
+        "k_gather_move": (lambda: smc.smc_k_gather_move(ctx, P, u_in, anc, u_out, 0, 1, 1),
+                          P * D * r + 4 * N * P, P * D * r),
+        "k_select": (lambda: smc.smc_k_select(ctx, P, logw, chat, 1.0, best), 16 * P * N, 8),
+    }
+    ops["k_reduce"][0]()
+    smc.smc_k_resample_offsets(ctx, 0, 1, U)
+    out = {}
+    for name, (fn, rd, wr) in ops.items():
+        fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record()
+            fn()
+            e1.record()
+        torch.cuda.synchronize()
+        ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+        gbs = (rd + wr) / (ms * 1e-3) / 1e9
+        out[name] = {"bound": "hbm", "ms_per_launch": round(ms, 4), "bytes": rd + wr,
+                     "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    return out
 
 
 def bench_single(args, workload, steps, warmup, cpu=None, check_cost=True):
@@ -750,6 +808,7 @@ def bench_single(args, workload, steps, warmup, cpu=None, check_cost=True):
             "seconds_per_update": 56.0, "hardware": "NVIDIA GeForce GTX 580, mostly FP64",
             "workload": "10 aircraft, H=6, dt=10 s, L=10240, 100 iterations of "
                         "SampleSchedule(J) passes, 8-point wind grid (Gatwick traffic)"}
+    out["smc_ops_roofline"] = smc_ops_bandwidth(smc, torch, ctx, scen)
     ctx.close()
     return out
 
