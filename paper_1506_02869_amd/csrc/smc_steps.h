@@ -73,7 +73,7 @@ __device__ __forceinline__ bool above_threshold(uint64_t C, uint64_t P, uint64_t
 
 // One workgroup of RS_THREADS threads resamples row i of logw[P][N]:
 // quantised weights floor(exp(lw - max) 2^(52 - ceil log2 P)), exact FP64
-// inclusive scan into C[P], ancestors A[P] by binary search against the
+// inclusive scan into C[P], ancestors A[P] by searching the scan against the
 // thresholds (k + U 2^-32) Q / P.  red, red2: RS_THREADS doubles of LDS.
 __device__ __forceinline__ void resample_row(int P, int N, int i, const double* __restrict__ logw,
                                              uint32_t Uw, double* __restrict__ C,
@@ -138,16 +138,28 @@ __device__ __forceinline__ void resample_row(int P, int N, int i, const double* 
     __threadfence_block();
     __syncthreads();
 
-    // 3) systematic ancestors by binary search on the exact scan
+    // 3) systematic ancestors on the exact scan: A[k] is the first index
+    // whose C is above threshold k (P - 1 if none).  The thresholds grow
+    // with k, so A is nondecreasing along the thread's run of k: each search
+    // starts at the previous ancestor (every index below it is below the
+    // new threshold too), walks up to 8 entries, then halves the rest.
     const uint64_t Q = (uint64_t)Qd;
     const uint64_t U = Uw;
     const uint64_t PP = (uint64_t)P;
+    int lo = 0;
     for (int k = l0; k < l1; ++k) {
-        int lo = 0, hi = P - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (above_threshold((uint64_t)C[mid], PP, (uint64_t)k, U, Q)) hi = mid;
-            else lo = mid + 1;
+        int w = 0;
+        while (lo < P - 1 && w < 8 && !above_threshold((uint64_t)C[lo], PP, (uint64_t)k, U, Q)) {
+            ++lo;
+            ++w;
+        }
+        if (w == 8 && lo < P - 1 && !above_threshold((uint64_t)C[lo], PP, (uint64_t)k, U, Q)) {
+            int hi = P - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (above_threshold((uint64_t)C[mid], PP, (uint64_t)k, U, Q)) hi = mid;
+                else lo = mid + 1;
+            }
         }
         A[k] = lo;
     }
