@@ -11,7 +11,7 @@ Paper passages followed:
     explicit Euler update of (x, y, z, v, chi, m) with the wind added to
     x and y;
   * the inverse relations of Sec. "Fuel Estimate 1" (eqs. for eta, gamma and
-    T) and "Fuel Estimate 2" (bank from heading change) map this build's
+    T) and "Fuel Estimate 2" (bank from heading change) map the library's
     per-segment kinematic controls (heading rate, airspeed, climb rate) onto
     the paper's thrust / climb angle / bank angle; the airspeed control is
     the speed reached at the end of its segment, approached linearly
