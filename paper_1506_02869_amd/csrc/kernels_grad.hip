@@ -562,7 +562,8 @@ __global__ void __launch_bounds__(GR_BLOCK) __attribute__((amdgpu_waves_per_eu(2
 // Of an aircraft's state only (x, y) depend on the wind sample: heading,
 // speed, altitude and burn follow from the controls alone (eq. hor), and a
 // sample's landing only ends that sample's steps.  So for 33 ... 64 samples
-// one wave takes one (particle, aircraft): it computes that chain and every
+// one wave takes one (particle, aircraft), for 17 ... 32 each half-wave
+// takes one: the group computes that chain and every
 // step's reverse coefficients once, into an LDS record per step, and each
 // lane then carries only its sample's (x, y) forward and the adjoint
 // backward.  The adjoint of (z, v, chi, burn) stays per lane (it depends on
@@ -590,7 +591,7 @@ __global__ void __launch_bounds__(GR_BLOCK) __attribute__((amdgpu_waves_per_eu(2
 constexpr int GS_CK = 8;      // (x, y) checkpoint interval [steps]
 constexpr int GS_REC = 16;    // reals per step record
 constexpr int GS_MAXH = 160;  // horizons of the hoisted form (20 checkpoints)
-constexpr int GS_MIN_M = 33;  // fewest samples for the hoisted form (idle lanes below)
+constexpr int GS_MIN_M = 17;  // fewest samples for the hoisted form (idle lanes below)
 enum {
     RS_Z = 0, RS_A, RS_CHI, RS_VN, RS_IR, RS_C1, RS_C2, RS_C3,
     RS_DFZ, RS_DFV, RS_DFM, RS_DFCD, RS_DFVC, RS_DFZD, RS_B
@@ -620,7 +621,9 @@ __device__ __forceinline__ void ck2_get(const R (&cx)[NSEG], const R (&cy)[NSEG]
 
 // (FP32: held to 168 registers, three waves per SIMD; one value spills,
 // outside the step loops)
-template <typename R>
+// MP lanes per (particle, aircraft): 64 (one per wave) or 32 (two per wave,
+// each half with its own records); gp.Mp == MP.
+template <typename R, int MP>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1)))
 k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __restrict__ W,
                      const double* __restrict__ states, const int32_t* __restrict__ k_active,
@@ -628,15 +631,20 @@ k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __re
                      const int8_t* __restrict__ kind, double* __restrict__ out) {
     typedef typename V2<R>::t R2;
     typedef Ops<R> O;
+    static_assert(MP == 64 || MP == 32, "one or two (particle, aircraft) per wave");
     constexpr int NSEG = (GS_MAXH + GS_CK - 1) / GS_CK;
+    constexpr int GPW = 64 / MP;
     extern __shared__ __align__(16) unsigned char gs_smem[];
-    R* rec = (R*)gs_smem;    // [H + 1][GS_REC]
     const RolloutParams& p = gp.rp;
     const int N = p.N, S = p.S, H = p.H, M = p.M;
     const int lane = threadIdx.x;
-    const int64_t grp = blockIdx.x;   // (l, i), one wave
-    const int l = (int)(grp / N), i = (int)(grp % N);
-    const bool valid = lane < M;
+    const int m = lane % MP;                 // wind sample
+    const int64_t ngrp = (int64_t)p.P * N;
+    const int64_t grp = (int64_t)blockIdx.x * GPW + lane / MP;   // (l, i)
+    const bool gin = grp < ngrp;
+    const int l = gin ? (int)(grp / N) : 0, i = gin ? (int)(grp % N) : 0;
+    const bool valid = gin && m < M;
+    R* rec = (R*)gs_smem + (lane / MP) * (H + 1) * GS_REC;   // [H + 1][GS_REC] per group
 
     AcConst ac;
     ac.Sw = acpar[i * 9 + 0]; ac.cd0 = acpar[i * 9 + 1]; ac.cd2 = acpar[i * 9 + 2];
@@ -644,16 +652,17 @@ k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __re
     ac.dtma = targets[i * 4 + 3]; ac.m0 = states[i * 6 + 5];
     ac.arr = kind[i] == 0;
     const int k0 = k_active[i];
-    const bool gact = k0 >= 0 && k0 < H;   // the same for the whole wave
+    const bool gact = gin && k0 >= 0 && k0 < H;   // the same for the whole group
     const bool active = valid && gact;
-    const R2* Wm = (const R2*)W + (valid ? lane : 0);   // sample-interleaved Wt[g][m]
+    const R2* Wm = (const R2*)W + (valid ? m : 0);   // sample-interleaved Wt[g][m]
     const R* ub = u + ((int64_t)l * N + i) * S * 3;
     const double lo[3] = {p.ctrl_lo[0], p.ctrl_lo[1], p.ctrl_lo[2]};
     const double sp[3] = {p.ctrl_span[0], p.ctrl_span[1], p.ctrl_span[2]};
     const R dt = (R)p.dt;
 
+    // (1) sequential: z, v, chi at every step from k0 (a group's first lane
+    // writes; the barriers sit outside the per-group branches)
     if (gact) {
-        // (1) sequential: z, v, chi at every step from k0
         {
             R z = (R)states[i * 6 + 2], v = (R)states[i * 6 + 3], chi = (R)states[i * 6 + 4];
             int s_cur = -1, k_end = 0;
@@ -665,7 +674,7 @@ k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __re
                     k_end = ((s + 1) * H + S - 1) / S;
                     seg_controls<R>(ub, s, lo, sp, cd, vc, zd);
                 }
-                if (lane == 0) {
+                if (m == 0) {
                     R* r = rec + k * GS_REC;
                     r[0] = z; r[1] = v; r[2] = chi;
                 }
@@ -674,14 +683,16 @@ k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __re
                 chi = chi + dt * cd;
                 v = v + (vc - v) * O::rcp((R)(k_end - k));
             }
-            if (lane == 0) {
+            if (m == 0) {
                 R* r = rec + H * GS_REC;
                 r[0] = z; r[1] = v; r[2] = chi;
             }
         }
-        __syncthreads();
-        // (2) step-parallel: the burn's inputs that do not depend on the mass
-        for (int k = k0 + lane; k < H; k += 64) {
+    }
+    __syncthreads();
+    // (2) step-parallel: the burn's inputs that do not depend on the mass
+    if (gact) {
+        for (int k = k0 + m; k < H; k += MP) {
             R* r = rec + k * GS_REC;
             const R z = r[0], v = r[1], chi = r[2];
             const int s = (k * S) / H;
@@ -693,8 +704,10 @@ k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __re
             r[3] = o.icphi; r[4] = o.qd * (R)ac.Sw; r[5] = o.vn - v; r[6] = o.sg;
             r[7] = (R)p.dt * o.eta;
         }
-        __syncthreads();
-        // (3) sequential: the burn, by step_core's expressions
+    }
+    __syncthreads();
+    // (3) sequential: the burn, by step_core's expressions
+    if (gact) {
         {
             const R g0 = (R)kG0, inv_dt = (R)(1.0 / p.dt);
             R B = 0;
@@ -706,13 +719,15 @@ k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __re
                 const R CL = O::div(mass * g0 * icphi, A0);
                 const R D = A0 * ((R)ac.cd0 + (R)ac.cd2 * CL * CL);
                 const R T = mass * dv * inv_dt + D + mass * g0 * sg;
-                if (lane == 0) { r[8] = B; r[9] = CL; r[10] = T; }
+                if (m == 0) { r[8] = B; r[9] = CL; r[10] = T; }
                 B = B + dteta * m_max(T, (R)0);
             }
         }
-        __syncthreads();
-        // (4) step-parallel: the record (reverse coefficients)
-        for (int k = k0 + lane; k < H; k += 64) {
+    }
+    __syncthreads();
+    // (4) step-parallel: the record (reverse coefficients)
+    if (gact) {
+        for (int k = k0 + m; k < H; k += MP) {
             R* r = rec + k * GS_REC;
             const R z = r[0], v = r[1], chi = r[2], B = r[8], CL = r[9], T = r[10];
             const int s = (k * S) / H;
@@ -757,8 +772,8 @@ k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __re
             r[RS_DFZ] = df_dz; r[RS_DFV] = df_dv; r[RS_DFM] = df_dm; r[RS_DFCD] = df_dcd;
             r[RS_DFVC] = df_dvc; r[RS_DFZD] = df_dzd; r[RS_B] = b;
         }
-        __syncthreads();
     }
+    __syncthreads();
 
     // forward over the sample's (x, y): checkpoints every GS_CK steps, landing step
     R ckx[NSEG], cky[NSEG];
@@ -855,7 +870,7 @@ k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __re
             if (k > kd) continue;   // uniform
             const int s = (k * S) / H;
             if (s != s_grad) {      // uniform: the sweep leaves control segment s_grad
-                flush_segment<R>(gp, s_grad, gc, sp, lane, grp, (int64_t)p.P * N, l, i, out);
+                flush_segment<R>(gp, s_grad, gc, sp, m, grp, ngrp, l, i, out);
                 gc[0] = gc[1] = gc[2] = (R)0;
                 s_grad = s;
             }
@@ -881,7 +896,7 @@ k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __re
             ax = nx_; ay = ny_; az = nz_; achi = nchi; av = nv; aB = nB;
         }
     }
-    flush_segment<R>(gp, s_grad, gc, sp, lane, grp, (int64_t)p.P * N, l, i, out);
+    flush_segment<R>(gp, s_grad, gc, sp, m, grp, ngrp, l, i, out);
 }
 
 // W[m][g] -> Wt[m / B][g][m % B] (pairs of reals), one 32 x 32 tile per
@@ -964,21 +979,26 @@ hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u,
     const unsigned blocks = (unsigned)((lanes + GR_BLOCK - 1) / GR_BLOCK);
     double* dst = gp.chunks > 1 ? partial : grad_out;
     if (rp.M >= GS_MIN_M && rp.M <= 64 && rp.H <= GS_MAXH && rp.G < (1 << 24)) {
-        // one wave per (particle, aircraft): the sample-independent chain
-        // hoisted; lanes past M idle (a 64-lane sum, written by lane 0)
+        // the sample-independent chain hoisted: one (particle, aircraft) per
+        // wave above 32 samples, two per wave (32 lanes each) from 17 to 32;
+        // lanes past M idle (a sum over the group's lanes, written by its
+        // first lane)
         GradParams gs = gp;
-        gs.Mp = 64;
+        gs.Mp = rp.M > 32 ? 64 : 32;
         gs.chunks = 1;
-        const size_t lds = (size_t)(rp.H + 1) * GS_REC * (prec == 0 ? 8 : 4);
-        const unsigned groups = (unsigned)((int64_t)rp.P * rp.N);
-        if (prec == 0)
-            hipLaunchKernelGGL(k_rollout_grad_split<double>, dim3(groups), dim3(64), lds, st, gs,
-                               (const double*)u, (const double*)Wt, states, k_active, acpar,
-                               targets, kind, grad_out);
-        else
-            hipLaunchKernelGGL(k_rollout_grad_split<float>, dim3(groups), dim3(64), lds, st, gs,
-                               (const float*)u, (const float*)Wt, states, k_active, acpar,
-                               targets, kind, grad_out);
+        const int gpw = 64 / gs.Mp;
+        const size_t lds = (size_t)gpw * (rp.H + 1) * GS_REC * (prec == 0 ? 8 : 4);
+        const int64_t groups = (int64_t)rp.P * rp.N;
+        const unsigned waves = (unsigned)((groups + gpw - 1) / gpw);
+        if (prec == 0) {
+            auto k = gs.Mp == 64 ? k_rollout_grad_split<double, 64> : k_rollout_grad_split<double, 32>;
+            hipLaunchKernelGGL(k, dim3(waves), dim3(64), lds, st, gs, (const double*)u,
+                               (const double*)Wt, states, k_active, acpar, targets, kind, grad_out);
+        } else {
+            auto k = gs.Mp == 64 ? k_rollout_grad_split<float, 64> : k_rollout_grad_split<float, 32>;
+            hipLaunchKernelGGL(k, dim3(waves), dim3(64), lds, st, gs, (const float*)u,
+                               (const float*)Wt, states, k_active, acpar, targets, kind, grad_out);
+        }
         return hipGetLastError();
     }
     const int nseg = (rp.H + GR_CK - 1) / GR_CK;
