@@ -563,10 +563,9 @@ __global__ void __launch_bounds__(GR_BLOCK) __attribute__((amdgpu_waves_per_eu(2
 // speed, altitude and burn follow from the controls alone (eq. hor), and a
 // sample's landing only ends that sample's steps.  So for 33 ... 64 samples
 // one wave takes one (particle, aircraft), for 17 ... 32 each half-wave
-// takes one: the group computes that chain and every
-// step's reverse coefficients once, into an LDS record per step, and each
-// lane then carries only its sample's (x, y) forward and the adjoint
-// backward.  The adjoint of (z, v, chi, burn) stays per lane (it depends on
+// takes one: the group computes that chain and every step's reverse
+// coefficients once, into an LDS record per step, and each lane then
+// carries only its sample's (x, y) forward and the adjoint backward.  The adjoint of (z, v, chi, burn) stays per lane (it depends on
 // the sample through the wind's altitude derivative and the landing step);
 // its update is linear with the record's coefficients.  The step arithmetic
 // is k_rollout_grad's (up to the order of some products).
