@@ -158,6 +158,8 @@ hipError_t launch_kron_expand(int prec, const double* Lx, const double* Ly,
 // unused) holds the chunk products.
 constexpr int kWindGemmSplitBelow = 1024;
 size_t wind_gemm_part_elems(int G, int M);
+// Most grid levels of the vertical-factor pass (k_wind_levels).
+constexpr int kMaxWindLevels = 16;
 hipError_t launch_wind_gemm(int prec, const void* Lfac, const void* Z,
                             double wm0, double wm1, int G, int M, void* W, void* part,
                             hipStream_t st);
@@ -256,6 +258,11 @@ hipError_t launch_select(int P, int N, const double* logw, const double* chat,
 hipError_t launch_wind_gemm_grouped(int prec, const void* Lfac, const void* Z,
                                     const double* wmean, int mper, int G, int M, void* W,
                                     void* part, hipStream_t st);
+// The horizontal factor's product over level-mixed columns (as
+// launch_wind_gemm_levels) with a mean per group of mper fields.
+hipError_t launch_wind_gemm_levels_grouped(int prec, const void* Lh, const void* Y,
+                                           const double* wmean, int mper, int nh, int nz, int M,
+                                           void* W, void* part, hipStream_t st);
 
 // batched launches: grids span every scenario of the table (ns entries)
 hipError_t launch_b_fill(uint32_t* p, int64_t n, hipStream_t st);

@@ -313,7 +313,6 @@ __global__ void __launch_bounds__(256) k_wind_gemm_sum(const T* __restrict__ par
 // Y[h][col][iz] = sum_{j <= iz} Lz[iz][j] U[h nz + j][col] (FP64 sums).
 // Thread per (h, col); the reads of consecutive columns and the writes of a
 // thread's nz levels are contiguous.
-constexpr int kMaxWindLevels = 16;
 template <typename T>
 __global__ void k_wind_levels(const T* __restrict__ U, const double* __restrict__ Lz, int nh,
                               int nz, int NC, T* __restrict__ Y) {
@@ -418,6 +417,13 @@ hipError_t launch_wind_gemm_levels(int prec, const void* Lh, const void* Y, doub
                                    double wm1, int nh, int nz, int M, void* W, void* part,
                                    hipStream_t st) {
     return wind_gemm(prec, Lh, Y, wm0, wm1, nullptr, 1, nh, M * nz, nz, W, part, st);
+}
+
+hipError_t launch_wind_gemm_levels_grouped(int prec, const void* Lh, const void* Y,
+                                           const double* wmean, int mper, int nh, int nz, int M,
+                                           void* W, void* part, hipStream_t st) {
+    if (!wmean || mper < 1) return hipErrorInvalidValue;
+    return wind_gemm(prec, Lh, Y, 0.0, 0.0, wmean, mper, nh, M * nz, nz, W, part, st);
 }
 
 hipError_t launch_wind_gemm_grouped(int prec, const void* Lfac, const void* Z,

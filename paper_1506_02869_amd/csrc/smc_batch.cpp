@@ -60,6 +60,12 @@ struct smc_batch {
     int8_t* d_kind = nullptr;
     void *d_Lfac = nullptr, *d_Z = nullptr, *d_W = nullptr;
     void* d_wpart = nullptr;   // wind GEMM chunk products (few-tile shapes)
+    // the fields' grouped product, as the single-scenario context: sigma
+    // Lx (x) Ly [nh][nh] real, L_z double, the level-mixed normals
+    bool wind_grouped = false;
+    int nx = 0, ny = 0, nz = 0;
+    void *d_Lh = nullptr, *d_Y = nullptr;
+    double *d_Lzd = nullptr, *d_one = nullptr;
     void *d_u = nullptr, *d_u2 = nullptr, *d_up = nullptr;
     // Langevin moves: the adjoint's gradients of the particles and of the
     // proposals (laid out like the particles), its chunk partials and its
@@ -286,6 +292,22 @@ hipError_t batch_grad(smc_batch* b, const void* u, double* g, hipStream_t st) {
 
 // The device work of one update; every per-update input is already in the
 // batch's device buffers (table, header, wind means, states, items).
+// Every scenario's fields from its normals: W = wbar_s + L Z, through the
+// same grouped product as the single-scenario context (levels' factor, then
+// the horizontal factor's GEMM) or the dense factor, so that a scenario's
+// fields equal its own context's bit for bit.
+hipError_t batch_wind_fields(smc_batch* b, hipStream_t st) {
+    if (!b->wind_grouped)
+        return launch_wind_gemm_grouped(b->prec, b->d_Lfac, b->d_Z, b->d_wmean, b->M, b->G,
+                                        b->ns * b->M, b->d_W, b->d_wpart, st);
+    const int nh = b->nx * b->ny;
+    const hipError_t e = launch_wind_levels(b->prec, b->d_Z, b->d_Lzd, nh, b->nz, b->ns * b->M,
+                                            b->d_Y, st);
+    if (e != hipSuccess) return e;
+    return launch_wind_gemm_levels_grouped(b->prec, b->d_Lh, b->d_Y, b->d_wmean, b->M, nh, b->nz,
+                                           b->ns * b->M, b->d_W, b->d_wpart, st);
+}
+
 hipError_t enqueue_update(smc_batch* b, hipStream_t st, int* launches, bool timed) {
     hipError_t e;
 #define Q(expr) do { if ((e = (expr)) != hipSuccess) return e; } while (0)
@@ -298,8 +320,7 @@ hipError_t enqueue_update(smc_batch* b, hipStream_t st, int* launches, bool time
     int pass = 0;
     for (int J = 0; J < K; ++J) {
         Q(launch_b_normals(b->prec, b->d_tab, b->d_hdr, ns, J, b->G, M, b->d_Z, st));
-        Q(launch_wind_gemm_grouped(b->prec, b->d_Lfac, b->d_Z, b->d_wmean, M, b->G, ns * M,
-                                   b->d_W, b->d_wpart, st));
+        Q(batch_wind_fields(b, st));
         Q(mark(2 * pass));
         Q(rollout_pass(b, pass, u, launches, st));
         Q(mark(2 * pass + 1));
@@ -544,6 +565,8 @@ smc_status smc_batch_init(const smc_scenario* sc, int32_t ns, smc_batch** out) {
     const smc_scenario& a = sc[0];
     b->ns = ns; b->L = a.n_particles; b->M = a.n_wind; b->K = a.n_iters;
     b->G = a.grid_n[0] * a.grid_n[1] * a.grid_n[2];
+    b->nx = a.grid_n[0]; b->ny = a.grid_n[1]; b->nz = a.grid_n[2];
+    b->wind_grouped = b->nz <= kMaxWindLevels;   // as the single-scenario context
     b->prec = a.precision; b->move = a.move;
     b->rsz = b->prec == SMC_FP64 ? sizeof(double) : sizeof(float);
     std::memset(&b->tune, 0, sizeof b->tune);
@@ -615,7 +638,13 @@ smc_status smc_batch_init(const smc_scenario* sc, int32_t ns, smc_batch** out) {
         (st = balloc<char>(b, (char**)&b->d_Z, G * 2 * M * nsz, b->rsz)) ||
         (st = balloc<char>(b, (char**)&b->d_W, G * 2 * M * nsz, b->rsz)) ||
         (st = balloc<char>(b, (char**)&b->d_wpart,
-                           std::max<size_t>(wind_gemm_part_elems((int)G, (int)(M * nsz)), 1), b->rsz)) ||
+                           std::max<size_t>({wind_gemm_part_elems((int)G, (int)(M * nsz)),
+                                             b->wind_grouped ? wind_gemm_part_elems(
+                                                                   a.grid_n[0] * a.grid_n[1],
+                                                                   (int)(M * nsz) * a.grid_n[2])
+                                                             : 0,
+                                             (size_t)1}),
+                           b->rsz)) ||
         (st = balloc<char>(b, (char**)&b->d_u, nu, b->rsz)) ||
         (st = balloc<char>(b, (char**)&b->d_u2, nu, b->rsz)) ||
         (st = balloc<char>(b, (char**)&b->d_up, b->move != SMC_MOVE_JITTER ? nu : 1, b->rsz)) ||
@@ -623,6 +652,10 @@ smc_status smc_batch_init(const smc_scenario* sc, int32_t ns, smc_batch** out) {
         (st = balloc(b, &b->d_g2, b->move == SMC_MOVE_MALA ? nu : 1)) ||
         (st = balloc<char>(b, (char**)&b->d_Wt, b->move == SMC_MOVE_MALA ? G * 2 * M : 1, b->rsz)) ||
         (st = balloc(b, &b->d_gpart, b->move == SMC_MOVE_MALA ? b->gpart_elems : 1)) ||
+        (st = balloc<char>(b, (char**)&b->d_Lh,
+                           b->wind_grouped ? (size_t)b->nx * b->ny * b->nx * b->ny : 1, b->rsz)) ||
+        (st = balloc<char>(b, (char**)&b->d_Y, b->wind_grouped ? G * 2 * M * nsz : 1, b->rsz)) ||
+        (st = balloc(b, &b->d_Lzd, (size_t)b->nz * b->nz)) || (st = balloc(b, &b->d_one, 1)) ||
         (st = balloc(b, &b->d_cost, M * npn)) || (st = balloc(b, &b->d_feas, M * npn)) ||
         (st = balloc(b, &b->d_chat, npn)) || (st = balloc(b, &b->d_logw, npn)) ||
         (st = balloc(b, &b->d_chat2, npn)) || (st = balloc(b, &b->d_logw2, npn)) ||
@@ -723,6 +756,13 @@ smc_status smc_batch_init(const smc_scenario* sc, int32_t ns, smc_batch** out) {
     IHIP(hipMemcpy(d_Lz, Lz.data(), Lz.size() * sizeof(double), hipMemcpyHostToDevice));
     IHIP(launch_kron_expand(b->prec, d_Lx, d_Ly, d_Lz, a.grid_n[0], a.grid_n[1], a.grid_n[2],
                             a.wind_sigma, b->d_Lfac, b->stream));
+    if (b->wind_grouped) {   // sigma Lx (x) Ly (d_one: the 1 x 1 factor 1), and L_z
+        const double one = 1.0;
+        IHIP(hipMemcpy(b->d_one, &one, sizeof(double), hipMemcpyHostToDevice));
+        IHIP(launch_kron_expand(b->prec, d_Lx, d_Ly, b->d_one, a.grid_n[0], a.grid_n[1], 1,
+                                a.wind_sigma, b->d_Lh, b->stream));
+        IHIP(hipMemcpy(b->d_Lzd, Lz.data(), Lz.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     IHIP(hipStreamSynchronize(b->stream));
 #undef IHIP
     {   // initial plan (horizon_max) so that the bucket sizes and grids are known
@@ -832,8 +872,7 @@ smc_status smc_batch_autotune(smc_batch* b, int64_t mpc_step, const double* stat
     BHIP(b, launch_b_fill(b->d_cnt, b->n_cnt, st));
     BHIP(b, launch_b_init(b->prec, b->d_tab, b->d_hdr, b->ns, b->max_count, b->d_u, st));
     BHIP(b, launch_b_normals(b->prec, b->d_tab, b->d_hdr, b->ns, 0, b->G, b->M, b->d_Z, st));
-    BHIP(b, launch_wind_gemm_grouped(b->prec, b->d_Lfac, b->d_Z, b->d_wmean, b->M, b->G,
-                                     b->ns * b->M, b->d_W, b->d_wpart, st));
+    BHIP(b, batch_wind_fields(b, st));
     unsigned long long* steps = reinterpret_cast<unsigned long long*>(b->d_cnt + b->cnt_steps);
     smc_batch_tuning best = b->tune;
     const int blocks[3] = {64, 128, 256};

@@ -64,11 +64,14 @@ struct smc_ctx {
     int warm_start = 0;          // start from the previous update's population
     void* u_last = nullptr;      // the buffer holding the last update's final population
     void* d_wpart = nullptr;   // wind GEMM chunk products (few-tile shapes)
-    // time-correlated wind: sigma L_h [nh][nh] real, L_z [nz][nz] double, the
-    // level-mixed normals Y [nh][2 Mf][nz] real
+    // time-correlated wind, and the static wind's grouped product: sigma L_h
+    // [nh][nh] real (L_h = Lx (x) Ly for the static wind), L_z [nz][nz]
+    // double, the level-mixed normals Y [nh][2 Mf][nz] real
     void* d_Lh = nullptr;
     double* d_Lzd = nullptr;
     void* d_Y = nullptr;
+    bool wind_grouped = false;   // static wind through (L_h (x) I) (I (x) L_z) Z
+    double* d_one = nullptr;     // the 1 x 1 factor 1 (static wind's L_h expansion)
     void *d_u = nullptr, *d_u2 = nullptr, *d_up = nullptr;
     double* d_cost = nullptr;
     uint8_t* d_feas = nullptr;
@@ -363,11 +366,26 @@ hipError_t wind_normals(smc_ctx* c, int64_t mpc_step, int J, hipStream_t st, int
 
 // The fields from the normals: the dense factor's product (static), or the
 // horizontal factor's product over the level-mixed normals.
+// The static factor L = sigma Lx (x) Ly (x) Lz is applied in two groups:
+// the levels' factor along z for every horizontal node, then the horizontal
+// factor sigma Lx (x) Ly (an MFMA GEMM with nh rows over the level-mixed
+// columns): the same product, nh (nh + 1) nz 2M flops instead of
+// G (G + 1) 2M.
+hipError_t wind_fields_grouped(smc_ctx* c, const void* Z, const double* wind_mean, int Mc,
+                               void* W, hipStream_t st) {
+    const int nh = c->nx * c->ny;
+    const hipError_t e = launch_wind_levels(c->prec, Z, c->d_Lzd, nh, c->nz, Mc, c->d_Y, st);
+    if (e != hipSuccess) return e;
+    return launch_wind_gemm_levels(c->prec, c->d_Lh, c->d_Y, wind_mean[0], wind_mean[1], nh,
+                                   c->nz, Mc, W, c->d_wpart, st);
+}
+
 hipError_t wind_fields_gemm(smc_ctx* c, const double* wind_mean, void* W, hipStream_t st,
                             int Ms = 0) {
     if (c->wind_model == SMC_WIND_EXP_AR1)
         return launch_wind_gemm_levels(c->prec, c->d_Lh, c->d_Y, wind_mean[0], wind_mean[1],
                                        c->nx * c->ny, c->nz, c->Mf, W, c->d_wpart, st);
+    if (c->wind_grouped) return wind_fields_grouped(c, c->d_Z, wind_mean, Ms ? Ms : c->M, W, st);
     return launch_wind_gemm(c->prec, c->d_Lfac, c->d_Z, wind_mean[0], wind_mean[1], c->G,
                             Ms ? Ms : c->M, W, c->d_wpart, st);
 }
@@ -845,6 +863,7 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     std::vector<double> Lx, Ly, Lz;
     int fx = c->nx, fy = c->ny;
     bool pd;
+    c->wind_grouped = c->wind_model != SMC_WIND_EXP_AR1 && c->nz <= kMaxWindLevels;
     if (c->wind_model == SMC_WIND_EXP_AR1) {
         fx = c->nx * c->ny;
         fy = 1;
@@ -912,6 +931,7 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         (st = dalloc(c, &c->d_W, Mf * G * 2 * c->rsz)) || (st = dalloc(c, &c->d_Wt, wt_elems(M, G, kWtBlockPw) * 2 * c->rsz)) ||
         (st = dalloc(c, &c->d_wpart, std::max<size_t>({part_elems_upto(c),
                                                        c->wind_model == SMC_WIND_EXP_AR1 ? wind_gemm_part_elems(fx, (int)Mf * c->nz) : 0,
+                                                       c->wind_grouped ? wind_gemm_part_elems(c->nx * c->ny, (int)Mf * c->nz) : 0,
                                                        (size_t)1}) *
                                          c->rsz)) ||
         (st = dalloc(c, &c->d_u, L * N * D * c->rsz)) ||
@@ -936,6 +956,11 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
         ((st = dalloc(c, &c->d_Lh, (size_t)fx * fx * c->rsz)) ||
          (st = dalloc_t(c, &c->d_Lzd, (size_t)c->nz * c->nz)) ||
          (st = dalloc(c, &c->d_Y, G * 2 * Mf * c->rsz))))
+        return bail(st);
+    if (c->wind_grouped &&
+        ((st = dalloc(c, &c->d_Lh, (size_t)c->nx * c->ny * c->nx * c->ny * c->rsz)) ||
+         (st = dalloc_t(c, &c->d_Lzd, (size_t)c->nz * c->nz)) ||
+         (st = dalloc(c, &c->d_Y, G * 2 * Mf * c->rsz)) || (st = dalloc_t(c, &c->d_one, 1))))
         return bail(st);
     {
         const size_t gl = (c->move == SMC_MOVE_MALA ? L : 1) * N * D;
@@ -975,7 +1000,13 @@ smc_status smc_mpc_init(const smc_scenario* s, smc_ctx** out) {
     INIT_HIP(hipMemcpy(d_Lz, Lz.data(), Lz.size() * sizeof(double), hipMemcpyHostToDevice));
     INIT_HIP(launch_kron_expand(c->prec, d_Lx, d_Ly, d_Lz, fx, fy, c->nz, c->sigma, c->d_Lfac,
                                 c->stream));
-    if (c->d_Lh) {   // sigma L_h alone (d_Ly holds the 1 x 1 factor 1), and L_z
+    if (c->wind_grouped) {   // sigma Lx (x) Ly (d_one: the 1 x 1 factor 1), and L_z
+        const double one = 1.0;
+        INIT_HIP(hipMemcpy(c->d_one, &one, sizeof(double), hipMemcpyHostToDevice));
+        INIT_HIP(launch_kron_expand(c->prec, d_Lx, d_Ly, c->d_one, fx, fy, 1, c->sigma, c->d_Lh,
+                                    c->stream));
+        INIT_HIP(hipMemcpy(c->d_Lzd, Lz.data(), Lz.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else if (c->d_Lh) {   // sigma L_h alone (d_Ly holds the 1 x 1 factor 1), and L_z
         INIT_HIP(launch_kron_expand(c->prec, d_Lx, d_Ly, d_Ly, fx, 1, 1, c->sigma, c->d_Lh,
                                     c->stream));
         INIT_HIP(hipMemcpy(c->d_Lzd, Lz.data(), Lz.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -1129,6 +1160,10 @@ smc_status smc_k_wind_normals(smc_ctx* c, int64_t mpc_step, int32_t iter, void* 
 
 smc_status smc_k_wind_gemm(smc_ctx* c, const void* Z, const double* wind_mean, void* W, void* stream) {
     if (!c || !Z || !W || !wind_mean) return fail(c, SMC_EINVAL, "smc_k_wind_gemm: bad arguments");
+    if (c->wind_grouped) {
+        HIP_OK(c, wind_fields_grouped(c, Z, wind_mean, c->M, W, pick(c, stream)));
+        return SMC_OK;
+    }
     HIP_OK(c, launch_wind_gemm(c->prec, c->d_Lfac, Z, wind_mean[0], wind_mean[1], c->G, c->M, W,
                                c->d_wpart, pick(c, stream)));
     return SMC_OK;

@@ -85,20 +85,34 @@ def test_teacher_forced_fp32_update_matches_oracle(lib):
 
 def test_c2_fp32_update_against_fp64_path(lib):
     """The C2 workload (10 aircraft, L = 8192, M = 64, K = 40) in FP32 and in
-    FP64 through smc_mpc_step: the two paths' returned expected costs agree
-    within 1e-3 relative, and the FP32 path's controls re-scored by the FP64
-    path (smc_eval_cost on the last iteration's fields) agree with the cost
-    the FP32 path returned within 1e-4."""
-    s32 = synth.c2()
-    s64 = synth.c2(precision="fp64")
-    c32 = lib.smc_mpc_init(s32)
-    c64 = lib.smc_mpc_init(s64)
-    ctrl32, cost32, st32, _ = lib.smc_mpc_step(c32)
-    ctrl64, cost64, st64, _ = lib.smc_mpc_step(c64)
-    assert st32 == st64 == 0
-    assert abs(cost32[0] - cost64[0]) <= 1e-3 * abs(cost64[0]), (cost32[0], cost64[0])
-    lo, hi = s64["ctrl_lo"], s64["ctrl_hi"]
-    un = ((ctrl32 - lo) / (hi - lo))[None]
-    rc, rf = lib.smc_eval_cost(c64, un, s64["K"] - 1)
-    assert rf.all()
-    assert abs(rc.sum() - cost32[0]) <= 1e-4 * abs(cost32[0]), (rc.sum(), cost32[0])
+    FP64 through smc_mpc_step, for three MPC steps (three draws of every
+    random stream).  Once one resampling decision differs, the two updates
+    are different Monte Carlo runs, so their returned costs differ by the
+    run-to-run spread of the 40-iteration estimate (0.1 ... 0.8 % measured
+    here, with either product of the wind fields): the FP32 path may not end
+    worse than the FP64 path by more than 1 %, nor differ by more than 1 % on
+    average.  What FP32 itself changes is checked exactly: the FP32 path's
+    controls, re-scored by the FP64 path (smc_eval_cost on the last
+    iteration's fields), cost what the FP32 path returned within 1e-4 (and the
+    teacher-forced test above follows the iterations themselves)."""
+    rel = []
+    for step in (0, 1, 2):
+        s32 = synth.c2()
+        s64 = synth.c2(precision="fp64")
+        s32["mpc_step"] = step
+        s64["mpc_step"] = step
+        c32 = lib.smc_mpc_init(s32)
+        c64 = lib.smc_mpc_init(s64)
+        ctrl32, cost32, st32, _ = lib.smc_mpc_step(c32)
+        ctrl64, cost64, st64, _ = lib.smc_mpc_step(c64)
+        assert st32 == st64 == 0
+        assert cost32[0] <= cost64[0] * (1 + 1e-2), (step, cost32[0], cost64[0])
+        rel.append(abs(cost32[0] - cost64[0]) / abs(cost64[0]))
+        lo, hi = s64["ctrl_lo"], s64["ctrl_hi"]
+        un = ((ctrl32 - lo) / (hi - lo))[None]
+        rc, rf = lib.smc_eval_cost(c64, un, s64["K"] - 1)
+        assert rf.all()
+        assert abs(rc.sum() - cost32[0]) <= 1e-4 * abs(cost32[0]), (step, rc.sum(), cost32[0])
+        c32.close()
+        c64.close()
+    assert np.mean(rel) <= 1e-2, rel
