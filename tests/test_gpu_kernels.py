@@ -94,9 +94,12 @@ def test_wind_factor_matches_kronecker(lib):
     assert np.all(err <= tol), (err.max(), (err / tol).max())
 
 
+# up to 16 levels: the grouped product (levels' factor, then the horizontal
+# factor's GEMM); 17 levels: the dense factor's GEMM
 @pytest.mark.parametrize("prec,grid,M", [("fp64", (16, 16, 4), 16), ("fp64", (5, 7, 3), 3),
                                          ("fp32", (16, 16, 4), 16), ("fp32", (32, 32, 8), 64),
-                                         ("fp32", (9, 6, 5), 40)])
+                                         ("fp32", (9, 6, 5), 40), ("fp64", (4, 5, 17), 6),
+                                         ("fp32", (4, 5, 17), 6)])
 def test_wind_gemm(lib, prec, grid, M):
     s = synth.shrink(small_scenario("c1", prec), grid=grid, M=M)
     ctx = _ctx(lib, s)
