@@ -58,7 +58,12 @@ smc_status smc_k_wind_normals(smc_ctx* ctx, int64_t mpc_step, int32_t iter,
 
 /* Wind fields W[m][g][c] = wind_mean[c] + sum_h Lchol[g][h] Z[h][2m+c]
  * (Sec. "Wind Model": Cholesky factor times Gaussian vector), with the
- * context's dense lower-triangular factor; MFMA GEMM. wind_mean: host [2]. */
+ * context's lower-triangular factor Lchol = sigma Lx (x) Ly (x) Lz.  Up to 16
+ * grid levels the product is grouped by that structure: each horizontal
+ * node's levels mixed by Lz, then sigma Lx (x) Ly applied by an MFMA GEMM
+ * (the same product up to rounding order); above 16 levels, the dense
+ * factor's MFMA GEMM.  Uses the context's scratch buffers: calls on one
+ * context are ordered by their stream.  wind_mean: host [2]. */
 smc_status smc_k_wind_gemm(smc_ctx* ctx, const void* Z, const double* wind_mean,
                            void* W, void* stream);
 
