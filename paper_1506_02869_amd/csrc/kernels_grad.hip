@@ -637,13 +637,16 @@ k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __re
     const RolloutParams& p = gp.rp;
     const int N = p.N, S = p.S, H = p.H, M = p.M;
     const int lane = threadIdx.x;
-    const int m = lane % MP;                 // wind sample
+    // one group per wave: the group and everything read from its index stay
+    // wave-uniform (scalar registers, scalar loads)
+    const int slot = MP == 64 ? 0 : lane / MP;    // the group's place in the wave
+    const int m = MP == 64 ? lane : lane % MP;    // wind sample
     const int64_t ngrp = (int64_t)p.P * N;
-    const int64_t grp = (int64_t)blockIdx.x * GPW + lane / MP;   // (l, i)
+    const int64_t grp = (int64_t)blockIdx.x * GPW + slot;   // (l, i)
     const bool gin = grp < ngrp;
     const int l = gin ? (int)(grp / N) : 0, i = gin ? (int)(grp % N) : 0;
     const bool valid = gin && m < M;
-    R* rec = (R*)gs_smem + (lane / MP) * (H + 1) * GS_REC;   // [H + 1][GS_REC] per group
+    R* rec = (R*)gs_smem + slot * (H + 1) * GS_REC;   // [H + 1][GS_REC] per group
 
     AcConst ac;
     ac.Sw = acpar[i * 9 + 0]; ac.cd0 = acpar[i * 9 + 1]; ac.cd2 = acpar[i * 9 + 2];
