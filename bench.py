@@ -767,8 +767,8 @@ def bench_single(args, workload, steps, warmup, cpu=None, check_cost=True):
         gflops = ls_launch * FLOPS_PER_ADJOINT_STEP
         gach = gflops / (ms_grad * 1e-3) / 1e12
         # the sample-independent chain hoisted per (particle, aircraft) for
-        # 17 ... 64 samples and horizons up to 160 steps
-        gk = ("k_rollout_grad_split" if 16 < scen["M"] <= 64 and scen["H"] <= 160
+        # 17 ... 128 samples and horizons up to 160 steps
+        gk = ("k_rollout_grad_split" if 16 < scen["M"] <= 128 and scen["H"] <= 160
               else "k_rollout_grad")
         grad_roof = {"kernel": gk, "bound": "alu", "achieved": round(gach, 3),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(gach / peak, 4),

@@ -561,11 +561,12 @@ __global__ void __launch_bounds__(GR_BLOCK) __attribute__((amdgpu_waves_per_eu(2
 //
 // Of an aircraft's state only (x, y) depend on the wind sample: heading,
 // speed, altitude and burn follow from the controls alone (eq. hor), and a
-// sample's landing only ends that sample's steps.  So for 33 ... 64 samples
-// one wave takes one (particle, aircraft), for 17 ... 32 each half-wave
-// takes one: the group computes that chain and every step's reverse
-// coefficients once, into an LDS record per step, and each lane then
-// carries only its sample's (x, y) forward and the adjoint backward.  The adjoint of (z, v, chi, burn) stays per lane (it depends on
+// sample's landing only ends that sample's steps.  So for 65 ... 128 samples
+// a workgroup of two waves takes one (particle, aircraft), for 33 ... 64 one
+// wave, for 17 ... 32 each half-wave: the group computes that chain and
+// every step's reverse coefficients once, into an LDS record per step, and
+// each lane then carries only its sample's (x, y) forward and the adjoint
+// backward.  The adjoint of (z, v, chi, burn) stays per lane (it depends on
 // the sample through the wind's altitude derivative and the landing step);
 // its update is linear with the record's coefficients.  The step arithmetic
 // is k_rollout_grad's (up to the order of some products).
@@ -620,27 +621,29 @@ __device__ __forceinline__ void ck2_get(const R (&cx)[NSEG], const R (&cy)[NSEG]
 
 // (FP32: held to 168 registers, three waves per SIMD; one value spills,
 // outside the step loops)
-// MP lanes per (particle, aircraft): 64 (one per wave) or 32 (two per wave,
-// each half with its own records); gp.Mp == MP.
+// MP lanes per (particle, aircraft): 128 (a workgroup of two waves, whose
+// 64-lane partial sums go to the chunk buffer), 64 (one per wave) or 32 (two
+// per wave, each half with its own records); gp.Mp == MP.
 template <typename R, int MP>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1)))
+__global__ void __launch_bounds__(MP > 64 ? MP : 64)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1)))
 k_rollout_grad_split(const GradParams gp, const R* __restrict__ u, const R* __restrict__ W,
                      const double* __restrict__ states, const int32_t* __restrict__ k_active,
                      const double* __restrict__ acpar, const double* __restrict__ targets,
                      const int8_t* __restrict__ kind, double* __restrict__ out) {
     typedef typename V2<R>::t R2;
     typedef Ops<R> O;
-    static_assert(MP == 64 || MP == 32, "one or two (particle, aircraft) per wave");
+    static_assert(MP == 128 || MP == 64 || MP == 32, "two waves, one or half a wave per group");
     constexpr int NSEG = (GS_MAXH + GS_CK - 1) / GS_CK;
-    constexpr int GPW = 64 / MP;
+    constexpr int GPW = MP >= 64 ? 1 : 64 / MP;   // groups per workgroup
     extern __shared__ __align__(16) unsigned char gs_smem[];
     const RolloutParams& p = gp.rp;
     const int N = p.N, S = p.S, H = p.H, M = p.M;
     const int lane = threadIdx.x;
     // one group per wave: the group and everything read from its index stay
     // wave-uniform (scalar registers, scalar loads)
-    const int slot = MP == 64 ? 0 : lane / MP;    // the group's place in the wave
-    const int m = MP == 64 ? lane : lane % MP;    // wind sample
+    const int slot = MP >= 64 ? 0 : lane / MP;    // the group's place in the wave
+    const int m = MP >= 64 ? lane : lane % MP;    // wind sample
     const int64_t ngrp = (int64_t)p.P * N;
     const int64_t grp = (int64_t)blockIdx.x * GPW + slot;   // (l, i)
     const bool gin = grp < ngrp;
@@ -980,27 +983,36 @@ hipError_t launch_rollout_grad(int prec, const RolloutParams& rp, const void* u,
     const int64_t lanes = (int64_t)rp.P * rp.N * gp.Mp;
     const unsigned blocks = (unsigned)((lanes + GR_BLOCK - 1) / GR_BLOCK);
     double* dst = gp.chunks > 1 ? partial : grad_out;
-    if (rp.M >= GS_MIN_M && rp.M <= 64 && rp.H <= GS_MAXH && rp.G < (1 << 24)) {
+    if (rp.M >= GS_MIN_M && rp.M <= 128 && rp.H <= GS_MAXH && rp.G < (1 << 24)) {
         // the sample-independent chain hoisted: one (particle, aircraft) per
-        // wave above 32 samples, two per wave (32 lanes each) from 17 to 32;
-        // lanes past M idle (a sum over the group's lanes, written by its
-        // first lane)
+        // two-wave workgroup from 65 to 128 samples, per wave from 33 to 64,
+        // two per wave (32 lanes each) from 17 to 32; lanes past M idle (a
+        // sum over each 64 lanes of the group, written by its first lane)
         GradParams gs = gp;
-        gs.Mp = rp.M > 32 ? 64 : 32;
-        gs.chunks = 1;
-        const int gpw = 64 / gs.Mp;
+        gs.Mp = rp.M > 64 ? 128 : rp.M > 32 ? 64 : 32;
+        gs.chunks = gs.Mp > 64 ? gs.Mp / 64 : 1;
+        const int gpw = gs.Mp >= 64 ? 1 : 64 / gs.Mp;
+        const int block = gs.Mp > 64 ? gs.Mp : 64;
         const size_t lds = (size_t)gpw * (rp.H + 1) * GS_REC * (prec == 0 ? 8 : 4);
         const int64_t groups = (int64_t)rp.P * rp.N;
-        const unsigned waves = (unsigned)((groups + gpw - 1) / gpw);
+        const unsigned blocks = (unsigned)((groups + gpw - 1) / gpw);
+        double* gdst = gs.chunks > 1 ? partial : grad_out;
         if (prec == 0) {
-            auto k = gs.Mp == 64 ? k_rollout_grad_split<double, 64> : k_rollout_grad_split<double, 32>;
-            hipLaunchKernelGGL(k, dim3(waves), dim3(64), lds, st, gs, (const double*)u,
-                               (const double*)Wt, states, k_active, acpar, targets, kind, grad_out);
+            auto k = gs.Mp == 128 ? k_rollout_grad_split<double, 128>
+                     : gs.Mp == 64 ? k_rollout_grad_split<double, 64> : k_rollout_grad_split<double, 32>;
+            hipLaunchKernelGGL(k, dim3(blocks), dim3(block), lds, st, gs, (const double*)u,
+                               (const double*)Wt, states, k_active, acpar, targets, kind, gdst);
         } else {
-            auto k = gs.Mp == 64 ? k_rollout_grad_split<float, 64> : k_rollout_grad_split<float, 32>;
-            hipLaunchKernelGGL(k, dim3(waves), dim3(64), lds, st, gs, (const float*)u,
-                               (const float*)Wt, states, k_active, acpar, targets, kind, grad_out);
+            auto k = gs.Mp == 128 ? k_rollout_grad_split<float, 128>
+                     : gs.Mp == 64 ? k_rollout_grad_split<float, 64> : k_rollout_grad_split<float, 32>;
+            hipLaunchKernelGGL(k, dim3(blocks), dim3(block), lds, st, gs, (const float*)u,
+                               (const float*)Wt, states, k_active, acpar, targets, kind, gdst);
         }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || gs.chunks == 1) return e;
+        const int64_t n = (int64_t)rp.P * rp.N * rp.S * 3;
+        hipLaunchKernelGGL(k_grad_chunks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+                           gs.chunks, partial, grad_out);
         return hipGetLastError();
     }
     const int nseg = (rp.H + GR_CK - 1) / GR_CK;

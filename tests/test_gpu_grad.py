@@ -60,10 +60,10 @@ def _grad_case_events(lib, prec, M, H, S=6, P=5):
 
 
 # M = 40 and 64 with H <= 160: one wave per (particle, aircraft) (the last
-# 8-step block ragged at H = 157); M = 24: two per wave; H = 161: the
-# per-lane form
+# 8-step block ragged at H = 157); M = 24: two per wave; M = 80: a two-wave
+# workgroup per (particle, aircraft); H = 161: the per-lane form
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("M,H", [(40, 157), (64, 160), (24, 157), (40, 161)])
+@pytest.mark.parametrize("M,H", [(40, 157), (64, 160), (24, 157), (80, 157), (40, 161)])
 def test_adjoint_landing_late_and_inactive_aircraft(lib, prec, M, H):
     got, ref = _grad_case_events(lib, prec, M, H)
     assert np.all(got[:, 2] == 0.0) and np.all(ref[:, 2] == 0.0)   # never active
@@ -110,7 +110,7 @@ def test_adjoint_fp64_matches_reference(lib, M, H):
 
 # (M, H, S): segment checkpoints in registers up to 6 segments (H <= 150),
 # in scratch memory beyond; one wave per (particle, aircraft) at M = 64
-@pytest.mark.parametrize("M,H,S", [(8, 40, 4), (64, 150, 6), (5, 180, 6)])
+@pytest.mark.parametrize("M,H,S", [(8, 40, 4), (64, 150, 6), (5, 180, 6), (100, 150, 6)])
 def test_adjoint_fp32_matches_reference(lib, M, H, S):
     got, ref = _grad_case(lib, "fp32", M=M, H=H, S=S)
     scale = np.abs(ref).max()
